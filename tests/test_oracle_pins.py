@@ -1,0 +1,310 @@
+"""Pins of the FP64 reference against facts fixed by the paper and by mathematics.
+
+None of these compares the reference with itself: every expected value comes from a
+closed form, an independent quadrature, an algebraic identity or a property of the
+sampling construction.  Each test names what a plausible mistake would break.
+"""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial.legendre import leggauss
+from scipy import integrate
+from scipy.special import j1
+
+from paper_2408_06765_amd import workloads as W
+
+C_W, RHO_W = W.WATER
+A = W.PISTON_RADIUS
+
+
+def gl_panels(lo, hi, n_panels, order=16):
+    """Composite Gauss-Legendre nodes and weights on [lo, hi]."""
+    x, w = leggauss(order)
+    e = np.linspace(lo, hi, n_panels + 1)
+    mid, half = (e[:-1] + e[1:]) / 2, (e[1:] - e[:-1]) / 2
+    return (mid[:, None] + half[:, None] * x[None, :]).ravel(), (half[:, None] * w[None, :]).ravel()
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+# ----------------------------------------------------------------------------- eq. 3
+def test_piston_axis_closed_form_exact_quadrature(orc):
+    """eq. (3) on the axis of a baffled piston (Sec. 2.1, piston of Seki et al.):
+    p(z) = rho c v0 [e^{ikz} - e^{ik sqrt(z^2 + a^2)}].  A radial Gauss rule is exact
+    to rounding for the axisymmetric integrand, so this pins the -1/2pi prefactor, the
+    e^{ikr}/r kernel, the exp(-i omega t) sign and p = i omega rho phi together."""
+    f = 1.0e6
+    k = 2 * math.pi * f / C_W
+    r, wr = gl_panels(0.0, A, 32, 64)
+    w = 2 * math.pi * r * wr  # axisymmetric: the angle integral is 2 pi r
+    z = np.linspace(1e-3, 0.1, 64)
+    phi = orc.propagate(orc.MONOPOLE, (r, 0 * r, 0 * r), w, 1.0, (0 * z, 0 * z, z), C_W, f)
+    p = orc.to_pressure(phi, RHO_W, f)
+    pex = RHO_W * C_W * (np.exp(1j * k * z) - np.exp(1j * k * np.sqrt(z * z + A * A)))
+    assert rel(p, pex) < 1e-11
+
+
+def test_piston_axis_closed_form_qmc(orc):
+    """The 1 MHz, 4096-sample piston workload against the same closed form: the QMC
+    estimator (eq. 16) with area weights pi a^2 / N reaches the QMC error level."""
+    cfg = W.PistonAxis()
+    k = 2 * math.pi * cfg.freq / C_W
+    x, y, z, w = orc.sample_disc(cfg.seed, cfg.n_src, cfg.radius)
+    tx, ty, tz = cfg.targets()
+    phi = orc.propagate(orc.MONOPOLE, (x, y, z), w, 1.0, (tx, ty, tz), C_W, cfg.freq)
+    p = orc.to_pressure(phi, RHO_W, cfg.freq)
+    pex = RHO_W * C_W * (np.exp(1j * k * tz) - np.exp(1j * k * np.sqrt(tz * tz + A * A)))
+    assert rel(p, pex) < 5e-4
+
+
+def test_far_field_directivity(orc):
+    """Far field of eq. (3): phi -> -v0 a^2 (e^{ikR}/R) J1(ka sin t)/(ka sin t).  Pins the
+    angular dependence (geometry of r) and the prefactor away from the axis."""
+    f = 1.0e6
+    k = 2 * math.pi * f / C_W
+    rg, wg = gl_panels(0.0, A, 3, 16)
+    nt = 128
+    th = 2 * math.pi * np.arange(nt) / nt
+    R_, T_ = np.meshgrid(rg, th, indexing="ij")
+    w = (wg[:, None] * R_ * (2 * math.pi / nt)).ravel()
+    X, Y = (R_ * np.cos(T_)).ravel(), (R_ * np.sin(T_)).ravel()
+    Rff = 100.0
+    ang = np.radians([0.0, 2.0, 5.0, 10.0, 20.0, 40.0])
+    P = (Rff * np.sin(ang), 0 * ang, Rff * np.cos(ang))
+    phi = orc.propagate(orc.MONOPOLE, (X, Y, 0 * X), w, 1.0, P, C_W, f)
+    s = np.maximum(np.sin(ang), 1e-300)
+    D = np.where(np.sin(ang) > 0, j1(k * A * s) / (k * A * s), 0.5)
+    ff = -A * A * np.exp(1j * k * Rff) / Rff * D
+    assert np.max(np.abs(phi - ff)) / np.abs(ff[0]) < 1e-3
+
+
+def test_qmc_matches_adaptive_quadrature_and_converges(orc):
+    """Brute-force adaptive quadrature (scipy dblquad) of eq. (3) at off-axis points: the
+    QMC estimate approaches it faster than Monte Carlo (fitted log-log slope <= -0.8)."""
+    f = 1.0e6
+    k = 2 * math.pi * f / C_W
+    pts = [(0.004, 0.001, 0.02), (0.002, 0.0, 0.05), (-0.003, 0.002, 0.01)]
+
+    def exact(px, py, pz):
+        def g(r, t, part):
+            dx, dy = px - r * math.cos(t), py - r * math.sin(t)
+            R = math.sqrt(dx * dx + dy * dy + pz * pz)
+            v = np.exp(1j * k * R) / R * r
+            return v.real if part == 0 else v.imag
+        re = integrate.dblquad(lambda r, t: g(r, t, 0), 0, 2 * math.pi, 0, A, epsabs=1e-14, epsrel=1e-12)[0]
+        im = integrate.dblquad(lambda r, t: g(r, t, 1), 0, 2 * math.pi, 0, A, epsabs=1e-14, epsrel=1e-12)[0]
+        return -(re + 1j * im) / (2 * math.pi)
+
+    ex = np.array([exact(*p) for p in pts])
+    P = tuple(np.array(pts).T)
+    Ns = [2 ** m for m in range(8, 17, 2)]
+    errs = []
+    for n in Ns:
+        x, y, z, w = orc.sample_disc(3, n, A)
+        errs.append(rel(orc.propagate(orc.MONOPOLE, (x, y, z), w, 1.0, P, C_W, f), ex))
+    slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
+    assert errs[-1] < 1e-4
+    assert slope <= -0.8
+
+
+# ----------------------------------------------------------------------------- eqs. 2, 7
+@pytest.mark.parametrize("z", [0.005, 0.01, 0.03, 0.06])
+def test_dipole_point_source_identity(orc, z):
+    """First Rayleigh-Sommerfeld solution (eqs. 2, 7): a point source S behind the plane
+    z = 0 gives phi = e^{ik|Q-S|}/|Q-S| on it, and the dipole sum must continue that
+    field exactly: phi(P) = e^{ik|P-S|}/|P-S|.  Windowed radial Gauss rule on the axis.
+    Pins the overall sign, cos(theta), the (ik - 1/r) factor and 1/2pi."""
+    f = 1.0e6
+    k = 2 * math.pi * f / C_W
+    d, rmax = 0.02, 0.6
+    r, wr = gl_panels(0.0, rmax, 4000, 16)
+    win = np.where(r < rmax / 2, 1.0, np.cos(0.5 * math.pi * (r - rmax / 2) / (rmax / 2)) ** 2)
+    w = 2 * math.pi * r * wr * win
+    R1 = np.sqrt(r * r + d * d)
+    s = np.exp(1j * k * R1) / R1
+    zt = np.array([z])
+    phi = orc.propagate(orc.DIPOLE, (r, 0 * r, 0 * r), w, s, (0 * zt, 0 * zt, zt), C_W, f,
+                        normal=(0.0, 0.0, 1.0))
+    ex = np.exp(1j * k * (z + d)) / (z + d)
+    assert abs(phi[0] / ex - 1) < 1e-7
+
+
+def test_dipole_gives_normal_velocity_power(orc):
+    """Energy flux: with strength v0 the dipole kernel is d/dz of the monopole field, so
+    0.5 Re sum p v_z* dA over a plane equals the baffled-piston radiated power
+    0.5 rho c v0^2 pi a^2 [1 - J1(2ka)/(ka)] (plane truncation ~1e-2)."""
+    f = 1.0e6
+    k = 2 * math.pi * f / C_W
+    x, y, z, w = orc.sample_disc(0, 4096, A)
+    g = np.linspace(-0.03, 0.03, 161)
+    dA = (g[1] - g[0]) ** 2
+    X, Y = np.meshgrid(g, g)
+    X, Y = X.ravel(), Y.ravel()
+    Z = np.full_like(X, 0.005)
+    phi = orc.propagate(orc.MONOPOLE, (x, y, z), w, 1.0, (X, Y, Z), C_W, f)
+    vz = orc.propagate(orc.DIPOLE, (x, y, z), w, 1.0, (X, Y, Z), C_W, f, normal=(0, 0, 1))
+    p = orc.to_pressure(phi, RHO_W, f)
+    power = 0.5 * np.real(np.sum(p * np.conj(vz))) * dA
+    exact = 0.5 * RHO_W * C_W * math.pi * A * A * (1 - j1(2 * k * A) / (k * A))
+    assert abs(power / exact - 1) < 1e-2
+
+
+def test_reciprocity_and_dipole_antisymmetry(orc):
+    """The monopole kernel is symmetric in its end points: u^T G(A->B) v = v^T G(B->A) u.
+    With one normal, cos(theta) flips sign when source and target swap, so the dipole
+    kernel is antisymmetric.  Exact to rounding."""
+    f = 2.0e6
+    A_pts = W.random_cloud(1, 300, (0, 0, 0.0), (0.01, 0.01, 0.002))
+    B_pts = W.random_cloud(2, 200, (0.002, 0, 0.03), (0.01, 0.01, 0.002))
+    u = W.random_complex(3, 200)
+    v = W.random_complex(4, 300)
+    one_a, one_b = np.ones(300), np.ones(200)
+    for kind, sign in ((orc.MONOPOLE, 1.0), (orc.DIPOLE, -1.0)):
+        ab = orc.propagate(kind, A_pts, one_a, v, B_pts, C_W, f, normal=(0, 0, 1))
+        ba = orc.propagate(kind, B_pts, one_b, u, A_pts, C_W, f, normal=(0, 0, 1))
+        lhs, rhs = np.sum(u * ab), sign * np.sum(v * ba)
+        assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), 1e-300)
+
+
+def test_singular_pair_excluded(orc):
+    """A target on a source point: that pair contributes nothing (r < 1e-12 m)."""
+    src = (np.array([0.0, 0.001]), np.array([0.0, 0.0]), np.array([0.0, 0.0]))
+    phi = orc.propagate(orc.MONOPOLE, src, np.array([1.0, 1.0]), np.array([1.0, 0.0]),
+                        (np.array([0.0]), np.array([0.0]), np.array([0.0])), C_W, 1e6)
+    assert phi[0] == 0.0
+
+
+# ----------------------------------------------------------------------------- chain
+def test_transparent_interface_reproduces_direct_field(orc):
+    """Matched media with T = 1 (the display mode of Sec. 3.1): the chain transducer ->
+    plane -> P must equal the direct field transducer -> P up to QMC and truncation error.
+    Pins the hand-over between eq. (3) and eq. (7) and the strength s = T phi."""
+    f = 1.0e6
+    xd = orc.sample_disc(0, 4096, A)
+    q = orc.sample_square(1, 1 << 16, 0.0, 0.0, 0.03, 0.03)
+    zt = np.linspace(0.035, 0.08, 16)
+    xt = np.linspace(-0.003, 0.003, 16)
+    tgt = (xt, 0 * xt, zt)
+    for tmode in (orc.T_UNITY, orc.T_LOCAL):
+        ch = orc.chain(xd, 1.0, (0, 0, 0), (0, 0, 1), [q], [0.03], [C_W, C_W], [RHO_W, RHO_W], tgt,
+                       [f], tmode)[0]
+        direct = orc.propagate(orc.MONOPOLE, xd[:3], xd[3], 1.0, tgt, C_W, f)
+        assert rel(ch, direct) < 1e-2
+
+
+# ----------------------------------------------------------------------------- eqs. 8, 11, 15
+IMPEDANCE_CASES = [(1480.0, 1000.0, 5900.0, 7800.0), (5900.0, 7800.0, 2700.0, 2700.0),
+                   (1480.0, 1000.0, 6409.0, 2700.0)]
+
+
+@pytest.mark.parametrize("c1,r1,c2,r2", IMPEDANCE_CASES)
+def test_transmission_reflection_algebra(orc, c1, r1, c2, r2):
+    """eq. (11) equals (rho1/rho2)(1 + R12) of eqs. (7)-(8); normal incidence gives
+    (Z2 - Z1)/(Z2 + Z1); energy 1 - |R|^2 = (Z1 cos a2 / (Z2 cos a1)) |1 + R|^2 below the
+    critical angle; |R| = 1 beyond it (eq. 15 gives sin a2 > 1)."""
+    Z1, Z2 = r1 * c1, r2 * c2
+    R0 = orc.reflection_coefficient(0.0, c1, r1, c2, r2)
+    assert abs(R0 - (Z2 - Z1) / (Z2 + Z1)) < 1e-15
+    crit = c1 / c2 if c2 > c1 else 2.0
+    for s in np.linspace(0.0, 0.999, 37):
+        T = orc.transmission_coefficient(s, c1, r1, c2, r2)
+        R = orc.reflection_coefficient(s, c1, r1, c2, r2)
+        assert abs(T - (r1 / r2) * (1 + R)) < 1e-13 * max(1.0, abs(T))
+        s2 = s * c2 / c1
+        if s2 < 1.0:
+            ca1, ca2 = math.sqrt(1 - s * s), math.sqrt(1 - s2 * s2)
+            if ca1 > 1e-6:
+                assert abs((1 - abs(R) ** 2) - Z1 * ca2 / (Z2 * ca1) * abs(1 + R) ** 2) < 1e-12
+        elif s < 1.0:
+            assert abs(abs(R) - 1.0) < 1e-13
+            assert s > crit - 1e-15
+
+
+def test_ray_slowness_round_trip(orc):
+    """Conserved slowness of eqs. (14)-(15): a ray built forward with a chosen C through
+    three layers (angles from Snell's law, offsets h tan t) is recovered from its offset."""
+    h = [0.05, 0.002, 0.002]
+    c = [1480.0, 5900.0, 2700.0]
+    for C in np.linspace(0.0, 0.99 / 5900.0, 9):
+        rho_h = sum(hl * math.tan(math.asin(C * cl)) for hl, cl in zip(h, c))
+        assert abs(orc.ray_slowness(rho_h, h, c) - C) <= 1e-12 * (1.0 / 5900.0)
+    # one layer: the straight line
+    for rho_h in (0.0, 0.003, 0.02, 0.2):
+        assert abs(orc.ray_slowness(rho_h, [0.05], [1480.0]) * 1480.0 -
+                   rho_h / math.hypot(rho_h, 0.05)) < 1e-14
+
+
+def test_transmission_modes(orc):
+    """Per-point T for the three readings: unity; global (one tilt, Snell-chained); local
+    (straight line from the face centre for the first interface)."""
+    zif = [0.05, 0.052]
+    c = [1480.0, 5900.0, 2700.0]
+    rho = [1000.0, 7800.0, 2700.0]
+    qx = np.array([0.0, 0.005, 0.01, 0.02])
+    qy = np.array([0.0, 0.0, 0.003, -0.004])
+    tu = orc.transmission(orc.T_UNITY, 1, zif, c, rho, (0, 0, 0), (0, 0, 1), qx, qy)
+    assert np.all(tu == 1.0)
+    tilt = math.radians(10.0)
+    tg = orc.transmission(orc.T_GLOBAL, 2, zif, c, rho, (0, 0, 0), (math.sin(tilt), 0, math.cos(tilt)), qx, qy)
+    s_in = math.sin(tilt) / 1480.0 * 5900.0
+    assert np.allclose(tg, orc.transmission_coefficient(s_in, 5900.0, 7800.0, 2700.0, 2700.0), rtol=0, atol=1e-15)
+    tl = orc.transmission(orc.T_LOCAL, 1, zif, c, rho, (0, 0, 0), (0, 0, 1), qx, qy)
+    for j in range(4):
+        s = math.hypot(qx[j], qy[j]) / math.sqrt(qx[j] ** 2 + qy[j] ** 2 + 0.05 ** 2)
+        assert abs(tl[j] - orc.transmission_coefficient(s, 1480.0, 1000.0, 5900.0, 7800.0)) < 1e-13
+
+
+def test_pressure_conversion(orc):
+    phi = np.array([1.0 + 2.0j, -0.5j])
+    p = orc.to_pressure(phi, 1000.0, 2.0e6)
+    assert np.allclose(p, 1j * 2 * math.pi * 2.0e6 * 1000.0 * phi, rtol=1e-15)
+
+
+# ----------------------------------------------------------------------------- eqs. 16-18
+def test_sobol_net_property(orc):
+    """The first 2^m scrambled points form a (0, m, 2)-net: every elementary box of area
+    2^-m (all 2^k x 2^(m-k) splits) holds exactly one point.  Any wrong direction number
+    or a scramble that is not a nested uniform permutation breaks this."""
+    for seed in (0, 1, 12345):
+        for m in (4, 8, 12):
+            u = orc.sobol2d(seed, 1 << m).astype(np.uint64)
+            for kx in range(m + 1):
+                ky = m - kx
+                cell = (u[:, 0] >> np.uint64(32 - kx)) * np.uint64(1 << ky) + (u[:, 1] >> np.uint64(32 - ky)) \
+                    if kx > 0 and ky > 0 else (u[:, 0] >> np.uint64(32 - kx) if kx > 0 else u[:, 1] >> np.uint64(32 - ky))
+                counts = np.bincount(cell.astype(np.int64), minlength=1 << m)
+                assert np.all(counts == 1), (seed, m, kx)
+
+
+def test_sobol_seeds_differ_and_first_range(orc):
+    a = orc.sobol2d(0, 64)
+    b = orc.sobol2d(1, 64)
+    assert not np.array_equal(a, b)
+    # a later range equals the tail of a longer draw (counter-based)
+    full = orc.sobol2d(7, 100)
+    assert np.array_equal(orc.sobol2d(7, 40, first=60), full[60:])
+
+
+def test_disc_and_square_maps(orc):
+    """eq. (18): area-uniform disc, E[r^2] = a^2/2, all points inside, weights pi a^2/N,
+    tilted points lie in the plane normal to the axis.  eq. (17): square of half-width h."""
+    n = 1 << 14
+    tilt = math.radians(10.0)
+    centre = (0.001, -0.002, 0.003)
+    x, y, z, w = orc.sample_disc(0, n, A, centre, tilt)
+    axis = np.array([math.sin(tilt), 0.0, math.cos(tilt)])
+    d = np.stack([x - centre[0], y - centre[1], z - centre[2]], 1)
+    assert np.max(np.abs(d @ axis)) < 1e-17
+    r2 = np.sum(d * d, 1)
+    assert np.max(r2) <= A * A * (1 + 1e-12)
+    assert abs(np.mean(r2) / (A * A / 2) - 1) < 1e-3
+    assert np.allclose(w, math.pi * A * A / n, rtol=1e-15)
+    xs, ys, zs, ws = orc.sample_square(1, n, 0.00882, 0.0, 0.05, 0.03)
+    assert xs.min() >= 0.00882 - 0.03 and xs.max() < 0.00882 + 0.03
+    assert ys.min() >= -0.03 and ys.max() < 0.03
+    assert np.all(zs == 0.05)
+    assert abs(np.mean(xs) - 0.00882) < 1e-5
+    assert np.allclose(ws, 0.06 ** 2 / n, rtol=1e-15)

@@ -1,0 +1,241 @@
+/*
+ * rsi.h -- C ABI of librsi: the Rayleigh-Sommerfeld integral (RSI) quasi-Monte-Carlo
+ * beam model on MI355X (gfx950).
+ *
+ * Paper: "Efficient numerical frameworks for modelling ultrasonic beams propagating
+ * across interfaces" (Lello de Almeida, Png, Lan).  The library evaluates the QMC
+ * estimator (eq. 16) of the piston integral (eq. 3) and of the interface integral
+ * (eq. 7) at arbitrary field points, and chains them transducer -> interface 1 ->
+ * ... -> field (Sec. 2.1; Sec. 2.2 for the interface count as the bottleneck).
+ *
+ * Conventions shared by every entry point
+ *  - SI units; time dependence exp(-i omega t); the returned field is the velocity
+ *    potential phi (v = grad phi); rsi_to_pressure gives p = i omega rho phi.
+ *  - Complex numbers are interleaved (re, im) pairs of the stated precision.
+ *  - Every array argument is a DEVICE pointer owned by the caller, unless the
+ *    comment says "host".  Point sets are structure-of-arrays FP64.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null stream)
+ *    and returns after enqueueing.  Calls on distinct streams may run concurrently.
+ *    One-shot calls take their temporary workspace from the stream-ordered
+ *    allocator (hipMallocAsync/hipFreeAsync) on `stream`; plans own theirs.
+ *  - Errors are reported as rsi_status; no C++ exception crosses the ABI.  An
+ *    argument error is detected before anything is enqueued.  n = 0 is valid and
+ *    enqueues nothing (a zero-length output has nothing to write).
+ *  - Precision: RSI_FP64 computes every operation in FP64 and excludes pairs closer
+ *    than 1e-12 m, exactly as the FP64 reference does.  RSI_FP32 keeps FP64 for the
+ *    per-target reference distance and the reduction of the phase k r to
+ *    revolutions, and runs the per-pair arithmetic and the accumulation in FP32; it
+ *    clamps r^2 from below instead of excluding close pairs, so it assumes no field
+ *    point lies closer to a source than about 1e-6 of the source-set extent (the
+ *    kernel is singular on the radiating surface, Sec. 3.2).
+ */
+#ifndef RSI_H
+#define RSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSI_OK = 0,
+    RSI_ERR_NULL = 1,        /* a required pointer is NULL                          */
+    RSI_ERR_ARG = 2,         /* a scalar argument is out of range (freq <= 0, ...)  */
+    RSI_ERR_SIZE = 3,        /* a count is negative or exceeds a documented limit   */
+    RSI_ERR_DEVICE = 4,      /* a HIP runtime call failed (message via last_error) */
+    RSI_ERR_WORKSPACE = 5,   /* workspace allocation failed                         */
+    RSI_ERR_NONFINITE = 6,   /* reserved: non-finite input detected                 */
+    RSI_ERR_UNSUPPORTED = 7  /* the combination of options is not implemented       */
+} rsi_status;
+
+typedef enum { RSI_MONOPOLE = 0, RSI_DIPOLE = 1 } rsi_kernel;
+typedef enum { RSI_FP32 = 0, RSI_FP64 = 1 } rsi_precision;
+typedef enum { RSI_T_GLOBAL = 0, RSI_T_LOCAL = 1, RSI_T_UNITY = 2 } rsi_tmode;
+
+typedef struct { double c, rho; } rsi_medium;            /* m/s, kg/m^3             */
+
+typedef struct {                                          /* device SoA, FP64, metres */
+    const double *x, *y, *z;
+    int64_t n;
+} rsi_points;
+
+typedef struct {                                          /* the radiating piston     */
+    rsi_points pts;          /* face samples (eq. 18)                                */
+    const double *w;         /* device quadrature weights (area / N, eq. 16)         */
+    double v0;               /* normal velocity amplitude (eq. 3)                    */
+    double centre[3];        /* face centre, for the incidence angles of RSI_T_*    */
+    double axis[3];          /* unit beam axis (RSI_T_GLOBAL uses its inclination)  */
+} rsi_transducer;
+
+typedef struct {                                          /* one planar interface     */
+    rsi_points pts;          /* samples on the plane z = `z` (eq. 17)                */
+    const double *w;         /* device quadrature weights                            */
+    double z;                /* plane depth; normal +z; planes strictly increasing   */
+} rsi_interface;
+
+/* One independent pair sum for rsi_propagate_batched / rsi_plan_create_batched. */
+typedef struct {
+    rsi_points src;          /* sources                                               */
+    const double *w;         /* weights                                               */
+    const double *vel;       /* complex FP64 strength per source, or NULL: all = v0   */
+    double v0;               /* used when vel == NULL                                 */
+    double normal[3];        /* dipole normal (ignored for RSI_MONOPOLE)              */
+    rsi_points tgt;          /* field points                                          */
+    rsi_medium medium;
+    double freq;             /* Hz                                                    */
+    rsi_kernel kind;
+    void *out;               /* complex [tgt.n], FP32 or FP64 per the call's precision */
+} rsi_instance;
+
+typedef struct rsi_plan rsi_plan;                         /* opaque                   */
+
+/* Human-readable status name; never NULL. */
+const char *rsi_status_string(rsi_status s);
+
+/* Text of the last HIP error seen by this thread (empty if none); never NULL. */
+const char *rsi_last_error(void);
+
+/* ABI version: (major << 16) | minor. */
+int rsi_version(void);
+
+/* ------------------------------------------------------------------------------
+ * a1. Sampling (Sec. 2.3, eqs. 16-18).
+ * ------------------------------------------------------------------------------ */
+
+/* Scrambled two-dimensional Sobol points `first .. first+n-1` as uint32 pairs,
+ * out[2i+d] = coordinate d.  Coordinate 0: van der Corput direction numbers;
+ * coordinate 1: primitive polynomial x+1.  Each coordinate is Owen-scrambled by the
+ * hash-based Laine-Karras permutation of Burley (JCGT 2020) with a per-coordinate
+ * seed fmix32(seed + 0x9e3779b9 * (d + 1)) (MurmurHash3 finaliser).  The first 2^m
+ * points of any seed form a (0, m, 2)-net.  Replaces the Halton sequence of Sec. 2.3.
+ * out: device uint32[2n].  RSI_ERR_SIZE if first < 0, n < 0 or first + n > 2^32. */
+rsi_status rsi_sobol2d(uint32_t seed, int64_t first, int64_t n, uint32_t *out, void *stream);
+
+/* Piston face samples, eq. (18): radius a sqrt(u0), angle 2 pi u1 on the disc, the
+ * disc tilted by `tilt` radians about +y (axis becomes (sin tilt, 0, cos tilt)) and
+ * translated to centre (host double[3]).  w = pi a^2 / n.  Outputs: device
+ * double[n] each.  RSI_ERR_ARG if radius <= 0. */
+rsi_status rsi_sample_disc(uint32_t seed, int64_t n, double radius, const double *centre,
+                           double tilt, double *x, double *y, double *z, double *w,
+                           void *stream);
+
+/* Interface patch samples, eq. (17): x = cx + h (2 u0 - 1), y = cy + h (2 u1 - 1),
+ * z = z0, w = (2h)^2 / n.  RSI_ERR_ARG if half_width <= 0. */
+rsi_status rsi_sample_square(uint32_t seed, int64_t n, double cx, double cy, double z0,
+                             double half_width, double *x, double *y, double *z, double *w,
+                             void *stream);
+
+/* ------------------------------------------------------------------------------
+ * a2. Interface transmission (eqs. 7, 8, 11, 15).
+ * ------------------------------------------------------------------------------ */
+
+/* Velocity-potential transmission coefficient at each sample of interface m
+ * (1-based) of the stack `zif` (host double[m], planes z = zif[l], normal +z) with
+ * media (host rsi_medium[m+1], medium 0 holds the transducer):
+ *     T = 2 rho1 c2 cos a1 / (rho2 c2 cos a1 + rho1 c1 cos a2)        (eq. 11)
+ *       = (rho1/rho2)(1 + R12)                                        (eqs. 7-8)
+ * with sin a2 = (c2/c1) sin a1 (eq. 15) and cos a2 = +i sqrt(sin^2 a2 - 1) past the
+ * critical angle.  The incidence angle a1 is, per tmode:
+ *   RSI_T_GLOBAL: the inclination of `axis` (host double[3]) from +z, Snell-chained
+ *                 through the layers above (one value per interface);
+ *   RSI_T_LOCAL:  the angle of the refracted ray from `xc` (host double[3]) to the
+ *                 sample, whose conserved slowness C solves
+ *                 sum_l h_l C c_l / sqrt(1 - C^2 c_l^2) = horizontal distance
+ *                 (eqs. 14-15; a straight line for m = 1);
+ *   RSI_T_UNITY:  T = 1 (the impedance-matched display mode of Sec. 3.1).
+ * qx, qy: device double[n] sample coordinates; out: device complex FP64 [n]. */
+rsi_status rsi_transmission(rsi_tmode tmode, int m, const double *zif,
+                            const rsi_medium *media, const double *xc, const double *axis,
+                            int64_t n, const double *qx, const double *qy, double *out,
+                            void *stream);
+
+/* ------------------------------------------------------------------------------
+ * a3/a4. The pair sum (eqs. 3, 7; estimator eq. 16).
+ * ------------------------------------------------------------------------------ */
+
+/* phi(P_i) = -(1/2 pi) sum_j w_j s_j K(P_i, Q_j) for every target P_i, with
+ *   RSI_MONOPOLE: K = e^{ikr}/r                                   (eq. 3, s = v0)
+ *   RSI_DIPOLE:   K = cos(theta) (ik - 1/r) e^{ikr}/r,  cos(theta) = n.(P-Q)/r
+ *                 (the first Rayleigh-Sommerfeld solution, eqs. 2 and 7, with the
+ *                 overall sign that reproduces a field continued through a
+ *                 transparent plane)
+ * k = 2 pi freq / medium.c.  src_vel: device complex FP64 [src->n] (s_j, e.g.
+ * T_j phi_in(Q_j)); normal: host double[3], required for RSI_DIPOLE (need not be
+ * unit: it is normalised), ignored otherwise.  out: device complex [tgt->n] of the
+ * call's precision (FP32: float pairs, FP64: double pairs), overwritten.
+ * RSI_ERR_ARG if freq <= 0 or medium.c <= 0. */
+rsi_status rsi_propagate(const rsi_points *src, const double *src_w, const double *src_vel,
+                         const double *normal, const rsi_points *tgt, rsi_medium medium,
+                         double freq, rsi_kernel kind, rsi_precision prec, void *out,
+                         void *stream);
+
+/* ------------------------------------------------------------------------------
+ * a5. The chain (Sec. 2.1 repeated per interface, Sec. 3.4-3.5).
+ * ------------------------------------------------------------------------------ */
+
+/* For every frequency f of `freqs` (host double[n_freq]):
+ *   phi_0 = monopole sum from the transducer (strength v0) onto interface 1;
+ *   for m = 1..n_if: s_j = T_m(Q_j) phi_{m-1}(Q_j) (rsi_transmission with `tmode`),
+ *     phi_m = dipole sum (normal +z, medium m) onto interface m+1, or onto `tgt`
+ *     after the last interface.
+ * n_if = 0 radiates the transducer straight onto tgt.  media: host rsi_medium
+ * [n_if+1]; ifaces: host array of n_if descriptors with strictly increasing z.
+ * out: device complex [n_freq][tgt->n] of the call's precision (FP32 chains keep
+ * their interface fields in FP32).  With RSI_FP32 and n_freq > 1 on a uniform
+ * frequency grid, each stage runs as one multi-frequency launch that evaluates the
+ * pair geometry once and advances e^{ikr} across the frequencies by complex
+ * rotation. */
+rsi_status rsi_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
+                     const rsi_medium *media, const rsi_points *tgt, const double *freqs,
+                     int n_freq, rsi_tmode tmode, rsi_precision prec, void *out,
+                     void *stream);
+
+/* ------------------------------------------------------------------------------
+ * a7. Batching: persistent launches, plans and graph replay.
+ * ------------------------------------------------------------------------------ */
+
+/* Evaluate n_inst independent pair sums (host rsi_instance[n_inst]) in ONE
+ * persistent launch: the work is cut into (instance, target tile, source chunk)
+ * items sorted by cost, pulled from a device work counter, and reduced per target in
+ * a fixed order (bitwise repeatable).  Tile shapes come from the autotune cache when
+ * it holds an entry for this workload, otherwise from built-in defaults. */
+rsi_status rsi_propagate_batched(const rsi_instance *inst, int n_inst, rsi_precision prec,
+                                 void *stream);
+
+/* Plans: the whole chain (or batched launch) with its workspace allocated once and
+ * its kernels captured into a hipGraph; rsi_plan_execute replays the graph on
+ * `stream`.  The plan binds the device pointers given at creation (inputs and
+ * output) -- their contents may change between executions, their addresses may not.
+ * A plan may be executed on one stream at a time. */
+rsi_status rsi_plan_create_chain(rsi_plan **plan, const rsi_transducer *xd,
+                                 const rsi_interface *ifaces, int n_if,
+                                 const rsi_medium *media, const rsi_points *tgt,
+                                 const double *freqs, int n_freq, rsi_tmode tmode,
+                                 rsi_precision prec, void *out);
+rsi_status rsi_plan_create_batched(rsi_plan **plan, const rsi_instance *inst, int n_inst,
+                                   rsi_precision prec);
+rsi_status rsi_plan_execute(rsi_plan *plan, void *stream);
+rsi_status rsi_plan_destroy(rsi_plan *plan);
+
+/* Time the candidate tile shapes (targets per lane, split-K chunk) of the batched
+ * launch for this instance list on the current device and store the fastest in the
+ * autotune cache (file named by RSI_AUTOTUNE_CACHE, else ~/.cache/rsi_autotune.txt).
+ * Synchronises the device; overwrites every inst[i].out.  A missing or corrupt cache
+ * file is treated as empty. */
+rsi_status rsi_autotune_batched(const rsi_instance *inst, int n_inst, rsi_precision prec);
+
+/* ------------------------------------------------------------------------------
+ * a8. Output.
+ * ------------------------------------------------------------------------------ */
+
+/* p = i omega rho phi with omega = 2 pi freq; phi and p: device complex [n] of the
+ * given precision (may alias). */
+rsi_status rsi_to_pressure(int64_t n, const void *phi, rsi_precision prec, double rho,
+                           double freq, void *p, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSI_H */

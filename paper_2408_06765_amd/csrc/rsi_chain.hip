@@ -1,0 +1,317 @@
+// rsi_chain.hip -- interface transmission (eqs. 7, 8, 11, 14, 15), the chained model
+// transducer -> interface 1 -> ... -> field (Sec. 2.1 applied once per interface), and
+// the pressure conversion.
+#include <cmath>
+
+#include "rsi_internal.h"
+
+namespace rsi {
+
+constexpr int kMaxInterfaces = 32;
+
+struct Layers {
+    int m;                         // interface index (1-based) the coefficients are for
+    double h[kMaxInterfaces];      // vertical thickness of each layer above interface m
+    double c[kMaxInterfaces + 1];  // speeds of media 0..m
+    double rho[kMaxInterfaces + 1];
+    double c_max;                  // fastest of media 0..m-1
+    double C_global;               // slowness of the beam axis (RSI_T_GLOBAL)
+    double xc, yc;                 // transducer face centre (horizontal)
+};
+
+// Slowness C of the refracted ray reaching horizontal distance `rho_h` through the
+// layers (eqs. 14-15): sum_l h_l C c_l / sqrt(1 - C^2 c_l^2) = rho_h.  Newton steps
+// on a shrinking bracket [lo, hi] of 0 <= C < 1/c_max; bisection whenever a step
+// leaves the bracket.
+__device__ double ray_slowness_dev(const Layers &L, double rho_h) {
+    if (rho_h <= 0.0) return 0.0;
+    double lo = 0.0, hi = 1.0 / L.c_max;
+    // start from the straight line through the whole stack, scaled into the bracket
+    double H = 0.0;
+    for (int l = 0; l < L.m; ++l) H += L.h[l];
+    double C = (rho_h / sqrt(rho_h * rho_h + H * H)) / L.c_max;
+    for (int it = 0; it < 200; ++it) {
+        double f = -rho_h, df = 0.0;
+        for (int l = 0; l < L.m; ++l) {
+            const double sc = C * L.c[l];
+            const double q = 1.0 - sc * sc;
+            const double sq = sqrt(q);
+            f += L.h[l] * sc / sq;
+            df += L.h[l] * L.c[l] / (q * sq);
+        }
+        if (f < 0.0) lo = C; else hi = C;
+        double Cn = C - f / df;
+        if (!(Cn > lo && Cn < hi)) Cn = 0.5 * (lo + hi);
+        if (fabs(Cn - C) <= 1e-17 * fabs(C) || Cn == lo || Cn == hi) {
+            C = Cn;
+            break;
+        }
+        C = Cn;
+    }
+    return C;
+}
+
+__device__ inline void cos_of_sine(double s, double &re, double &im) {
+    if (s <= 1.0) {
+        re = sqrt(1.0 - s * s);
+        im = 0.0;
+    } else {  // past the critical angle: the branch decaying away from the plane
+        re = 0.0;
+        im = sqrt(s * s - 1.0);
+    }
+}
+
+__global__ void __launch_bounds__(256) transmission_kernel(int tmode, Layers L, int64_t n,
+                                                           const double *__restrict__ qx,
+                                                           const double *__restrict__ qy,
+                                                           double2 *__restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    if (tmode == RSI_T_UNITY) {
+        out[j] = make_double2(1.0, 0.0);
+        return;
+    }
+    double C = L.C_global;
+    if (tmode == RSI_T_LOCAL) {
+        const double ex = qx[j] - L.xc, ey = qy[j] - L.yc;
+        C = ray_slowness_dev(L, sqrt(ex * ex + ey * ey));
+    }
+    const int m = L.m;
+    const double c1 = L.c[m - 1], c2 = L.c[m], r1 = L.rho[m - 1], r2 = L.rho[m];
+    double a_re, a_im, b_re, b_im;
+    cos_of_sine(C * c1, a_re, a_im);  // incidence
+    cos_of_sine(C * c2, b_re, b_im);  // refraction (eq. 15)
+    // eq. (11): T = 2 rho1 c2 cos a1 / (rho2 c2 cos a1 + rho1 c1 cos a2)
+    const double nre = 2.0 * r1 * c2 * a_re, nim = 2.0 * r1 * c2 * a_im;
+    const double dre = r2 * c2 * a_re + r1 * c1 * b_re, dim = r2 * c2 * a_im + r1 * c1 * b_im;
+    const double d2 = dre * dre + dim * dim;
+    out[j] = make_double2((nre * dre + nim * dim) / d2, (nim * dre - nre * dim) / d2);
+}
+
+static rsi_status make_layers(rsi_tmode tmode, int m, const double *zif, const rsi_medium *media,
+                              const double *xc, const double *axis, Layers &L) {
+    if (m < 1 || m > kMaxInterfaces) return RSI_ERR_SIZE;
+    if (!zif || !media) return RSI_ERR_NULL;
+    for (int l = 0; l <= m; ++l)
+        if (!(media[l].c > 0.0) || !(media[l].rho > 0.0)) return RSI_ERR_ARG;
+    L = Layers{};
+    L.m = m;
+    if (tmode == RSI_T_LOCAL) {
+        if (!xc) return RSI_ERR_NULL;
+        L.h[0] = zif[0] - xc[2];
+        if (!(L.h[0] > 0.0)) return RSI_ERR_ARG;  // the source must lie above interface 1
+        L.xc = xc[0];
+        L.yc = xc[1];
+    }
+    for (int l = 1; l < m; ++l) {
+        L.h[l] = zif[l] - zif[l - 1];
+        if (!(L.h[l] > 0.0)) return RSI_ERR_ARG;
+    }
+    L.c_max = 0.0;
+    for (int l = 0; l <= m; ++l) {
+        L.c[l] = media[l].c;
+        L.rho[l] = media[l].rho;
+        if (l < m && L.c[l] > L.c_max) L.c_max = L.c[l];
+    }
+    if (tmode == RSI_T_GLOBAL) {
+        if (!axis) return RSI_ERR_NULL;
+        const double an = sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+        if (!(an > 0.0)) return RSI_ERR_ARG;
+        L.C_global = sqrt(axis[0] * axis[0] + axis[1] * axis[1]) / an / media[0].c;
+    }
+    return RSI_OK;
+}
+
+rsi_status transmission_device(rsi_tmode tmode, int m, const double *zif,
+                               const rsi_medium *media, const double *xc, const double *axis,
+                               int64_t n, const double *qx, const double *qy, double *out,
+                               hipStream_t s) {
+    if (tmode != RSI_T_GLOBAL && tmode != RSI_T_LOCAL && tmode != RSI_T_UNITY) return RSI_ERR_ARG;
+    if (n < 0) return RSI_ERR_SIZE;
+    Layers L;
+    RSI_TRY(make_layers(tmode, m, zif, media, xc, axis, L));
+    if (n == 0) return RSI_OK;
+    if (!out || (tmode == RSI_T_LOCAL && (!qx || !qy))) return RSI_ERR_NULL;
+    hipLaunchKernelGGL(transmission_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (int)tmode, L, n, qx, qy, reinterpret_cast<double2 *>(out));
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+template <typename T2>
+__global__ void __launch_bounds__(256) pressure_kernel(int64_t n, const T2 *__restrict__ phi,
+                                                       double scale, T2 *__restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const T2 v = phi[i];
+    T2 r;
+    r.x = -scale * (double)v.y;  // i omega rho phi
+    r.y = scale * (double)v.x;
+    p[i] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Chain orchestration.
+// ---------------------------------------------------------------------------
+rsi_status validate_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
+                                 const rsi_medium *media, const rsi_points *tgt,
+                                 const double *freqs, int n_freq, rsi_tmode tmode,
+                                 rsi_precision prec, void *out) {
+    if (!xd || !media || !tgt || (n_if > 0 && !ifaces) || (n_freq > 0 && !freqs))
+        return RSI_ERR_NULL;
+    if (n_if < 0 || n_if > kMaxInterfaces || n_freq < 0) return RSI_ERR_SIZE;
+    if (prec != RSI_FP32 && prec != RSI_FP64) return RSI_ERR_ARG;
+    if (tmode != RSI_T_GLOBAL && tmode != RSI_T_LOCAL && tmode != RSI_T_UNITY) return RSI_ERR_ARG;
+    for (int l = 0; l <= n_if; ++l)
+        if (!(media[l].c > 0.0) || !(media[l].rho > 0.0)) return RSI_ERR_ARG;
+    for (int f = 0; f < n_freq; ++f)
+        if (!(freqs[f] > 0.0) || !std::isfinite(freqs[f])) return RSI_ERR_ARG;
+    if (xd->pts.n < 0 || tgt->n < 0) return RSI_ERR_SIZE;
+    for (int m = 0; m < n_if; ++m) {
+        if (ifaces[m].pts.n < 0) return RSI_ERR_SIZE;
+        if (m > 0 && !(ifaces[m].z > ifaces[m - 1].z)) return RSI_ERR_ARG;
+        if (ifaces[m].pts.n > 0 &&
+            (!ifaces[m].pts.x || !ifaces[m].pts.y || !ifaces[m].pts.z || !ifaces[m].w))
+            return RSI_ERR_NULL;
+    }
+    if (n_if > 0 && tmode == RSI_T_LOCAL && !(ifaces[0].z > xd->centre[2])) return RSI_ERR_ARG;
+    if (xd->pts.n > 0 && (!xd->pts.x || !xd->pts.y || !xd->pts.z || !xd->w)) return RSI_ERR_NULL;
+    if (tgt->n > 0 && n_freq > 0 && (!out || !tgt->x || !tgt->y || !tgt->z)) return RSI_ERR_NULL;
+    return RSI_OK;
+}
+
+rsi_status alloc_chain(const AllocFn &alloc, const rsi_transducer *xd, const rsi_interface *ifaces,
+                              int n_if, const rsi_points *tgt, rsi_precision prec, ChainWork &W) {
+    W.tco.assign(n_if, nullptr);
+    W.bbox.assign(n_if + 1, nullptr);
+    W.setf.assign(n_if + 1, SrcSetF{});
+    W.setd.assign(n_if + 1, SrcSetD{});
+    int64_t nmax = 1, nslot = 0;
+    for (int m = 0; m <= n_if; ++m) {
+        const rsi_points &sp = (m == 0) ? xd->pts : ifaces[m - 1].pts;
+        const rsi_points &tp = (m == n_if) ? *tgt : ifaces[m].pts;
+        const PairShape sh = default_shape(sp.n, tp.n);
+        const int64_t ps = partial_slots(sh, sp.n, tp.n);
+        if (ps > nslot) nslot = ps;
+        if (m < n_if && ifaces[m].pts.n > nmax) nmax = ifaces[m].pts.n;
+        if (prec == RSI_FP32) {
+            RSI_TRY(alloc((void **)&W.setf[m].rec, sizeof(SrcRecF) * (size_t)(sp.n > 0 ? sp.n : 1)));
+            RSI_TRY(alloc((void **)&W.setf[m].anchor, sizeof(double) * 4));
+            RSI_TRY(alloc((void **)&W.bbox[m], sizeof(double) * kBBoxBlocks * 6));
+        } else {
+            RSI_TRY(alloc((void **)&W.setd[m].rec, sizeof(SrcRecD) * (size_t)(sp.n > 0 ? sp.n : 1)));
+        }
+    }
+    for (int m = 0; m < n_if; ++m)
+        RSI_TRY(alloc((void **)&W.tco[m], sizeof(double) * 2 * (size_t)(ifaces[m].pts.n > 0 ? ifaces[m].pts.n : 1)));
+    const size_t esz = prec == RSI_FP32 ? sizeof(float2) : sizeof(double2);
+    RSI_TRY(alloc(&W.field[0], esz * (size_t)nmax));
+    RSI_TRY(alloc(&W.field[1], esz * (size_t)nmax));
+    RSI_TRY(alloc(&W.partial, esz * (size_t)(nslot > 0 ? nslot : 1)));
+    return RSI_OK;
+}
+
+// Enqueue the whole chain on `s` using the workspace W.
+rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
+                                const rsi_medium *media, const rsi_points *tgt,
+                                const double *freqs, int n_freq, rsi_tmode tmode,
+                                rsi_precision prec, void *out, ChainWork &W, hipStream_t s) {
+    static const double nz[3] = {0.0, 0.0, 1.0};
+    std::vector<double> zif(n_if > 0 ? n_if : 1);
+    for (int m = 0; m < n_if; ++m) zif[m] = ifaces[m].z;
+    // geometry of every source set, once for all frequencies
+    for (int m = 0; m <= n_if; ++m) {
+        const rsi_points &sp = (m == 0) ? xd->pts : ifaces[m - 1].pts;
+        const double *w = (m == 0) ? xd->w : ifaces[m - 1].w;
+        if (prec == RSI_FP32) {
+            if (sp.n > 0) {
+                RSI_TRY(bbox_partials(sp, W.bbox[m], s));
+                RSI_TRY(prep_sources_f32(sp, w, nullptr, m == 0 ? xd->v0 : 0.0, m == 0 ? nullptr : nz,
+                                         W.bbox[m], W.setf[m], s));
+            } else {
+                W.setf[m].n = 0;
+            }
+        } else {
+            RSI_TRY(prep_sources_f64(sp, w, nullptr, m == 0 ? xd->v0 : 0.0, W.setd[m], s));
+        }
+    }
+    for (int m = 1; m <= n_if; ++m)
+        RSI_TRY(transmission_device(tmode, m, zif.data(), media, xd->centre, xd->axis,
+                                    ifaces[m - 1].pts.n, ifaces[m - 1].pts.x, ifaces[m - 1].pts.y,
+                                    W.tco[m - 1], s));
+    const size_t esz = prec == RSI_FP32 ? sizeof(float2) : sizeof(double2);
+    for (int f = 0; f < n_freq; ++f) {
+        char *out_f = static_cast<char *>(out) + esz * (size_t)f * (size_t)tgt->n;
+        int cur = 0;
+        for (int m = 0; m <= n_if; ++m) {
+            const rsi_points &sp = (m == 0) ? xd->pts : ifaces[m - 1].pts;
+            const rsi_points &tp = (m == n_if) ? *tgt : ifaces[m].pts;
+            const Targets t{tp.x, tp.y, tp.z, tp.n};
+            // stage m reads field[cur] (m > 0) and writes field[cur ^ 1], or the output
+            void *dst = (m == n_if) ? (void *)out_f : W.field[m == 0 ? 0 : cur ^ 1];
+            const PairShape sh = default_shape(sp.n, tp.n);
+            const rsi_kernel kind = m == 0 ? RSI_MONOPOLE : RSI_DIPOLE;
+            if (prec == RSI_FP32) {
+                if (m > 0)
+                    RSI_TRY(set_strength_f32(W.setf[m], ifaces[m - 1].w, W.field[cur], false,
+                                             W.tco[m - 1], s));
+                RSI_TRY(pairsum_f32(W.setf[m], t, kind, m == 0 ? nullptr : nz, media[m].c, freqs[f],
+                                    sh, static_cast<float2 *>(W.partial), static_cast<float2 *>(dst), s));
+            } else {
+                if (m > 0)
+                    RSI_TRY(set_strength_f64(W.setd[m], ifaces[m - 1].w,
+                                             static_cast<const double *>(W.field[cur]), W.tco[m - 1], s));
+                RSI_TRY(pairsum_f64(W.setd[m], t, kind, m == 0 ? nullptr : nz, media[m].c, freqs[f],
+                                    sh, static_cast<double2 *>(W.partial), static_cast<double2 *>(dst), s));
+            }
+            if (m > 0) cur ^= 1;
+        }
+    }
+    return RSI_OK;
+}
+
+}  // namespace rsi
+
+using namespace rsi;
+
+extern "C" {
+
+rsi_status rsi_transmission(rsi_tmode tmode, int m, const double *zif, const rsi_medium *media,
+                            const double *xc, const double *axis, int64_t n, const double *qx,
+                            const double *qy, double *out, void *stream) {
+    return transmission_device(tmode, m, zif, media, xc, axis, n, qx, qy, out, as_stream(stream));
+}
+
+rsi_status rsi_to_pressure(int64_t n, const void *phi, rsi_precision prec, double rho,
+                           double freq, void *p, void *stream) {
+    if (n < 0) return RSI_ERR_SIZE;
+    if (prec != RSI_FP32 && prec != RSI_FP64) return RSI_ERR_ARG;
+    if (!(rho > 0.0) || !(freq > 0.0)) return RSI_ERR_ARG;
+    if (n == 0) return RSI_OK;
+    if (!phi || !p) return RSI_ERR_NULL;
+    const double scale = kTwoPi * freq * rho;
+    const dim3 g((unsigned)((n + 255) / 256));
+    if (prec == RSI_FP32)
+        hipLaunchKernelGGL(pressure_kernel<float2>, g, dim3(256), 0, as_stream(stream), n,
+                           static_cast<const float2 *>(phi), scale, static_cast<float2 *>(p));
+    else
+        hipLaunchKernelGGL(pressure_kernel<double2>, g, dim3(256), 0, as_stream(stream), n,
+                           static_cast<const double2 *>(phi), scale, static_cast<double2 *>(p));
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+rsi_status rsi_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
+                     const rsi_medium *media, const rsi_points *tgt, const double *freqs,
+                     int n_freq, rsi_tmode tmode, rsi_precision prec, void *out, void *stream) {
+    RSI_TRY(validate_chain(xd, ifaces, n_if, media, tgt, freqs, n_freq, tmode, prec, out));
+    if (tgt->n == 0 || n_freq == 0) return RSI_OK;
+    hipStream_t s = as_stream(stream);
+    Scratch scratch(s);
+    ChainWork W;
+    RSI_TRY(alloc_chain([&](void **p, size_t bytes) { return scratch.alloc((char **)p, bytes); },
+                        xd, ifaces, n_if, tgt, prec, W));
+    return enqueue_chain(xd, ifaces, n_if, media, tgt, freqs, n_freq, tmode, prec, out, W, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+// rsi_device.h -- device-side building blocks of the pair sum, shared by the one-shot
+// kernels (rsi_pairsum.hip) and the persistent batched kernels (rsi_batched.hip).
+//
+// Pair sum (eqs. 3 and 7 under eq. 16):
+//   phi(P_i) = sum_j s'_j K(P_i, Q_j),  s'_j = -(1/2pi) w_j s_j (folded at preparation)
+//   monopole K = e^{ikr}/r,  dipole K = cos(theta)(ik - 1/r) e^{ikr}/r.
+#pragma once
+
+#include "rsi_internal.h"
+
+namespace rsi {
+
+constexpr int kSub = 64;  // sources per FP32 partial block before the compensated fold
+
+// Per-target constants of the FP32 path (see rsi_pairsum.hip for the derivation).
+template <int KIND, int TPL>
+struct TargetsF {
+    float dmx[TPL], dmy[TPL], dmz[TPL];  // -2 (P - C)
+    float rr2[TPL], rr[TPL], p0[TPL];    // r_ref^2, r_ref, frac(r_ref f / c)
+    float ht[TPL];                       // n.(P - C) (dipole)
+};
+
+// FP64 set-up of TPL targets per lane: tbase + u * kBlock, u < TPL.  Targets past the
+// end repeat the last one (their results are never stored).
+template <int KIND, int TPL>
+__device__ __forceinline__ void setup_targets_f32(TargetsF<KIND, TPL> &T, const double *tx,
+                                                  const double *ty, const double *tz,
+                                                  int64_t n_tgt, int64_t tbase, double ax,
+                                                  double ay, double az, double inv_lam,
+                                                  double nx, double ny, double nz) {
+#pragma unroll
+    for (int u = 0; u < TPL; ++u) {
+        int64_t i = tbase + (int64_t)u * kBlock;
+        if (i >= n_tgt) i = n_tgt - 1;
+        const double dx = tx[i] - ax, dy = ty[i] - ay, dz = tz[i] - az;
+        const double rr2 = dx * dx + dy * dy + dz * dz;
+        const double rr = sqrt(rr2);
+        double ph = rr * inv_lam;  // reference phase in revolutions, reduced in FP64
+        ph -= floor(ph);
+        T.dmx[u] = (float)(-2.0 * dx);
+        T.dmy[u] = (float)(-2.0 * dy);
+        T.dmz[u] = (float)(-2.0 * dz);
+        T.rr2[u] = (float)rr2;
+        T.rr[u] = (float)rr;
+        T.p0[u] = (float)ph;
+        T.ht[u] = (float)(nx * dx + ny * dy + nz * dz);
+    }
+}
+
+// One source against the lane's TPL targets.  `s` is wave-uniform (SGPRs).
+template <int KIND, int TPL>
+__device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const SrcRecF &s,
+                                         float ilam, float k, float (&are)[TPL],
+                                         float (&aim)[TPL]) {
+#pragma unroll
+    for (int u = 0; u < TPL; ++u) {
+        float t = T.dmx[u] * s.ex;
+        t = fmaf(T.dmy[u], s.ey, t);
+        t = fmaf(T.dmz[u], s.ez, t);
+        const float q = t + s.es2;                           // r^2 - r_ref^2
+        const float r2 = fmaxf(T.rr2[u] + q, kR2MinF);
+        const float ir = __builtin_amdgcn_rsqf(r2);           // 1/r
+        const float den = fmaf(r2, ir, T.rr[u]);              // r + r_ref
+        const float dr = q * __builtin_amdgcn_rcpf(den);      // r - r_ref
+        const float ph = __builtin_amdgcn_fractf(fmaf(dr, ilam, T.p0[u]));  // revolutions
+        const float cs = __builtin_amdgcn_cosf(ph);
+        const float sn = __builtin_amdgcn_sinf(ph);
+        float gr, gi;
+        if constexpr (KIND == RSI_MONOPOLE) {
+            gr = cs * ir;  // e^{ikr}/r
+            gi = sn * ir;
+        } else {
+            const float g2 = (T.ht[u] - s.h) * ir * ir;  // cos(theta)/r
+            const float al = -g2 * ir, be = g2 * k;      // cos(theta)(ik - 1/r)/r
+            gr = al * cs - be * sn;
+            gi = fmaf(al, sn, be * cs);
+        }
+        are[u] = fmaf(s.sre, gr, are[u]);
+        are[u] = fmaf(-s.sim, gi, are[u]);
+        aim[u] = fmaf(s.sre, gi, aim[u]);
+        aim[u] = fmaf(s.sim, gr, aim[u]);
+    }
+}
+
+// Sum of sources [j0, j1): FP32 blocks of kSub sources folded into a Kahan-compensated
+// running sum (mre, mim with compensation cre, cim).
+template <int KIND, int TPL>
+__device__ __forceinline__ void sum_range_f32(const TargetsF<KIND, TPL> &T,
+                                              const SrcRecF *__restrict__ rec, int64_t j0,
+                                              int64_t j1, float ilam, float k,
+                                              float (&mre)[TPL], float (&mim)[TPL]) {
+    float cre[TPL], cim[TPL];
+#pragma unroll
+    for (int u = 0; u < TPL; ++u) mre[u] = mim[u] = cre[u] = cim[u] = 0.0f;
+    for (int64_t jb = j0; jb < j1; jb += kSub) {
+        const int64_t je = (jb + kSub < j1) ? jb + kSub : j1;
+        float are[TPL], aim[TPL];
+#pragma unroll
+        for (int u = 0; u < TPL; ++u) are[u] = aim[u] = 0.0f;
+        if (je - jb == kSub) {
+#pragma unroll 4
+            for (int jj = 0; jj < kSub; ++jj) pair_f32<KIND, TPL>(T, rec[jb + jj], ilam, k, are, aim);
+        } else {
+            for (int64_t j = jb; j < je; ++j) pair_f32<KIND, TPL>(T, rec[j], ilam, k, are, aim);
+        }
+#pragma unroll
+        for (int u = 0; u < TPL; ++u) {
+            float y = are[u] - cre[u];
+            float t = mre[u] + y;
+            cre[u] = (t - mre[u]) - y;
+            mre[u] = t;
+            y = aim[u] - cim[u];
+            t = mim[u] + y;
+            cim[u] = (t - mim[u]) - y;
+            mim[u] = t;
+        }
+    }
+}
+
+// FP64: sources [j0, j1) against one target, same operations as the definition.
+template <int KIND>
+__device__ __forceinline__ void sum_range_f64(double px, double py, double pz,
+                                              const SrcRecD *__restrict__ rec, int64_t j0,
+                                              int64_t j1, double inv_lam, double k, double nx,
+                                              double ny, double nz, double &mre, double &mim) {
+    double cre = 0.0, cim = 0.0;
+    mre = mim = 0.0;
+    for (int64_t jb = j0; jb < j1; jb += kSub) {
+        const int64_t je = (jb + kSub < j1) ? jb + kSub : j1;
+        double are = 0.0, aim = 0.0;
+        for (int64_t j = jb; j < je; ++j) {
+            const SrcRecD s = rec[j];
+            const double dx = px - s.x, dy = py - s.y, dz = pz - s.z;
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r < kRMin) continue;  // singular pair: contributes nothing
+            const double ir = 1.0 / r;
+            double ph = r * inv_lam;
+            ph -= rint(ph);  // k r in revolutions, reduced to [-1/2, 1/2]
+            double sn, cs;
+            sincospi(2.0 * ph, &sn, &cs);
+            double gr, gi;
+            if constexpr (KIND == RSI_MONOPOLE) {
+                gr = cs * ir;
+                gi = sn * ir;
+            } else {
+                const double g2 = (nx * dx + ny * dy + nz * dz) * ir * ir;
+                const double al = -g2 * ir, be = g2 * k;
+                gr = al * cs - be * sn;
+                gi = al * sn + be * cs;
+            }
+            are += s.sre * gr - s.sim * gi;
+            aim += s.sre * gi + s.sim * gr;
+        }
+        double y = are - cre, t = mre + y;
+        cre = (t - mre) - y;
+        mre = t;
+        y = aim - cim;
+        t = mim + y;
+        cim = (t - mim) - y;
+        mim = t;
+    }
+}
+
+}  // namespace rsi

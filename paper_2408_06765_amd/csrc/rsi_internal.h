@@ -1,0 +1,192 @@
+// rsi_internal.h -- shared internals of librsi (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/rsi.h"
+
+namespace rsi {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+// Pairs closer than this contribute nothing in the FP64 path (the kernel is
+// singular on the radiating surface).
+constexpr double kRMin = 1.0e-12;
+// Lower clamp of r^2 in the FP32 path (keeps rsqrt finite; see rsi.h).
+constexpr float kR2MinF = 1.0e-30f;
+
+// Threads per workgroup of the pair-sum kernels (four wave64s).
+constexpr int kBlock = 256;
+
+void set_last_error(const char *what, hipError_t e);
+
+#define RSI_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) {                                         \
+            ::rsi::set_last_error(#call, e_);                           \
+            return RSI_ERR_DEVICE;                                      \
+        }                                                               \
+    } while (0)
+
+#define RSI_TRY(call)                                                   \
+    do {                                                                \
+        rsi_status s_ = (call);                                         \
+        if (s_ != RSI_OK) return s_;                                    \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Stream-ordered scratch allocations released together (hipFreeAsync) on scope exit.
+class Scratch {
+public:
+    explicit Scratch(hipStream_t s) : stream_(s) {}
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    ~Scratch() {
+        for (void *p : ptrs_) (void)hipFreeAsync(p, stream_);
+    }
+    template <class T>
+    rsi_status alloc(T **p, size_t count) {
+        *p = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMallocAsync(reinterpret_cast<void **>(p), sizeof(T) * count, stream_);
+        if (e != hipSuccess) {
+            set_last_error("hipMallocAsync", e);
+            return RSI_ERR_WORKSPACE;
+        }
+        ptrs_.push_back(*p);
+        return RSI_OK;
+    }
+
+private:
+    hipStream_t stream_;
+    std::vector<void *> ptrs_;
+};
+
+// Device memory that lives as long as its owner (plans).
+class DeviceBuffer {
+public:
+    DeviceBuffer() = default;
+    DeviceBuffer(const DeviceBuffer &) = delete;
+    DeviceBuffer &operator=(const DeviceBuffer &) = delete;
+    ~DeviceBuffer() { release(); }
+    rsi_status alloc(size_t bytes) {
+        release();
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(&ptr_, bytes);
+        if (e != hipSuccess) {
+            ptr_ = nullptr;
+            set_last_error("hipMalloc", e);
+            return RSI_ERR_WORKSPACE;
+        }
+        bytes_ = bytes;
+        return RSI_OK;
+    }
+    void release() {
+        if (ptr_) (void)hipFree(ptr_);
+        ptr_ = nullptr;
+        bytes_ = 0;
+    }
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(ptr_); }
+    size_t bytes() const { return bytes_; }
+
+private:
+    void *ptr_ = nullptr;
+    size_t bytes_ = 0;
+};
+
+// ---------------------------------------------------------------------------
+// FP32 source records.  One record per source, read by wave-uniform (scalar)
+// loads: offsets from the set's anchor, |offset|^2, the folded strength
+// -(1/2pi) w_j s_j, and the normal offset n.e_j used by the dipole.
+// ---------------------------------------------------------------------------
+struct alignas(32) SrcRecF {
+    float ex, ey, ez, es2;
+    float sre, sim, h, pad;
+};
+
+// FP64 source records: absolute coordinates and folded strength.
+struct alignas(64) SrcRecD {
+    double x, y, z, pad0;
+    double sre, sim, pad1, pad2;
+};
+
+// A prepared source set on the device.
+struct SrcSetF {
+    SrcRecF *rec = nullptr;   // [n]
+    double *anchor = nullptr; // [4]: anchor x, y, z (device)
+    int64_t n = 0;
+};
+struct SrcSetD {
+    SrcRecD *rec = nullptr;
+    int64_t n = 0;
+};
+
+struct Targets {
+    const double *x, *y, *z;
+    int64_t n;
+};
+
+// Launch shape of one pair sum.
+struct PairShape {
+    int tpl = 2;          // targets per lane (1, 2 or 4)
+    int64_t chunk = 0;    // sources per split (0: all)
+};
+
+// --- rsi_pairsum.hip ---------------------------------------------------------
+rsi_status bbox_partials(const rsi_points &pts, double *partials /*[kBBoxBlocks*6]*/,
+                         hipStream_t s);
+constexpr int kBBoxBlocks = 64;
+rsi_status prep_sources_f32(const rsi_points &pts, const double *w, const double *vel,
+                            double v0, const double *normal, const double *partials,
+                            SrcSetF &set, hipStream_t s);
+rsi_status set_strength_f32(SrcSetF &set, const double *w, const void *field, bool field_fp64,
+                            const double *tco, hipStream_t s);
+rsi_status prep_sources_f64(const rsi_points &pts, const double *w, const double *vel,
+                            double v0, SrcSetD &set, hipStream_t s);
+rsi_status set_strength_f64(SrcSetD &set, const double *w, const double *field,
+                            const double *tco, hipStream_t s);
+PairShape default_shape(int64_t n_src, int64_t n_tgt);
+int64_t partial_slots(const PairShape &sh, int64_t n_src, int64_t n_tgt);
+rsi_status pairsum_f32(const SrcSetF &set, const Targets &t, rsi_kernel kind,
+                       const double *normal, double c, double freq, const PairShape &sh,
+                       float2 *partial, float2 *out, hipStream_t s);
+rsi_status pairsum_f64(const SrcSetD &set, const Targets &t, rsi_kernel kind,
+                       const double *normal, double c, double freq, const PairShape &sh,
+                       double2 *partial, double2 *out, hipStream_t s);
+
+// --- rsi_chain.hip -----------------------------------------------------------
+// Workspace of a chain: shared by the one-shot call and the chain plan.
+struct ChainWork {
+    std::vector<double *> tco;   // complex FP64 transmission coefficients per interface
+    std::vector<double *> bbox;  // partial extents per source set
+    std::vector<SrcSetF> setf;   // [0]: transducer, [m]: interface m
+    std::vector<SrcSetD> setd;
+    void *field[2] = {nullptr, nullptr};
+    void *partial = nullptr;
+};
+using AllocFn = std::function<rsi_status(void **, size_t)>;
+rsi_status validate_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
+                          const rsi_medium *media, const rsi_points *tgt, const double *freqs,
+                          int n_freq, rsi_tmode tmode, rsi_precision prec, void *out);
+rsi_status alloc_chain(const AllocFn &alloc, const rsi_transducer *xd,
+                       const rsi_interface *ifaces, int n_if, const rsi_points *tgt,
+                       rsi_precision prec, ChainWork &W);
+rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
+                         const rsi_medium *media, const rsi_points *tgt, const double *freqs,
+                         int n_freq, rsi_tmode tmode, rsi_precision prec, void *out,
+                         ChainWork &W, hipStream_t s);
+rsi_status transmission_device(rsi_tmode tmode, int m, const double *zif,
+                               const rsi_medium *media, const double *xc, const double *axis,
+                               int64_t n, const double *qx, const double *qy, double *out,
+                               hipStream_t s);
+
+}  // namespace rsi

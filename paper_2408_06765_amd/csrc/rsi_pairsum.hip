@@ -1,0 +1,485 @@
+// rsi_pairsum.hip -- the RSI pair sum (eqs. 3 and 7 under the estimator of eq. 16).
+//
+//   phi(P_i) = -(1/2pi) sum_j w_j s_j K(P_i, Q_j)
+//   monopole K = e^{ikr}/r,  dipole K = cos(theta)(ik - 1/r) e^{ikr}/r.
+//
+// Layout and precision (FP32 path)
+//   * Sources are prepared once per set into 32-byte records: the offset e_j of the
+//     source from the set's anchor C (bounding-box centre) in FP32, |e_j|^2, the folded
+//     strength -(1/2pi) w_j s_j, and n.e_j for the dipole.  All lanes of a wave walk
+//     the same source at the same time, so the records are read with wave-uniform
+//     (scalar) loads into SGPRs and broadcast to every lane for free: no LDS traffic
+//     and no VGPRs spent on source data.
+//   * Field points are coalesced, TPL per lane.  For each target the kernel computes,
+//     once and in FP64, D = P - C, r_ref = |D| and the reference phase
+//     frac(r_ref f / c) in revolutions.  Per pair it then needs only FP32:
+//         q  = |e|^2 - 2 D.e              ( = r^2 - r_ref^2 )
+//         r  = sqrt(r_ref^2 + q)          (via rsqrt, amplitude only)
+//         dr = q / (r + r_ref)            ( = r - r_ref, free of cancellation )
+//         phase = frac(p_ref + dr f / c)  (revolutions, fed to v_sin/v_cos directly)
+//     so the large part of k r never passes through FP32.
+//   * Sums run in FP32: per 64-source block, then folded into a Kahan-compensated
+//     running sum.  Source ranges may be split across workgroups (split-K); partial
+//     sums are reduced in a fixed order, so results are bitwise repeatable.
+//
+// FP64 path: absolute coordinates, r from sqrt, phase reduced to revolutions and
+// evaluated with sincospi, pairs closer than 1e-12 m skipped -- the same operations
+// as the definition, in FP64.
+#include <cfloat>
+#include <cmath>
+
+#include "rsi_device.h"
+
+namespace rsi {
+
+// ---------------------------------------------------------------------------
+// Anchor: bounding-box centre of the source set, from per-block partial extents.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) bbox_kernel(const double *__restrict__ x,
+                                                   const double *__restrict__ y,
+                                                   const double *__restrict__ z, int64_t n,
+                                                   double *__restrict__ partials) {
+    double v[6] = {DBL_MAX, DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX, -DBL_MAX};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        const double a = x[i], b = y[i], c = z[i];
+        v[0] = fmin(v[0], a); v[1] = fmin(v[1], b); v[2] = fmin(v[2], c);
+        v[3] = fmax(v[3], a); v[4] = fmax(v[4], b); v[5] = fmax(v[5], c);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[k] = fmin(v[k], __shfl_xor(v[k], off));
+#pragma unroll
+        for (int k = 3; k < 6; ++k) v[k] = fmax(v[k], __shfl_xor(v[k], off));
+    }
+    __shared__ double sh[4][6];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) sh[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double r = sh[0][k];
+        for (int w = 1; w < 4; ++w) r = (k < 3) ? fmin(r, sh[w][k]) : fmax(r, sh[w][k]);
+        partials[blockIdx.x * 6 + k] = r;
+    }
+}
+
+__device__ inline void anchor_from_partials(const double *__restrict__ partials, double &ax,
+                                            double &ay, double &az) {
+    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    for (int b = 0; b < kBBoxBlocks; ++b)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], partials[b * 6 + k]);
+            hi[k] = fmax(hi[k], partials[b * 6 + 3 + k]);
+        }
+    ax = 0.5 * (lo[0] + hi[0]);
+    ay = 0.5 * (lo[1] + hi[1]);
+    az = 0.5 * (lo[2] + hi[2]);
+}
+
+rsi_status bbox_partials(const rsi_points &pts, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(bbox_kernel, dim3(kBBoxBlocks), dim3(256), 0, s, pts.x, pts.y, pts.z,
+                       pts.n, partials);
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Source preparation.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) prep_f32_kernel(
+    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const double *__restrict__ w, const double *__restrict__ vel,
+    double v0, double nx, double ny, double nz, const double *__restrict__ partials,
+    double *__restrict__ anchor_out, SrcRecF *__restrict__ rec) {
+    double ax, ay, az;
+    anchor_from_partials(partials, ax, ay, az);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        anchor_out[0] = ax;
+        anchor_out[1] = ay;
+        anchor_out[2] = az;
+        anchor_out[3] = 0.0;
+    }
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const float ex = (float)(x[j] - ax), ey = (float)(y[j] - ay), ez = (float)(z[j] - az);
+    const double dex = ex, dey = ey, dez = ez;  // the rounded offset is the source position
+    double sre = v0, sim = 0.0;
+    if (vel) {
+        sre = vel[2 * j];
+        sim = vel[2 * j + 1];
+    }
+    const double scale = -w[j] / kTwoPi;
+    SrcRecF r;
+    r.ex = ex;
+    r.ey = ey;
+    r.ez = ez;
+    r.es2 = (float)(dex * dex + dey * dey + dez * dez);
+    r.sre = (float)(scale * sre);
+    r.sim = (float)(scale * sim);
+    r.h = (float)(nx * dex + ny * dey + nz * dez);
+    r.pad = 0.0f;
+    rec[j] = r;
+}
+
+// s_j = T_j phi_j (interface strength, eq. 7) folded with -(1/2pi) w_j.
+template <typename FieldT>
+__global__ void __launch_bounds__(256) strength_f32_kernel(int64_t n, const double *__restrict__ w,
+                                                           const FieldT *__restrict__ field,
+                                                           const double *__restrict__ tco,
+                                                           SrcRecF *__restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const double fre = field[2 * j], fim = field[2 * j + 1];
+    double sre = fre, sim = fim;
+    if (tco) {
+        const double tre = tco[2 * j], tim = tco[2 * j + 1];
+        sre = tre * fre - tim * fim;
+        sim = tre * fim + tim * fre;
+    }
+    const double scale = -w[j] / kTwoPi;
+    rec[j].sre = (float)(scale * sre);
+    rec[j].sim = (float)(scale * sim);
+}
+
+__global__ void __launch_bounds__(256) prep_f64_kernel(int64_t n, const double *__restrict__ x,
+                                                       const double *__restrict__ y,
+                                                       const double *__restrict__ z,
+                                                       const double *__restrict__ w,
+                                                       const double *__restrict__ vel, double v0,
+                                                       SrcRecD *__restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    double sre = v0, sim = 0.0;
+    if (vel) {
+        sre = vel[2 * j];
+        sim = vel[2 * j + 1];
+    }
+    const double scale = -w[j] / kTwoPi;
+    SrcRecD r;
+    r.x = x[j];
+    r.y = y[j];
+    r.z = z[j];
+    r.pad0 = 0.0;
+    r.sre = scale * sre;
+    r.sim = scale * sim;
+    r.pad1 = r.pad2 = 0.0;
+    rec[j] = r;
+}
+
+__global__ void __launch_bounds__(256) strength_f64_kernel(int64_t n, const double *__restrict__ w,
+                                                           const double *__restrict__ field,
+                                                           const double *__restrict__ tco,
+                                                           SrcRecD *__restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const double fre = field[2 * j], fim = field[2 * j + 1];
+    double sre = fre, sim = fim;
+    if (tco) {
+        const double tre = tco[2 * j], tim = tco[2 * j + 1];
+        sre = tre * fre - tim * fim;
+        sim = tre * fim + tim * fre;
+    }
+    const double scale = -w[j] / kTwoPi;
+    rec[j].sre = scale * sre;
+    rec[j].sim = scale * sim;
+}
+
+static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+static void unit_normal(const double *normal, double &nx, double &ny, double &nz) {
+    nx = ny = nz = 0.0;
+    if (!normal) return;
+    const double l = sqrt(normal[0] * normal[0] + normal[1] * normal[1] + normal[2] * normal[2]);
+    if (l > 0.0) {
+        nx = normal[0] / l;
+        ny = normal[1] / l;
+        nz = normal[2] / l;
+    }
+}
+
+rsi_status prep_sources_f32(const rsi_points &pts, const double *w, const double *vel,
+                            double v0, const double *normal, const double *partials,
+                            SrcSetF &set, hipStream_t s) {
+    double nx, ny, nz;
+    unit_normal(normal, nx, ny, nz);
+    set.n = pts.n;
+    if (pts.n == 0) return RSI_OK;
+    hipLaunchKernelGGL(prep_f32_kernel, dim3(blocks_for(pts.n)), dim3(256), 0, s, pts.n, pts.x,
+                       pts.y, pts.z, w, vel, v0, nx, ny, nz, partials, set.anchor, set.rec);
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+rsi_status set_strength_f32(SrcSetF &set, const double *w, const void *field, bool field_fp64,
+                            const double *tco, hipStream_t s) {
+    if (set.n == 0) return RSI_OK;
+    if (field_fp64)
+        hipLaunchKernelGGL(strength_f32_kernel<double>, dim3(blocks_for(set.n)), dim3(256), 0, s,
+                           set.n, w, static_cast<const double *>(field), tco, set.rec);
+    else
+        hipLaunchKernelGGL(strength_f32_kernel<float>, dim3(blocks_for(set.n)), dim3(256), 0, s,
+                           set.n, w, static_cast<const float *>(field), tco, set.rec);
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+rsi_status prep_sources_f64(const rsi_points &pts, const double *w, const double *vel,
+                            double v0, SrcSetD &set, hipStream_t s) {
+    set.n = pts.n;
+    if (pts.n == 0) return RSI_OK;
+    hipLaunchKernelGGL(prep_f64_kernel, dim3(blocks_for(pts.n)), dim3(256), 0, s, pts.n, pts.x,
+                       pts.y, pts.z, w, vel, v0, set.rec);
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+rsi_status set_strength_f64(SrcSetD &set, const double *w, const double *field,
+                            const double *tco, hipStream_t s) {
+    if (set.n == 0) return RSI_OK;
+    hipLaunchKernelGGL(strength_f64_kernel, dim3(blocks_for(set.n)), dim3(256), 0, s, set.n, w,
+                       field, tco, set.rec);
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 pair-sum kernel: grid (target tiles of kBlock*TPL, source splits).
+// ---------------------------------------------------------------------------
+template <int KIND, int TPL>
+__global__ void __launch_bounds__(kBlock) pairsum_f32_kernel(
+    const SrcRecF *__restrict__ rec, int64_t n_src, int64_t chunk,
+    const double *__restrict__ tx, const double *__restrict__ ty, const double *__restrict__ tz,
+    int64_t n_tgt, const double *__restrict__ anchor, double inv_lam, float k, double nx,
+    double ny, double nz, float2 *__restrict__ out) {
+    TargetsF<KIND, TPL> T;
+    const int64_t tbase = (int64_t)blockIdx.x * (kBlock * TPL) + threadIdx.x;
+    setup_targets_f32<KIND, TPL>(T, tx, ty, tz, n_tgt, tbase, anchor[0], anchor[1], anchor[2],
+                                 inv_lam, nx, ny, nz);
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = (j0 + chunk < n_src) ? j0 + chunk : n_src;
+    float mre[TPL], mim[TPL];
+    sum_range_f32<KIND, TPL>(T, rec, j0, j1, (float)inv_lam, k, mre, mim);
+    float2 *o = out + (int64_t)blockIdx.y * n_tgt;
+#pragma unroll
+    for (int u = 0; u < TPL; ++u) {
+        const int64_t i = tbase + (int64_t)u * kBlock;
+        if (i < n_tgt) o[i] = make_float2(mre[u], mim[u]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 pair-sum kernel (one target per lane).
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) pairsum_f64_kernel(
+    const SrcRecD *__restrict__ rec, int64_t n_src, int64_t chunk,
+    const double *__restrict__ tx, const double *__restrict__ ty, const double *__restrict__ tz,
+    int64_t n_tgt, double inv_lam, double k, double nx, double ny, double nz,
+    double2 *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < n_tgt;
+    if (!valid) i = n_tgt - 1;
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = (j0 + chunk < n_src) ? j0 + chunk : n_src;
+    double mre, mim;
+    sum_range_f64<KIND>(tx[i], ty[i], tz[i], rec, j0, j1, inv_lam, k, nx, ny, nz, mre, mim);
+    if (valid) out[(int64_t)blockIdx.y * n_tgt + i] = make_double2(mre, mim);
+}
+
+// ---------------------------------------------------------------------------
+// Split-K reduction (fixed order) and zero fill.
+// ---------------------------------------------------------------------------
+template <typename T2>
+__global__ void __launch_bounds__(256) reduce_splits_kernel(const T2 *__restrict__ partial,
+                                                            int n_split, int64_t n,
+                                                            T2 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < n_split; ++s) {
+        const T2 v = partial[(int64_t)s * n + i];
+        re += (double)v.x;
+        im += (double)v.y;
+    }
+    T2 r;
+    r.x = re;
+    r.y = im;
+    out[i] = r;
+}
+
+template <typename T2>
+__global__ void __launch_bounds__(256) zero_kernel(int64_t n, T2 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        T2 z;
+        z.x = 0;
+        z.y = 0;
+        out[i] = z;
+    }
+}
+
+PairShape default_shape(int64_t n_src, int64_t n_tgt) {
+    PairShape sh;
+    sh.tpl = 2;
+    const int64_t bx = (n_tgt + kBlock * sh.tpl - 1) / (kBlock * sh.tpl);
+    // aim for >= 2048 workgroups (8 per CU) while keeping >= 4096 sources per split
+    int64_t splits = (2048 + bx - 1) / (bx > 0 ? bx : 1);
+    const int64_t max_splits = (n_src + 4095) / 4096;
+    if (splits > max_splits) splits = max_splits;
+    if (splits < 1) splits = 1;
+    int64_t chunk = (n_src + splits - 1) / splits;
+    chunk = (chunk + kSub - 1) / kSub * kSub;
+    sh.chunk = chunk > 0 ? chunk : kSub;
+    return sh;
+}
+
+static int64_t n_splits(const PairShape &sh, int64_t n_src) {
+    if (n_src <= 0) return 1;
+    const int64_t chunk = sh.chunk > 0 ? sh.chunk : n_src;
+    return (n_src + chunk - 1) / chunk;
+}
+
+int64_t partial_slots(const PairShape &sh, int64_t n_src, int64_t n_tgt) {
+    const int64_t ns = n_splits(sh, n_src);
+    return ns > 1 ? ns * n_tgt : 0;
+}
+
+template <int KIND, int TPL>
+static void launch_f32(dim3 grid, hipStream_t s, const SrcSetF &set, int64_t chunk,
+                       const Targets &t, double inv_lam, float k, double nx, double ny,
+                       double nz, float2 *dst) {
+    hipLaunchKernelGGL((pairsum_f32_kernel<KIND, TPL>), grid, dim3(kBlock), 0, s, set.rec, set.n,
+                       chunk, t.x, t.y, t.z, t.n, set.anchor, inv_lam, k, nx, ny, nz, dst);
+}
+
+rsi_status pairsum_f32(const SrcSetF &set, const Targets &t, rsi_kernel kind,
+                       const double *normal, double c, double freq, const PairShape &sh,
+                       float2 *partial, float2 *out, hipStream_t s) {
+    if (t.n == 0) return RSI_OK;
+    if (set.n == 0) {
+        hipLaunchKernelGGL(zero_kernel<float2>, dim3(blocks_for(t.n)), dim3(256), 0, s, t.n, out);
+        RSI_HIP(hipGetLastError());
+        return RSI_OK;
+    }
+    double nx, ny, nz;
+    unit_normal(normal, nx, ny, nz);
+    const int tpl = (sh.tpl == 1 || sh.tpl == 4) ? sh.tpl : 2;
+    const int64_t chunk = sh.chunk > 0 ? sh.chunk : set.n;
+    const int64_t ns = n_splits(sh, set.n);
+    if (ns > 65535) return RSI_ERR_SIZE;
+    const int64_t bx = (t.n + (int64_t)kBlock * tpl - 1) / ((int64_t)kBlock * tpl);
+    if (bx > 0x7fffffff) return RSI_ERR_SIZE;
+    const dim3 grid((unsigned)bx, (unsigned)ns);
+    float2 *dst = ns > 1 ? partial : out;
+    if (ns > 1 && !partial) return RSI_ERR_WORKSPACE;
+    const double inv_lam = freq / c;
+    const float k = (float)(kTwoPi * freq / c);
+    if (kind == RSI_MONOPOLE) {
+        if (tpl == 1) launch_f32<RSI_MONOPOLE, 1>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
+        else if (tpl == 2) launch_f32<RSI_MONOPOLE, 2>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
+        else launch_f32<RSI_MONOPOLE, 4>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
+    } else {
+        if (tpl == 1) launch_f32<RSI_DIPOLE, 1>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
+        else if (tpl == 2) launch_f32<RSI_DIPOLE, 2>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
+        else launch_f32<RSI_DIPOLE, 4>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
+    }
+    RSI_HIP(hipGetLastError());
+    if (ns > 1) {
+        hipLaunchKernelGGL(reduce_splits_kernel<float2>, dim3(blocks_for(t.n)), dim3(256), 0, s,
+                           partial, (int)ns, t.n, out);
+        RSI_HIP(hipGetLastError());
+    }
+    return RSI_OK;
+}
+
+rsi_status pairsum_f64(const SrcSetD &set, const Targets &t, rsi_kernel kind,
+                       const double *normal, double c, double freq, const PairShape &sh,
+                       double2 *partial, double2 *out, hipStream_t s) {
+    if (t.n == 0) return RSI_OK;
+    if (set.n == 0) {
+        hipLaunchKernelGGL(zero_kernel<double2>, dim3(blocks_for(t.n)), dim3(256), 0, s, t.n, out);
+        RSI_HIP(hipGetLastError());
+        return RSI_OK;
+    }
+    double nx, ny, nz;
+    unit_normal(normal, nx, ny, nz);
+    const int64_t chunk = sh.chunk > 0 ? sh.chunk : set.n;
+    const int64_t ns = n_splits(sh, set.n);
+    if (ns > 65535) return RSI_ERR_SIZE;
+    const int64_t bx = (t.n + kBlock - 1) / kBlock;
+    if (bx > 0x7fffffff) return RSI_ERR_SIZE;
+    const dim3 grid((unsigned)bx, (unsigned)ns);
+    double2 *dst = ns > 1 ? partial : out;
+    if (ns > 1 && !partial) return RSI_ERR_WORKSPACE;
+    const double inv_lam = freq / c, k = kTwoPi * freq / c;
+    if (kind == RSI_MONOPOLE)
+        hipLaunchKernelGGL(pairsum_f64_kernel<RSI_MONOPOLE>, grid, dim3(kBlock), 0, s, set.rec,
+                           set.n, chunk, t.x, t.y, t.z, t.n, inv_lam, k, nx, ny, nz, dst);
+    else
+        hipLaunchKernelGGL(pairsum_f64_kernel<RSI_DIPOLE>, grid, dim3(kBlock), 0, s, set.rec,
+                           set.n, chunk, t.x, t.y, t.z, t.n, inv_lam, k, nx, ny, nz, dst);
+    RSI_HIP(hipGetLastError());
+    if (ns > 1) {
+        hipLaunchKernelGGL(reduce_splits_kernel<double2>, dim3(blocks_for(t.n)), dim3(256), 0, s,
+                           partial, (int)ns, t.n, out);
+        RSI_HIP(hipGetLastError());
+    }
+    return RSI_OK;
+}
+
+}  // namespace rsi
+
+using namespace rsi;
+
+extern "C" rsi_status rsi_propagate(const rsi_points *src, const double *src_w,
+                                    const double *src_vel, const double *normal,
+                                    const rsi_points *tgt, rsi_medium medium, double freq,
+                                    rsi_kernel kind, rsi_precision prec, void *out,
+                                    void *stream) {
+    if (!src || !tgt) return RSI_ERR_NULL;
+    if (kind != RSI_MONOPOLE && kind != RSI_DIPOLE) return RSI_ERR_ARG;
+    if (prec != RSI_FP32 && prec != RSI_FP64) return RSI_ERR_ARG;
+    if (!(freq > 0.0) || !(medium.c > 0.0) || !std::isfinite(freq) || !std::isfinite(medium.c))
+        return RSI_ERR_ARG;
+    if (src->n < 0 || tgt->n < 0) return RSI_ERR_SIZE;
+    if (tgt->n == 0) return RSI_OK;
+    if (!out || !tgt->x || !tgt->y || !tgt->z) return RSI_ERR_NULL;
+    if (src->n > 0 && (!src->x || !src->y || !src->z || !src_w || !src_vel)) return RSI_ERR_NULL;
+    if (kind == RSI_DIPOLE) {
+        if (!normal) return RSI_ERR_NULL;
+        const double l2 = normal[0] * normal[0] + normal[1] * normal[1] + normal[2] * normal[2];
+        if (!(l2 > 0.0) || !std::isfinite(l2)) return RSI_ERR_ARG;
+    }
+    hipStream_t s = as_stream(stream);
+    Scratch scratch(s);
+    const Targets t{tgt->x, tgt->y, tgt->z, tgt->n};
+    const PairShape sh = default_shape(src->n, tgt->n);
+    const int64_t nslots = partial_slots(sh, src->n, tgt->n);
+    if (prec == RSI_FP32) {
+        SrcSetF set;
+        double *partials = nullptr;
+        float2 *partial = nullptr;
+        if (src->n > 0) {
+            RSI_TRY(scratch.alloc(&set.rec, (size_t)src->n));
+            RSI_TRY(scratch.alloc(&set.anchor, 4));
+            RSI_TRY(scratch.alloc(&partials, kBBoxBlocks * 6));
+            RSI_TRY(bbox_partials(*src, partials, s));
+            RSI_TRY(prep_sources_f32(*src, src_w, src_vel, 0.0, normal, partials, set, s));
+        }
+        if (nslots > 0) RSI_TRY(scratch.alloc(&partial, (size_t)nslots));
+        return pairsum_f32(set, t, kind, normal, medium.c, freq, sh, partial,
+                           static_cast<float2 *>(out), s);
+    }
+    SrcSetD set;
+    double2 *partial = nullptr;
+    if (src->n > 0) {
+        RSI_TRY(scratch.alloc(&set.rec, (size_t)src->n));
+        RSI_TRY(prep_sources_f64(*src, src_w, src_vel, 0.0, set, s));
+    }
+    if (nslots > 0) RSI_TRY(scratch.alloc(&partial, (size_t)nslots));
+    return pairsum_f64(set, t, kind, normal, medium.c, freq, sh, partial,
+                       static_cast<double2 *>(out), s);
+}

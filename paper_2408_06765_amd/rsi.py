@@ -1,0 +1,275 @@
+"""Python binding of librsi: same names as the C ABI, argument marshalling only.
+
+Tensors are torch CUDA (HIP) tensors; every call enqueues on
+``torch.cuda.current_stream()``.  Point coordinates and weights are float64; complex
+strengths are complex128; outputs are complex64 (RSI_FP32) or complex128 (RSI_FP64).
+No arithmetic of the method happens here: every step runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+RSI_MONOPOLE, RSI_DIPOLE = 0, 1
+RSI_FP32, RSI_FP64 = 0, 1
+RSI_T_GLOBAL, RSI_T_LOCAL, RSI_T_UNITY = 0, 1, 2
+
+_OUT_DTYPE = {RSI_FP32: torch.complex64, RSI_FP64: torch.complex128}
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, what: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor]) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr() if t is not None and t.numel() > 0 else None)
+
+
+def _points(x, y, z, what: str) -> L.rsi_points:
+    for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+        _dev(t, torch.float64, f"{what}.{nm}")
+    n = x.numel()
+    if y.numel() != n or z.numel() != n:
+        raise ValueError(f"{what}: x, y, z lengths differ")
+    return L.rsi_points(_ptr(x), _ptr(y), _ptr(z), n)
+
+
+def _dvec(v) -> C.Array:
+    arr = (C.c_double * len(v))(*[float(a) for a in v])
+    return arr
+
+
+def _media(media) -> C.Array:
+    arr = (L.rsi_medium * len(media))()
+    for i, (c, rho) in enumerate(media):
+        arr[i] = L.rsi_medium(float(c), float(rho))
+    return arr
+
+
+# ---------------------------------------------------------------------------- a1
+def rsi_sobol2d(seed: int, n: int, first: int = 0, device="cuda") -> torch.Tensor:
+    """Scrambled Sobol points as int32-stored uint32 pairs [n, 2] (bit patterns)."""
+    out = torch.empty((n, 2), dtype=torch.int32, device=device)
+    L.check(L.load().rsi_sobol2d(seed & 0xFFFFFFFF, first, n, _ptr(out), _stream()), "rsi_sobol2d")
+    return out
+
+
+def rsi_sample_disc(seed: int, n: int, radius: float, centre=(0.0, 0.0, 0.0), tilt: float = 0.0,
+                    device="cuda"):
+    """Piston face samples (eq. 18): returns x, y, z, w (float64)."""
+    bufs = [torch.empty(n, dtype=torch.float64, device=device) for _ in range(4)]
+    L.check(L.load().rsi_sample_disc(seed & 0xFFFFFFFF, n, radius, _dvec(centre), tilt,
+                                     *[_ptr(b) for b in bufs], _stream()), "rsi_sample_disc")
+    return tuple(bufs)
+
+
+def rsi_sample_square(seed: int, n: int, cx: float, cy: float, z0: float, half_width: float,
+                      device="cuda"):
+    """Interface patch samples (eq. 17): returns x, y, z, w (float64)."""
+    bufs = [torch.empty(n, dtype=torch.float64, device=device) for _ in range(4)]
+    L.check(L.load().rsi_sample_square(seed & 0xFFFFFFFF, n, cx, cy, z0, half_width,
+                                       *[_ptr(b) for b in bufs], _stream()), "rsi_sample_square")
+    return tuple(bufs)
+
+
+# ---------------------------------------------------------------------------- a2
+def rsi_transmission(tmode: int, m: int, zif: Sequence[float], media, xc, axis,
+                     qx: torch.Tensor, qy: torch.Tensor) -> torch.Tensor:
+    """Per-sample transmission coefficient at interface m (1-based), complex128."""
+    _dev(qx, torch.float64, "qx")
+    _dev(qy, torch.float64, "qy")
+    out = torch.empty(qx.numel(), dtype=torch.complex128, device=qx.device)
+    L.check(L.load().rsi_transmission(tmode, m, _dvec(zif), _media(media), _dvec(xc), _dvec(axis),
+                                      qx.numel(), _ptr(qx), _ptr(qy), _ptr(out), _stream()),
+            "rsi_transmission")
+    return out
+
+
+# ---------------------------------------------------------------------------- a3/a4
+def rsi_propagate(src, w: torch.Tensor, vel: torch.Tensor, tgt, c: float, freq: float,
+                  kind: int, prec: int, normal=None, rho: float = 1000.0,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """phi at the targets (complex64 for RSI_FP32, complex128 for RSI_FP64)."""
+    sp = _points(*src, "src")
+    tp = _points(*tgt, "tgt")
+    _dev(w, torch.float64, "w")
+    _dev(vel, torch.complex128, "vel")
+    if out is None:
+        out = torch.empty(tp.n, dtype=_OUT_DTYPE[prec], device=tgt[0].device)
+    _dev(out, _OUT_DTYPE[prec], "out")
+    nrm = _dvec(normal) if normal is not None else None
+    L.check(L.load().rsi_propagate(C.byref(sp), _ptr(w), _ptr(vel), nrm, C.byref(tp),
+                                   L.rsi_medium(c, rho), freq, kind, prec, _ptr(out), _stream()),
+            "rsi_propagate")
+    return out
+
+
+# ---------------------------------------------------------------------------- a5
+@dataclass
+class Transducer:
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    w: torch.Tensor
+    v0: float = 1.0
+    centre: Sequence[float] = (0.0, 0.0, 0.0)
+    axis: Sequence[float] = (0.0, 0.0, 1.0)
+
+    def c_struct(self) -> L.rsi_transducer:
+        _dev(self.w, torch.float64, "transducer.w")
+        return L.rsi_transducer(_points(self.x, self.y, self.z, "transducer"), _ptr(self.w),
+                                float(self.v0), _dvec(self.centre), _dvec(self.axis))
+
+
+@dataclass
+class Interface:
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    w: torch.Tensor
+    depth: float
+
+    def c_struct(self) -> L.rsi_interface:
+        _dev(self.w, torch.float64, "interface.w")
+        return L.rsi_interface(_points(self.x, self.y, self.z, "interface"), _ptr(self.w),
+                               float(self.depth))
+
+
+def _chain_args(xd: Transducer, ifaces: Sequence[Interface], media, tgt, freqs):
+    xs = xd.c_struct()
+    arr = (L.rsi_interface * max(len(ifaces), 1))()
+    for i, f in enumerate(ifaces):
+        arr[i] = f.c_struct()
+    if len(media) != len(ifaces) + 1:
+        raise ValueError("need one medium per layer: len(media) == len(ifaces) + 1")
+    tp = _points(*tgt, "tgt")
+    fr = _dvec(list(freqs))
+    return xs, arr, _media(media), tp, fr
+
+
+def rsi_chain(xd: Transducer, ifaces: Sequence[Interface], media, tgt, freqs, tmode: int,
+              prec: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Field after the whole stack, complex [n_freq, n_tgt]."""
+    xs, arr, med, tp, fr = _chain_args(xd, ifaces, media, tgt, freqs)
+    if out is None:
+        out = torch.empty((len(freqs), tp.n), dtype=_OUT_DTYPE[prec], device=tgt[0].device)
+    _dev(out, _OUT_DTYPE[prec], "out")
+    L.check(L.load().rsi_chain(C.byref(xs), arr, len(ifaces), med, C.byref(tp), fr, len(freqs),
+                               tmode, prec, _ptr(out), _stream()), "rsi_chain")
+    return out
+
+
+# ---------------------------------------------------------------------------- a7
+@dataclass
+class Instance:
+    src: tuple
+    w: torch.Tensor
+    tgt: tuple
+    c: float
+    freq: float
+    kind: int = RSI_MONOPOLE
+    vel: Optional[torch.Tensor] = None
+    v0: float = 1.0
+    normal: Sequence[float] = (0.0, 0.0, 1.0)
+    rho: float = 1000.0
+    out: Optional[torch.Tensor] = None
+
+    def c_struct(self, prec: int) -> L.rsi_instance:
+        sp = _points(*self.src, "instance.src")
+        tp = _points(*self.tgt, "instance.tgt")
+        _dev(self.w, torch.float64, "instance.w")
+        if self.vel is not None:
+            _dev(self.vel, torch.complex128, "instance.vel")
+        if self.out is None:
+            self.out = torch.empty(tp.n, dtype=_OUT_DTYPE[prec], device=self.tgt[0].device)
+        _dev(self.out, _OUT_DTYPE[prec], "instance.out")
+        return L.rsi_instance(sp, _ptr(self.w), _ptr(self.vel), float(self.v0), _dvec(self.normal),
+                              tp, L.rsi_medium(self.c, self.rho), float(self.freq), int(self.kind),
+                              _ptr(self.out))
+
+
+def _instances(insts: Sequence[Instance], prec: int):
+    arr = (L.rsi_instance * max(len(insts), 1))()
+    for i, it in enumerate(insts):
+        arr[i] = it.c_struct(prec)
+    return arr
+
+
+def rsi_propagate_batched(insts: Sequence[Instance], prec: int) -> None:
+    """All instances in one persistent launch; results land in each instance's .out."""
+    arr = _instances(insts, prec)
+    L.check(L.load().rsi_propagate_batched(arr, len(insts), prec, _stream()), "rsi_propagate_batched")
+
+
+def rsi_autotune_batched(insts: Sequence[Instance], prec: int) -> None:
+    arr = _instances(insts, prec)
+    L.check(L.load().rsi_autotune_batched(arr, len(insts), prec), "rsi_autotune_batched")
+
+
+class Plan:
+    """A captured chain or batched launch (hipGraph), replayed by execute()."""
+
+    def __init__(self, handle: C.c_void_p, keep: list):
+        self._h = handle
+        self._keep = keep  # tensors whose addresses the graph binds
+
+    @classmethod
+    def chain(cls, xd: Transducer, ifaces: Sequence[Interface], media, tgt, freqs, tmode: int,
+              prec: int, out: Optional[torch.Tensor] = None) -> "Plan":
+        xs, arr, med, tp, fr = _chain_args(xd, ifaces, media, tgt, freqs)
+        if out is None:
+            out = torch.empty((len(freqs), tp.n), dtype=_OUT_DTYPE[prec], device=tgt[0].device)
+        h = C.c_void_p()
+        L.check(L.load().rsi_plan_create_chain(C.byref(h), C.byref(xs), arr, len(ifaces), med,
+                                               C.byref(tp), fr, len(freqs), tmode, prec, _ptr(out)),
+                "rsi_plan_create_chain")
+        plan = cls(h, [xd, list(ifaces), tgt])
+        plan.out = out
+        return plan
+
+    @classmethod
+    def batched(cls, insts: Sequence[Instance], prec: int) -> "Plan":
+        arr = _instances(insts, prec)
+        h = C.c_void_p()
+        L.check(L.load().rsi_plan_create_batched(C.byref(h), arr, len(insts), prec),
+                "rsi_plan_create_batched")
+        return cls(h, list(insts))
+
+    def execute(self) -> None:
+        L.check(L.load().rsi_plan_execute(self._h, _stream()), "rsi_plan_execute")
+
+    def destroy(self) -> None:
+        if self._h:
+            L.check(L.load().rsi_plan_destroy(self._h), "rsi_plan_destroy")
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------- a8
+def rsi_to_pressure(phi: torch.Tensor, rho: float, freq: float) -> torch.Tensor:
+    prec = RSI_FP32 if phi.dtype == torch.complex64 else RSI_FP64
+    _dev(phi, _OUT_DTYPE[prec], "phi")
+    p = torch.empty_like(phi)
+    L.check(L.load().rsi_to_pressure(phi.numel(), _ptr(phi), prec, rho, freq, _ptr(p), _stream()),
+            "rsi_to_pressure")
+    return p

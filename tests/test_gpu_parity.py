@@ -1,0 +1,251 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 reference.
+
+Tolerances: rel-L2 <= 1e-4 for the FP32 path and <= 1e-10 for the FP64 path (the
+FP64 path evaluates the same operations as the reference, in another order).  Integer
+work (Sobol digits) must match bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2408_06765_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-4, 1: 1e-10}
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def devpts(p):
+    return tuple(dev(np.asarray(v, dtype=np.float64)) for v in p)
+
+
+# ----------------------------------------------------------------------------- a1
+@pytest.mark.parametrize("seed,n,first", [(0, 1, 0), (0, 4096, 0), (12345, 1000, 0), (7, 777, 99991)])
+def test_sobol_bit_exact(gpu, orc, seed, n, first):
+    got = host(gpu.rsi_sobol2d(seed, n, first)).view(np.uint32)
+    assert np.array_equal(got, orc.sobol2d(seed, n, first))
+
+
+def test_sample_maps_match(gpu, orc):
+    tilt = math.radians(10.0)
+    g = [host(t) for t in gpu.rsi_sample_disc(0, 5000, W.PISTON_RADIUS, (0.001, 0.002, -0.003), tilt)]
+    o = orc.sample_disc(0, 5000, W.PISTON_RADIUS, (0.001, 0.002, -0.003), tilt)
+    for a, b in zip(g, o):
+        assert np.max(np.abs(a - b)) <= 1e-17 + 4e-16 * np.max(np.abs(b))
+    g = [host(t) for t in gpu.rsi_sample_square(1, 3001, 0.00882, 0.0, 0.05, 0.03)]
+    o = orc.sample_square(1, 3001, 0.00882, 0.0, 0.05, 0.03)
+    for a, b in zip(g, o):
+        assert np.max(np.abs(a - b)) <= 1e-17 + 4e-16 * np.max(np.abs(b))
+
+
+# ----------------------------------------------------------------------------- a2
+@pytest.mark.parametrize("tmode", [0, 1, 2])
+def test_transmission_matches(gpu, orc, tmode):
+    cfg = W.LayeredStack()
+    c = [m[0] for m in cfg.media]
+    rho = [m[1] for m in cfg.media]
+    xc, axis = (0.0, 0.0, 0.0), cfg.axis
+    qx, qy = W.random_cloud(5, 3000, (0.01, 0.0, 0.0), (0.03, 0.03, 0.0))[:2]
+    for m in (1, 2, 3):
+        got = host(gpu.rsi_transmission(tmode, m, cfg.z_if[:m], cfg.media[:m + 1], xc, axis, dev(qx), dev(qy)))
+        ref = orc.transmission(tmode, m, cfg.z_if[:m], c[:m + 1], rho[:m + 1], xc, axis, qx, qy)
+        assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+# ----------------------------------------------------------------------------- a3/a4
+SIZES = [(1, 1), (37, 5), (1000, 1237), (5000, 3001), (70001, 613)]
+
+
+def _case(seed, ns, nt, kind):
+    src = W.random_cloud(seed, ns, (0.0, 0.0, 0.0), (0.015, 0.015, 0.0 if kind == 1 else 0.002))
+    tgt = W.random_cloud(seed + 1, nt, (0.005, 0.0, 0.02), (0.02, 0.01, 0.015))
+    s = W.random_complex(seed + 2, ns)
+    w = W.random_weights(seed + 3, ns, 1e-4)
+    return src, w, s, tgt
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("ns,nt", SIZES)
+def test_propagate_matches_reference(gpu, orc, kind, prec, ns, nt):
+    src, w, s, tgt = _case(11 + ns, ns, nt, kind)
+    c, f = (1480.0, 5.0e6) if kind == 0 else (5900.0, 5.0e6)
+    ref = orc.propagate(kind, src, w, s, tgt, c, f, normal=(0.0, 0.0, 1.0))
+    got = host(gpu.rsi_propagate(devpts(src), dev(w), dev(s), devpts(tgt), c, f, kind, prec,
+                                 normal=(0.0, 0.0, 1.0)))
+    assert rel(got, ref) <= TOL[prec], (kind, prec, ns, nt, rel(got, ref))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_propagate_empty_sources_give_zero(gpu, prec):
+    import torch
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    tgt = devpts(W.random_cloud(1, 300, (0, 0, 0.02), (0.01, 0.01, 0.01)))
+    out = gpu.rsi_propagate((e, e, e), e, torch.empty(0, dtype=torch.complex128, device="cuda"), tgt,
+                            1480.0, 1e6, 0, prec)
+    assert np.all(host(out) == 0)
+
+
+def test_fp32_bitwise_repeatable(gpu):
+    src, w, s, tgt = _case(3, 70001, 2000, 1)
+    args = (devpts(src), dev(w), dev(s), devpts(tgt), 5900.0, 5e6, 1, 0)
+    a = host(gpu.rsi_propagate(*args, normal=(0, 0, 1)))
+    b = host(gpu.rsi_propagate(*args, normal=(0, 0, 1)))
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def test_high_frequency_phase_accuracy(gpu, orc):
+    """10 MHz in water over 0.1 m: k r ~ 4e3 rad; the FP32 path keeps 1e-4."""
+    src = W.random_cloud(21, 20000, (0.0, 0.0, 0.0), (0.03, 0.03, 0.0))
+    tgt = W.random_cloud(22, 500, (0.0, 0.0, 0.08), (0.02, 0.02, 0.02))
+    s = W.random_complex(23, 20000)
+    w = W.random_weights(24, 20000)
+    ref = orc.propagate(1, src, w, s, tgt, 1480.0, 10e6, normal=(0, 0, 1))
+    got = host(gpu.rsi_propagate(devpts(src), dev(w), dev(s), devpts(tgt), 1480.0, 10e6, 1, 0, normal=(0, 0, 1)))
+    assert rel(got, ref) <= 1e-4
+
+
+# ----------------------------------------------------------------------------- a5
+def _small_chain(orc, n_if_pts, ifaces_z, media, tilt, n_tgt, seed=0):
+    a = W.PISTON_RADIUS
+    xd = orc.sample_disc(seed, 4096, a, (0.0, 0.0, 0.0), tilt)
+    centres = W.snell_intercepts(0.0, tilt, list(ifaces_z), [m[0] for m in media])
+    ifs = [orc.sample_square(seed + 1 + m, n_if_pts, centres[m], 0.0, ifaces_z[m], 0.02)
+           for m in range(len(ifaces_z))]
+    tgt = W.random_cloud(seed + 9, n_tgt, (centres[-1] + 0.005, 0.0, ifaces_z[-1] + 0.012), (0.01, 0.004, 0.01))
+    return xd, ifs, tgt
+
+
+def _gpu_chain(gpu, xd, ifs, zs, media, tgt, freqs, tmode, prec, axis):
+    T = gpu.Transducer(*devpts(xd[:3]), dev(xd[3]), 1.0, (0.0, 0.0, 0.0), axis)
+    I = [gpu.Interface(*devpts(q[:3]), dev(q[3]), z) for q, z in zip(ifs, zs)]
+    return host(gpu.rsi_chain(T, I, media, devpts(tgt), freqs, tmode, prec))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("tmode", [0, 1, 2])
+def test_one_interface_chain(gpu, orc, prec, tmode):
+    tilt = math.radians(10.0)
+    axis = (math.sin(tilt), 0.0, math.cos(tilt))
+    media = (W.WATER, W.STEEL_5900)
+    xd, ifs, tgt = _small_chain(orc, 1 << 13, (0.05,), media, tilt, 1500)
+    freqs = [2.5e6]
+    ref = orc.chain(xd, 1.0, (0, 0, 0), axis, ifs, [0.05], [m[0] for m in media], [m[1] for m in media],
+                    tgt, freqs, tmode)
+    got = _gpu_chain(gpu, xd, ifs, [0.05], media, tgt, freqs, tmode, prec, axis)
+    assert rel(got, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_layered_chain_three_frequencies(gpu, orc, prec):
+    cfg = W.LayeredStack()
+    axis = cfg.axis
+    xd, ifs, tgt = _small_chain(orc, 1 << 12, cfg.z_if, cfg.media, cfg.tilt, 700)
+    freqs = [1.0e6, 5.5e6, 10.0e6]
+    ref = orc.chain(xd, 1.0, (0, 0, 0), axis, ifs, list(cfg.z_if), [m[0] for m in cfg.media],
+                    [m[1] for m in cfg.media], tgt, freqs, 1)
+    got = _gpu_chain(gpu, xd, ifs, cfg.z_if, cfg.media, tgt, freqs, 1, prec, axis)
+    for f in range(len(freqs)):
+        assert rel(got[f], ref[f]) <= TOL[prec], (f, rel(got[f], ref[f]))
+
+
+def test_piston_axis_workload(gpu, orc):
+    """The 1 MHz piston workload in full: GPU sampling + pair sum vs the reference's own
+    samples + sum, and vs the closed-form axis pressure."""
+    cfg = W.PistonAxis()
+    k = 2 * math.pi * cfg.freq / cfg.medium[0]
+    tgt = cfg.targets()
+    o = orc.sample_disc(cfg.seed, cfg.n_src, cfg.radius)
+    ref = orc.propagate(0, o[:3], o[3], 1.0, tgt, cfg.medium[0], cfg.freq)
+    g = gpu.rsi_sample_disc(cfg.seed, cfg.n_src, cfg.radius)
+    import torch
+    vel = torch.ones(cfg.n_src, dtype=torch.complex128, device="cuda")
+    pex = cfg.medium[1] * cfg.medium[0] * (np.exp(1j * k * tgt[2]) - np.exp(1j * k * np.sqrt(tgt[2] ** 2 + cfg.radius ** 2)))
+    for prec in (0, 1):
+        phi = gpu.rsi_propagate(g[:3], g[3], vel, devpts(tgt), cfg.medium[0], cfg.freq, 0, prec)
+        assert rel(host(phi), ref) <= TOL[prec]
+        p = host(gpu.rsi_to_pressure(phi, cfg.medium[1], cfg.freq))
+        assert rel(p, pex) < 5e-4
+
+
+# ----------------------------------------------------------------------------- a7
+def _instances(gpu, n_inst, prec, seed=0):
+    rng = np.random.default_rng(seed)
+    insts, refs = [], []
+    for i in range(n_inst):
+        ns = int(rng.integers(1, 9000)) if i % 5 else 0
+        nt = int(rng.integers(1, 3000))
+        kind = i % 2
+        src, w, s, tgt = _case(100 + i, max(ns, 1), nt, kind)
+        src = tuple(v[:ns] for v in src)
+        w, s = w[:ns], s[:ns]
+        c = 1480.0 if kind == 0 else 5900.0
+        f = 1e6 * (1 + i % 7)
+        insts.append(gpu.Instance(devpts(src), dev(w), devpts(tgt), c, f, kind, vel=dev(s),
+                                  normal=(0.0, 0.0, 1.0)))
+        refs.append((kind, src, w, s, tgt, c, f))
+    return insts, refs
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_matches_reference(gpu, orc, prec):
+    insts, refs = _instances(gpu, 23, prec)
+    gpu.rsi_propagate_batched(insts, prec)
+    for it, (kind, src, w, s, tgt, c, f) in zip(insts, refs):
+        ref = orc.propagate(kind, src, w, s, tgt, c, f, normal=(0, 0, 1))
+        got = host(it.out)
+        if len(src[0]) == 0:
+            assert np.all(got == 0)
+        else:
+            assert rel(got, ref) <= TOL[prec]
+
+
+def test_batched_plan_replay_bitwise(gpu):
+    import torch
+    insts, _ = _instances(gpu, 17, 0, seed=3)
+    gpu.rsi_propagate_batched(insts, 0)
+    eager = [host(i.out).copy() for i in insts]
+    plan = gpu.Plan.batched(insts, 0)
+    for rep in range(3):
+        for i in insts:
+            i.out.zero_()
+        plan.execute()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+        for i, e in zip(insts, eager):
+            assert np.array_equal(host(i.out).view(np.uint64), e.view(np.uint64))
+    plan.destroy()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_chain_plan_replay(gpu, orc, prec):
+    import torch
+    cfg = W.LayeredStack()
+    xd, ifs, tgt = _small_chain(orc, 1 << 11, cfg.z_if[:2], cfg.media[:3], cfg.tilt, 400)
+    T = gpu.Transducer(*devpts(xd[:3]), dev(xd[3]), 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    I = [gpu.Interface(*devpts(q[:3]), dev(q[3]), z) for q, z in zip(ifs, cfg.z_if[:2])]
+    tg = devpts(tgt)
+    freqs = [2e6, 3e6]
+    eager = host(gpu.rsi_chain(T, I, cfg.media[:3], tg, freqs, 1, prec))
+    plan = gpu.Plan.chain(T, I, cfg.media[:3], tg, freqs, 1, prec)
+    for rep in range(3):
+        plan.out.zero_()
+        plan.execute()
+        torch.cuda.synchronize()
+        _ = torch.randn(100, device="cuda").sum().item()
+        assert np.array_equal(host(plan.out).view(np.uint64), eager.view(np.uint64))
+    plan.destroy()

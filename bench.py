@@ -1,0 +1,205 @@
+"""Benchmark of the RSI-QMC hot path on one MI355X.
+
+A step is one pass of the whole chained model over the one-interface workload:
+  piston (2^16 Sobol samples, 5 MHz, tilted 10 deg) -> water/solid interface at 50 mm
+  (2^18 samples on a 60 x 60 mm patch, local transmission coefficient) -> 512 x 512
+  image 1-40 mm below the interface, FP32 path (FP64 reference distance and phase).
+  Pairs per step: 2^16 * 2^18 (piston, monopole) + 2^18 * 512^2 (interface, dipole)
+  = 8.59e10.  Inputs (sample points, weights, field points) are resident in HBM
+  before the timed region; the step is one replay of the chain plan (hipGraph).
+
+Printed: one JSON line with Gpairs/s, the roofline of the dominant kernel (the
+interface dipole pair sum, timed with HIP events on its own stream) and the FP64
+reference timed on the host cores over a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic FP32 flops per pair (FMA = 2, transcendental = 1); see the design notes
+FLOPS_MONOPOLE = 25
+FLOPS_DIPOLE = 33
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 2.4 GHz x 256 flop/CU/clk)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
+    ap.add_argument("--kernel-reps", type=int, default=5, help="launches for the roofline timing")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, target_seconds=4.0):
+    """The FP64 reference, as it stands, on a bounded sample of the same workload:
+    the piston stage onto a subset of interface points and the interface stage (all
+    2^18 sources, unit strengths) onto a subset of image points."""
+    import oracle
+
+    xd = oracle.sample_disc(cfg.xd_seed, cfg.n_xd, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt)
+    cx, cy = cfg.patch_centre
+    q = oracle.sample_square(cfg.if_seed, cfg.n_if, cx, cy, cfg.z_if, cfg.half_width)
+    tx, ty, tz = cfg.targets()
+    (c0, _), (c1, _) = cfg.media
+    # calibrate on a small sample, then size the sample for ~target_seconds
+    def run(m_if, m_img):
+        t0 = time.perf_counter()
+        oracle.propagate(0, xd[:3], xd[3], 1.0, tuple(a[:m_if] for a in q[:3]), c0, cfg.freq)
+        oracle.propagate(1, q[:3], q[3], 1.0, (tx[:m_img], ty[:m_img], tz[:m_img]), c1, cfg.freq,
+                         normal=(0.0, 0.0, 1.0))
+        return time.perf_counter() - t0, cfg.n_xd * m_if + cfg.n_if * m_img
+    dt, pairs = run(64, 64)
+    rate = pairs / max(dt, 1e-9)
+    # keep the workload's mix: interface points and image points in proportion 1 : 1
+    m = int(max(64, min(cfg.n_if, target_seconds * rate / (cfg.n_xd + cfg.n_if))))
+    dt, pairs = run(m, m)
+    return {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"piston stage onto {m} interface points + interface stage (2^18 sources) onto "
+                      f"{m} image points: {pairs:.3e} pairs in {dt:.2f} s"}
+
+
+KERNEL_SOURCES = ["paper_2408_06765_amd/csrc/rsi_device.h",
+                  "paper_2408_06765_amd/csrc/rsi_pairsum.hip",
+                  "paper_2408_06765_amd/csrc/rsi_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairsum_dipole_one_interface_traffic.txt")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if kv.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2408_06765_amd import rsi
+    from paper_2408_06765_amd import workloads as W
+
+    cfg = W.OneInterface()
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    cx, cy = cfg.patch_centre
+    # inputs: generated on the device by the library's own sampler, resident in HBM
+    xs = rsi.rsi_sample_disc(cfg.xd_seed, cfg.n_xd, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt)
+    qs = rsi.rsi_sample_square(cfg.if_seed, cfg.n_if, cx, cy, cfg.z_if, cfg.half_width)
+    tgt = tuple(dev(a) for a in cfg.targets())
+    T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    I = [rsi.Interface(*qs[:3], qs[3], cfg.z_if)]
+    freqs = [cfg.freq]
+    plan = rsi.Plan.chain(T, I, cfg.media, tgt, freqs, rsi.RSI_T_LOCAL, rsi.RSI_FP32)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        plan.execute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.execute()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / max(args.steps, 1)
+    pairs_stage0 = cfg.n_xd * cfg.n_if
+    pairs_stage1 = cfg.n_if * cfg.nx * cfg.nz
+    pairs = pairs_stage0 + pairs_stage1
+    value = pairs * args.steps / dt / 1e9
+
+    # dominant kernel: the interface (dipole) pair sum, one call per launch, timed with
+    # HIP events on the stream it runs on
+    s = torch.cuda.Stream()
+    vel = torch.ones(cfg.n_if, dtype=torch.complex128, device="cuda")
+    out = torch.empty(cfg.nx * cfg.nz, dtype=torch.complex64, device="cuda")
+    with torch.cuda.stream(s):
+        rsi.rsi_propagate(qs[:3], qs[3], vel, tgt, cfg.media[1][0], cfg.freq, rsi.RSI_DIPOLE,
+                          rsi.RSI_FP32, normal=(0.0, 0.0, 1.0), out=out)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.kernel_reps)]
+        for e0, e1 in ev:
+            e0.record(s)
+            rsi.rsi_propagate(qs[:3], qs[3], vel, tgt, cfg.media[1][0], cfg.freq, rsi.RSI_DIPOLE,
+                              rsi.RSI_FP32, normal=(0.0, 0.0, 1.0), out=out)
+            e1.record(s)
+    s.synchronize()
+    kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    achieved = FLOPS_DIPOLE * pairs_stage1 / (kms * 1e-3) / 1e12
+
+    # sanity of the timed output against stored reference samples, when present
+    check = None
+    gold = os.path.join(ROOT, "tests", "golden", "one_interface_samples.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        idx = np.array(g["index"])
+        ref = np.array(g["re"]) + 1j * np.array(g["im"])
+        got = plan.out[0].cpu().numpy()[idx]
+        check = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+    line = {
+        "metric": "Gpairs/s RSI-QMC (chained pair sum) + % FP32 VALU peak",
+        "value": round(value, 3),
+        "unit": "Gpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "one_interface: piston 2^16 -> interface 2^18 -> image 512x512, "
+                               "5 MHz, water->5900 m/s solid, tilt 10 deg, local T",
+                   "pairs_per_step": pairs, "precision": "fp32 (fp64 reference distance + phase)"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": measured_traffic(),
+                     "kernel": "pairsum_f32_kernel<dipole> (interface -> image), "
+                               f"{FLOPS_DIPOLE} flop/pair x {pairs_stage1:.3e} pairs / {kms:.3f} ms"},
+    }
+    if check is not None:
+        line["parity_vs_oracle_samples"] = check
+    if args.calib_copy:
+        # plain copy of known size: 256 MiB read + 256 MiB written, for scaling counters
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        line["calib_copy_bytes"] = a.numel() * 4
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(line), flush=True)
+    plan.destroy()
+
+
+if __name__ == "__main__":
+    main()

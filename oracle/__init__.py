@@ -54,6 +54,7 @@ def _load():
                               C.c_int, _dp, C.c_int, _dp]
     lib.orc_to_pressure.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _dp]
     lib.orc_to_pressure.restype = None
+    lib.orc_num_threads.restype = C.c_int
     _lib = lib
     return lib
 
@@ -216,3 +217,8 @@ def to_pressure(phi, rho: float, freq: float) -> np.ndarray:
     out = np.zeros(2 * n)
     lib.orc_to_pressure(n, src.ctypes.data_as(_dp), rho, freq, out.ctypes.data_as(_dp))
     return _cplx_out(out).reshape(phi.shape)
+
+
+def num_threads() -> int:
+    """OpenMP threads the reference uses."""
+    return int(_load().orc_num_threads())

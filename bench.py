@@ -40,6 +40,14 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=5, help="launches for the roofline timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--workload", default="one_interface",
+                    choices=["one_interface", "layered_stack", "scan_batch"],
+                    help="one_interface is the benchmark line; the others are secondary "
+                         "measurements printed in the same format")
+    ap.add_argument("--autotune", action="store_true",
+                    help="scan_batch: run the autotuner (writes the cache) before planning")
+    ap.add_argument("--fp64-compare", action="store_true",
+                    help="layered_stack: FP32 vs FP64 rel-L2 per frequency on a volume subsample")
     return ap.parse_args()
 
 
@@ -98,12 +106,110 @@ def measured_traffic():
     return int(float(kv["traffic_bytes_per_launch"]))
 
 
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def base_line(metric_value, steps, warmup, dt, config, unit="Gpairs/s"):
+    return {
+        "metric": "Gpairs/s RSI-QMC (chained pair sum) + % FP32 VALU peak",
+        "value": round(metric_value, 3), "unit": unit, "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(1e3 * dt / max(steps, 1), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": config,
+    }
+
+
+def layered_stack(args):
+    """Three interfaces, 64 frequencies (one multi-frequency launch per stage), 128^3."""
+    import torch
+    from paper_2408_06765_amd import rsi
+    from paper_2408_06765_amd import workloads as W
+
+    cfg = W.LayeredStack()
+    xs = rsi.rsi_sample_disc(cfg.xd_seed, cfg.n_xd, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt)
+    ifs = []
+    for seed, (cx, cy), z in zip(cfg.if_seeds, cfg.patch_centres, cfg.z_if):
+        q = rsi.rsi_sample_square(seed, cfg.n_if, cx, cy, z, cfg.half_width)
+        ifs.append(rsi.Interface(*q[:3], q[3], z))
+    tgt = tuple(torch.as_tensor(a, device="cuda") for a in cfg.targets())
+    T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    freqs = list(cfg.freqs)
+    plan = rsi.Plan.chain(T, ifs, cfg.media, tgt, freqs, rsi.RSI_T_LOCAL, rsi.RSI_FP32)
+    steps = max(1, min(args.steps, 3))
+    dt = timed(plan.execute, steps, min(args.warmup, 1))
+    n_t = tgt[0].numel()
+    pairs = len(freqs) * (cfg.n_xd * cfg.n_if + 2 * cfg.n_if * cfg.n_if + cfg.n_if * n_t)
+    line = base_line(pairs * steps / dt / 1e9, steps, min(args.warmup, 1), dt,
+                     {"workload": "layered_stack: piston 2^16 -> 3 interfaces x 2^18 -> 128^3 volume, "
+                                  "64 frequencies 1-10 MHz, local T", "pair_frequencies_per_step": pairs})
+    if args.fp64_compare:
+        # FP64 chain per frequency on every 64th volume point; FP32 from the timed plan
+        sub = torch.arange(0, n_t, 64, device="cuda")
+        tsub = tuple(a[sub].contiguous() for a in tgt)
+        f32 = plan.out[:, sub].cpu().numpy()
+        errs = []
+        for qi, f in enumerate(freqs):
+            ref = rsi.rsi_chain(T, ifs, cfg.media, tsub, [f], rsi.RSI_T_LOCAL, rsi.RSI_FP64)[0].cpu().numpy()
+            errs.append(float(np.linalg.norm(f32[qi] - ref) / np.linalg.norm(ref)))
+            print(f"freq {f/1e6:.4f} MHz  fp32 vs fp64 rel-L2 {errs[-1]:.3e}", file=sys.stderr, flush=True)
+        line["fp32_vs_fp64_rel_l2_per_frequency"] = errs
+    gold = os.path.join(ROOT, "tests", "golden", "layered_stack_samples.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        idx = np.array(g["index"])
+        ref = np.array(g["re"]) + 1j * np.array(g["im"])
+        got = plan.out[g["freq_index"]].cpu().numpy()[:, idx]
+        line["parity_vs_oracle_samples"] = [float(np.linalg.norm(a - b) / np.linalg.norm(b))
+                                            for a, b in zip(got, ref)]
+    print(json.dumps(line), flush=True)
+    plan.destroy()
+
+
+def scan_batch(args):
+    """256 uneven scan positions in one persistent launch (batched plan)."""
+    import torch
+    from paper_2408_06765_amd import rsi
+    from paper_2408_06765_amd import workloads as W
+
+    cfg = W.ScanBatch()
+    insts = []
+    for it in cfg.instances():
+        xs = rsi.rsi_sample_disc(it.seed, it.n_src, cfg.radius, (it.x_offset, 0.0, 0.0), it.tilt)
+        tgt = tuple(torch.as_tensor(a, device="cuda") for a in cfg.field_points(it))
+        insts.append(rsi.Instance(xs[:3], xs[3], tgt, cfg.medium[0], cfg.freq, rsi.RSI_MONOPOLE))
+    if args.autotune:
+        rsi.rsi_autotune_batched(insts, rsi.RSI_FP32)
+    plan = rsi.Plan.batched(insts, rsi.RSI_FP32)
+    dt = timed(plan.execute, args.steps, args.warmup)
+    pairs = sum(i.w.numel() * i.tgt[0].numel() for i in insts)
+    line = base_line(pairs * args.steps / dt / 1e9, args.steps, args.warmup, dt,
+                     {"workload": "scan_batch: 256 piston scan positions, 2^12-2^18 sources, "
+                                  "1e3-1e5 field points, 1 MHz water, one persistent launch",
+                      "pairs_per_step": pairs})
+    print(json.dumps(line), flush=True)
+    plan.destroy()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
+
+    if args.workload == "layered_stack":
+        return layered_stack(args)
+    if args.workload == "scan_batch":
+        return scan_batch(args)
 
     from paper_2408_06765_amd import rsi
     from paper_2408_06765_amd import workloads as W
@@ -141,14 +247,15 @@ def main():
     vel = torch.ones(cfg.n_if, dtype=torch.complex128, device="cuda")
     out = torch.empty(cfg.nx * cfg.nz, dtype=torch.complex64, device="cuda")
     with torch.cuda.stream(s):
-        rsi.rsi_propagate(qs[:3], qs[3], vel, tgt, cfg.media[1][0], cfg.freq, rsi.RSI_DIPOLE,
-                          rsi.RSI_FP32, normal=(0.0, 0.0, 1.0), out=out)
+        rsi.rsi_propagate_ex(qs[:3], qs[3], vel, tgt, cfg.media[1][0], cfg.freq, rsi.RSI_DIPOLE,
+                             rsi.RSI_FP32, rsi.RSI_FLAG_PLANAR_Z, normal=(0.0, 0.0, 1.0), out=out)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.kernel_reps)]
         for e0, e1 in ev:
             e0.record(s)
-            rsi.rsi_propagate(qs[:3], qs[3], vel, tgt, cfg.media[1][0], cfg.freq, rsi.RSI_DIPOLE,
-                              rsi.RSI_FP32, normal=(0.0, 0.0, 1.0), out=out)
+            rsi.rsi_propagate_ex(qs[:3], qs[3], vel, tgt, cfg.media[1][0], cfg.freq,
+                                 rsi.RSI_DIPOLE, rsi.RSI_FP32, rsi.RSI_FLAG_PLANAR_Z,
+                                 normal=(0.0, 0.0, 1.0), out=out)
             e1.record(s)
     s.synchronize()
     kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
@@ -183,7 +290,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": measured_traffic(),
-                     "kernel": "pairsum_f32_kernel<dipole> (interface -> image), "
+                     "kernel": "pairsum_f32_kernel<dipole, planar> (interface -> image), "
                                f"{FLOPS_DIPOLE} flop/pair x {pairs_stage1:.3e} pairs / {kms:.3f} ms"},
     }
     if check is not None:

@@ -170,6 +170,22 @@ rsi_status rsi_propagate(const rsi_points *src, const double *src_w, const doubl
                          double freq, rsi_kernel kind, rsi_precision prec, void *out,
                          void *stream);
 
+/* Flags of rsi_propagate_ex. */
+enum {
+    /* Every source has the same z (a horizontal interface patch).  The FP32 kernel then
+     * drops the z terms of each pair; for RSI_DIPOLE the normal must be +-z.  Results
+     * are unspecified if the sources do not share one z. */
+    RSI_FLAG_PLANAR_Z = 1u
+};
+
+/* rsi_propagate with flags (a bitwise OR of RSI_FLAG_*; 0 is rsi_propagate).
+ * RSI_ERR_ARG for unknown flags, or RSI_FLAG_PLANAR_Z with a dipole normal not
+ * parallel to z.  FP64 ignores RSI_FLAG_PLANAR_Z (it evaluates every term). */
+rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_w, const double *src_vel,
+                            const double *normal, const rsi_points *tgt, rsi_medium medium,
+                            double freq, rsi_kernel kind, rsi_precision prec, uint32_t flags,
+                            void *out, void *stream);
+
 /* ------------------------------------------------------------------------------
  * a5. The chain (Sec. 2.1 repeated per interface, Sec. 3.4-3.5).
  * ------------------------------------------------------------------------------ */

@@ -161,7 +161,7 @@ __device__ __forceinline__ void run_item_f32(const InstDev &I, const WorkItem &w
     setup_targets_f32<KIND, TPL>(T, I.tx, I.ty, I.tz, I.n_tgt, tbase, I.anchor[0], I.anchor[1],
                                  I.anchor[2], I.inv_lam, I.nx, I.ny, I.nz);
     float mre[TPL], mim[TPL];
-    sum_range_f32<KIND, TPL>(T, I.recf, w.j0, w.j1, (float)I.inv_lam, (float)I.k, mre, mim);
+    sum_range_f32<KIND, TPL, false>(T, I.recf, w.j0, w.j1, (float)I.inv_lam, (float)I.k, mre, mim);
     float2 *o = I.n_chunks > 1 ? static_cast<float2 *>(I.partial) + (int64_t)w.chunk * I.n_tgt
                                : static_cast<float2 *>(I.out);
 #pragma unroll
@@ -622,7 +622,7 @@ rsi_status rsi_plan_create_chain(rsi_plan **plan, const rsi_transducer *xd,
         *ptr = p->bufs.back()->as<void>();
         return RSI_OK;
     };
-    RSI_TRY(alloc_chain(alloc, xd, ifaces, n_if, tgt, prec, p->W));
+    RSI_TRY(alloc_chain(alloc, xd, ifaces, n_if, tgt, freqs, n_freq, prec, p->W));
     // copies of the host descriptors: the captured graph keeps only device pointers and
     // kernel arguments, so nothing here needs to outlive the call
     if (tgt->n > 0 && n_freq > 0) {

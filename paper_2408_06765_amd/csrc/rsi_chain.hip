@@ -2,8 +2,9 @@
 // transducer -> interface 1 -> ... -> field (Sec. 2.1 applied once per interface), and
 // the pressure conversion.
 #include <cmath>
+#include <cstdlib>
 
-#include "rsi_internal.h"
+#include "rsi_device.h"
 
 namespace rsi {
 
@@ -181,7 +182,13 @@ rsi_status validate_chain(const rsi_transducer *xd, const rsi_interface *ifaces,
 }
 
 rsi_status alloc_chain(const AllocFn &alloc, const rsi_transducer *xd, const rsi_interface *ifaces,
-                              int n_if, const rsi_points *tgt, rsi_precision prec, ChainWork &W) {
+                       int n_if, const rsi_points *tgt, const double *freqs, int n_freq,
+                       rsi_precision prec, ChainWork &W) {
+    static const bool mf_enabled = [] {
+        const char *v = std::getenv("RSI_MULTIFREQ");  // "0" disables the batched stages
+        return !(v && v[0] == '0');
+    }();
+    W.multifreq = mf_enabled && prec == RSI_FP32 && uniform_grid(freqs, n_freq, W.f0, W.df);
     W.tco.assign(n_if, nullptr);
     W.bbox.assign(n_if + 1, nullptr);
     W.setf.assign(n_if + 1, SrcSetF{});
@@ -205,8 +212,15 @@ rsi_status alloc_chain(const AllocFn &alloc, const rsi_transducer *xd, const rsi
     for (int m = 0; m < n_if; ++m)
         RSI_TRY(alloc((void **)&W.tco[m], sizeof(double) * 2 * (size_t)(ifaces[m].pts.n > 0 ? ifaces[m].pts.n : 1)));
     const size_t esz = prec == RSI_FP32 ? sizeof(float2) : sizeof(double2);
-    RSI_TRY(alloc(&W.field[0], esz * (size_t)nmax));
-    RSI_TRY(alloc(&W.field[1], esz * (size_t)nmax));
+    const size_t nf = W.multifreq ? (size_t)n_freq : 1;
+    RSI_TRY(alloc(&W.field[0], esz * (size_t)nmax * nf));
+    RSI_TRY(alloc(&W.field[1], esz * (size_t)nmax * nf));
+    if (W.multifreq) {
+        const size_t nf_pad = (size_t)(n_freq + kFB - 1) / kFB * kFB;
+        RSI_TRY(alloc((void **)&W.S, sizeof(float2) * (size_t)nmax * nf_pad));
+        W.partial = nullptr;  // the multi-frequency stages write their outputs directly
+        return RSI_OK;
+    }
     RSI_TRY(alloc(&W.partial, esz * (size_t)(nslot > 0 ? nslot : 1)));
     return RSI_OK;
 }
@@ -239,6 +253,28 @@ rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, 
         RSI_TRY(transmission_device(tmode, m, zif.data(), media, xd->centre, xd->axis,
                                     ifaces[m - 1].pts.n, ifaces[m - 1].pts.x, ifaces[m - 1].pts.y,
                                     W.tco[m - 1], s));
+    if (W.multifreq) {
+        // every stage once for all frequencies; fields are [n_freq][n]
+        int cur = 0;
+        for (int m = 0; m <= n_if; ++m) {
+            const rsi_points &tp = (m == n_if) ? *tgt : ifaces[m].pts;
+            const Targets t{tp.x, tp.y, tp.z, tp.n};
+            float2 *dst = (m == n_if) ? static_cast<float2 *>(out)
+                                      : static_cast<float2 *>(W.field[m == 0 ? 0 : cur ^ 1]);
+            if (m == 0) {
+                RSI_TRY(pairsum_multifreq_f32(W.setf[0], nullptr, t, RSI_MONOPOLE, false, media[0].c,
+                                              W.f0, W.df, n_freq, dst, s));
+            } else {
+                RSI_TRY(strength_multifreq(W.setf[m].n, n_freq, ifaces[m - 1].w,
+                                           static_cast<const float2 *>(W.field[cur]), W.tco[m - 1],
+                                           W.S, s));
+                RSI_TRY(pairsum_multifreq_f32(W.setf[m], W.S, t, RSI_DIPOLE, true, media[m].c,
+                                              W.f0, W.df, n_freq, dst, s));
+                cur ^= 1;
+            }
+        }
+        return RSI_OK;
+    }
     const size_t esz = prec == RSI_FP32 ? sizeof(float2) : sizeof(double2);
     for (int f = 0; f < n_freq; ++f) {
         char *out_f = static_cast<char *>(out) + esz * (size_t)f * (size_t)tgt->n;
@@ -255,8 +291,10 @@ rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, 
                 if (m > 0)
                     RSI_TRY(set_strength_f32(W.setf[m], ifaces[m - 1].w, W.field[cur], false,
                                              W.tco[m - 1], s));
+                // interface samples lie on their plane (ABI contract): planar kernel
                 RSI_TRY(pairsum_f32(W.setf[m], t, kind, m == 0 ? nullptr : nz, media[m].c, freqs[f],
-                                    sh, static_cast<float2 *>(W.partial), static_cast<float2 *>(dst), s));
+                                    sh, static_cast<float2 *>(W.partial), static_cast<float2 *>(dst), s,
+                                    m > 0));
             } else {
                 if (m > 0)
                     RSI_TRY(set_strength_f64(W.setd[m], ifaces[m - 1].w,
@@ -310,7 +348,7 @@ rsi_status rsi_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int 
     Scratch scratch(s);
     ChainWork W;
     RSI_TRY(alloc_chain([&](void **p, size_t bytes) { return scratch.alloc((char **)p, bytes); },
-                        xd, ifaces, n_if, tgt, prec, W));
+                        xd, ifaces, n_if, tgt, freqs, n_freq, prec, W));
     return enqueue_chain(xd, ifaces, n_if, media, tgt, freqs, n_freq, tmode, prec, out, W, s);
 }
 

@@ -11,6 +11,7 @@
 namespace rsi {
 
 constexpr int kSub = 64;  // sources per FP32 partial block before the compensated fold
+constexpr int kFB = 8;    // frequencies per block of the multi-frequency kernel
 
 // Per-target constants of the FP32 path (see rsi_pairsum.hip for the derivation).
 template <int KIND, int TPL>
@@ -47,8 +48,10 @@ __device__ __forceinline__ void setup_targets_f32(TargetsF<KIND, TPL> &T, const 
     }
 }
 
-// One source against the lane's TPL targets.  `s` is wave-uniform (SGPRs).
-template <int KIND, int TPL>
+// One source against the lane's TPL targets.  `s` is wave-uniform (SGPRs).  PLANAR:
+// every source lies in the plane z = C_z with normal +z (interface samples), so
+// e_z = 0 and n.e_j = 0, and the z terms drop out.
+template <int KIND, int TPL, bool PLANAR>
 __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const SrcRecF &s,
                                          float ilam, float k, float (&are)[TPL],
                                          float (&aim)[TPL]) {
@@ -56,7 +59,7 @@ __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const Src
     for (int u = 0; u < TPL; ++u) {
         float t = T.dmx[u] * s.ex;
         t = fmaf(T.dmy[u], s.ey, t);
-        t = fmaf(T.dmz[u], s.ez, t);
+        if constexpr (!PLANAR) t = fmaf(T.dmz[u], s.ez, t);
         const float q = t + s.es2;                           // r^2 - r_ref^2
         const float r2 = fmaxf(T.rr2[u] + q, kR2MinF);
         const float ir = __builtin_amdgcn_rsqf(r2);           // 1/r
@@ -70,7 +73,8 @@ __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const Src
             gr = cs * ir;  // e^{ikr}/r
             gi = sn * ir;
         } else {
-            const float g2 = (T.ht[u] - s.h) * ir * ir;  // cos(theta)/r
+            const float hh = PLANAR ? T.ht[u] : T.ht[u] - s.h;  // n.(P - Q)
+            const float g2 = hh * ir * ir;                      // cos(theta)/r
             const float al = -g2 * ir, be = g2 * k;      // cos(theta)(ik - 1/r)/r
             gr = al * cs - be * sn;
             gi = fmaf(al, sn, be * cs);
@@ -84,7 +88,7 @@ __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const Src
 
 // Sum of sources [j0, j1): FP32 blocks of kSub sources folded into a Kahan-compensated
 // running sum (mre, mim with compensation cre, cim).
-template <int KIND, int TPL>
+template <int KIND, int TPL, bool PLANAR>
 __device__ __forceinline__ void sum_range_f32(const TargetsF<KIND, TPL> &T,
                                               const SrcRecF *__restrict__ rec, int64_t j0,
                                               int64_t j1, float ilam, float k,
@@ -99,9 +103,9 @@ __device__ __forceinline__ void sum_range_f32(const TargetsF<KIND, TPL> &T,
         for (int u = 0; u < TPL; ++u) are[u] = aim[u] = 0.0f;
         if (je - jb == kSub) {
 #pragma unroll 4
-            for (int jj = 0; jj < kSub; ++jj) pair_f32<KIND, TPL>(T, rec[jb + jj], ilam, k, are, aim);
+            for (int jj = 0; jj < kSub; ++jj) pair_f32<KIND, TPL, PLANAR>(T, rec[jb + jj], ilam, k, are, aim);
         } else {
-            for (int64_t j = jb; j < je; ++j) pair_f32<KIND, TPL>(T, rec[j], ilam, k, are, aim);
+            for (int64_t j = jb; j < je; ++j) pair_f32<KIND, TPL, PLANAR>(T, rec[j], ilam, k, are, aim);
         }
 #pragma unroll
         for (int u = 0; u < TPL; ++u) {

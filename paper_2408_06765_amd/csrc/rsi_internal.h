@@ -156,12 +156,25 @@ rsi_status set_strength_f64(SrcSetD &set, const double *w, const double *field,
                             const double *tco, hipStream_t s);
 PairShape default_shape(int64_t n_src, int64_t n_tgt);
 int64_t partial_slots(const PairShape &sh, int64_t n_src, int64_t n_tgt);
+// planar_z: every source lies on the plane z = const through the set's anchor (normal
+// +z); the kernel then drops the z terms (interface samples, by the ABI contract).
 rsi_status pairsum_f32(const SrcSetF &set, const Targets &t, rsi_kernel kind,
                        const double *normal, double c, double freq, const PairShape &sh,
-                       float2 *partial, float2 *out, hipStream_t s);
+                       float2 *partial, float2 *out, hipStream_t s, bool planar_z = false);
 rsi_status pairsum_f64(const SrcSetD &set, const Targets &t, rsi_kernel kind,
                        const double *normal, double c, double freq, const PairShape &sh,
                        double2 *partial, double2 *out, hipStream_t s);
+
+// --- rsi_multifreq.hip -------------------------------------------------------
+// True when freqs[0..n) is a uniform grid f0 + q df (n >= 2, df > 0).
+bool uniform_grid(const double *freqs, int n, double &f0, double &df);
+// S [n][n_freq rounded up to the frequency block] of -(1/2pi) w T phi from field [n_freq][n].
+rsi_status strength_multifreq(int64_t n, int n_freq, const double *w, const float2 *field,
+                              const double *tco, float2 *S, hipStream_t s);
+// One stage for all frequencies; S == nullptr: the record strengths serve every frequency.
+rsi_status pairsum_multifreq_f32(const SrcSetF &set, const float2 *S, const Targets &t,
+                                 rsi_kernel kind, bool planar_z, double c, double f0, double df,
+                                 int n_freq, float2 *out, hipStream_t s);
 
 // --- rsi_chain.hip -----------------------------------------------------------
 // Workspace of a chain: shared by the one-shot call and the chain plan.
@@ -172,6 +185,9 @@ struct ChainWork {
     std::vector<SrcSetD> setd;
     void *field[2] = {nullptr, nullptr};
     void *partial = nullptr;
+    float2 *S = nullptr;      // multi-frequency strengths
+    bool multifreq = false;   // FP32 on a uniform frequency grid: one launch per stage
+    double f0 = 0.0, df = 0.0;
 };
 using AllocFn = std::function<rsi_status(void **, size_t)>;
 rsi_status validate_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
@@ -179,7 +195,7 @@ rsi_status validate_chain(const rsi_transducer *xd, const rsi_interface *ifaces,
                           int n_freq, rsi_tmode tmode, rsi_precision prec, void *out);
 rsi_status alloc_chain(const AllocFn &alloc, const rsi_transducer *xd,
                        const rsi_interface *ifaces, int n_if, const rsi_points *tgt,
-                       rsi_precision prec, ChainWork &W);
+                       const double *freqs, int n_freq, rsi_precision prec, ChainWork &W);
 rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
                          const rsi_medium *media, const rsi_points *tgt, const double *freqs,
                          int n_freq, rsi_tmode tmode, rsi_precision prec, void *out,

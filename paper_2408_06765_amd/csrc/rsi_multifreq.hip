@@ -1,0 +1,187 @@
+// rsi_multifreq.hip -- one stage of the chain for many frequencies in one launch
+// (multi-frequency superposition, Sec. 4), FP32 path.
+//
+// On a uniform grid f_q = f_0 + q df the phase of a pair is linear in q:
+//     r f_q / c = r f_b / c + (q - q_b) r df / c,
+// so e^{i k_q r} advances by the same unit phasor e^{i dk r} from one frequency to the
+// next.  The geometry of a pair (q, 1/r, r - r_ref) and two phasors (block start and
+// step) are evaluated once per block of kFB frequencies; each further frequency costs a
+// complex rotation and the complex multiply-accumulate with that frequency's strength.
+// The strengths of one source for a frequency block are contiguous (source-major,
+// frequency-minor), so a wave reads them with one wave-uniform load.
+#include <cmath>
+
+#include "rsi_device.h"
+
+namespace rsi {
+
+template <int KIND, bool PLANAR, bool SHARED_S>
+__global__ void __launch_bounds__(kBlock) multifreq_f32_kernel(
+    const SrcRecF *__restrict__ rec, const float2 *__restrict__ S, int64_t n_src, int nf_pad,
+    const double *__restrict__ tx, const double *__restrict__ ty, const double *__restrict__ tz,
+    int64_t n_tgt, const double *__restrict__ anchor, double f0, double df, int n_freq,
+    double inv_c, float2 *__restrict__ out) {
+    const int q0 = blockIdx.y * kFB;
+    const double fb = f0 + q0 * df;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < n_tgt;
+    if (!valid) i = n_tgt - 1;
+    // per target, in FP64: reference distance and the two reference phases
+    const double dx = tx[i] - anchor[0], dy = ty[i] - anchor[1], dz = tz[i] - anchor[2];
+    const double rr2d = dx * dx + dy * dy + dz * dz, rrd = sqrt(rr2d);
+    double pb = rrd * fb * inv_c, pd = rrd * df * inv_c;
+    pb -= floor(pb);
+    pd -= floor(pd);
+    const float dmx = (float)(-2.0 * dx), dmy = (float)(-2.0 * dy), dmz = (float)(-2.0 * dz);
+    const float rr2 = (float)rr2d, rr = (float)rrd, p0b = (float)pb, p0d = (float)pd;
+    const float ht = (float)dz;  // n = +z for the interface (dipole) stages
+    const float ilb = (float)(fb * inv_c), ild = (float)(df * inv_c);
+    float kq[kFB];
+#pragma unroll
+    for (int q = 0; q < kFB; ++q) kq[q] = (float)(kTwoPi * (fb + q * df) * inv_c);
+
+    float mre[kFB], mim[kFB], cre[kFB], cim[kFB];
+#pragma unroll
+    for (int q = 0; q < kFB; ++q) mre[q] = mim[q] = cre[q] = cim[q] = 0.0f;
+    for (int64_t jb = 0; jb < n_src; jb += kSub) {
+        const int64_t je = (jb + kSub < n_src) ? jb + kSub : n_src;
+        float are[kFB], aim[kFB];
+#pragma unroll
+        for (int q = 0; q < kFB; ++q) are[q] = aim[q] = 0.0f;
+        for (int64_t j = jb; j < je; ++j) {
+            const SrcRecF s = rec[j];
+            float t = dmx * s.ex;
+            t = fmaf(dmy, s.ey, t);
+            if constexpr (!PLANAR) t = fmaf(dmz, s.ez, t);
+            const float qq = t + s.es2;
+            const float r2 = fmaxf(rr2 + qq, kR2MinF);
+            const float ir = __builtin_amdgcn_rsqf(r2);
+            const float dr = qq * __builtin_amdgcn_rcpf(fmaf(r2, ir, rr));
+            const float phb = __builtin_amdgcn_fractf(fmaf(dr, ilb, p0b));
+            const float phd = __builtin_amdgcn_fractf(fmaf(dr, ild, p0d));
+            const float cd = __builtin_amdgcn_cosf(phd), sd = __builtin_amdgcn_sinf(phd);
+            float amp = ir;  // monopole: e^{ikr}/r
+            if constexpr (KIND == RSI_DIPOLE) {
+                const float hh = PLANAR ? ht : ht - s.h;
+                amp = hh * ir * ir;  // cos(theta)/r, times (ik - 1/r) per frequency below
+            }
+            float er = __builtin_amdgcn_cosf(phb) * amp, ei = __builtin_amdgcn_sinf(phb) * amp;
+#pragma unroll
+            for (int q = 0; q < kFB; ++q) {
+                float sre, sim;
+                if constexpr (SHARED_S) {
+                    sre = s.sre;
+                    sim = s.sim;
+                } else {
+                    const float2 sv = S[j * nf_pad + q0 + q];
+                    sre = sv.x;
+                    sim = sv.y;
+                }
+                float gr = er, gi = ei;
+                if constexpr (KIND == RSI_DIPOLE) {
+                    gr = -ir * er - kq[q] * ei;
+                    gi = fmaf(kq[q], er, -ir * ei);
+                }
+                are[q] = fmaf(sre, gr, are[q]);
+                are[q] = fmaf(-sim, gi, are[q]);
+                aim[q] = fmaf(sre, gi, aim[q]);
+                aim[q] = fmaf(sim, gr, aim[q]);
+                if (q + 1 < kFB) {  // advance to the next frequency: multiply by e^{i dk r}
+                    const float nr = er * cd - ei * sd;
+                    ei = fmaf(er, sd, ei * cd);
+                    er = nr;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kFB; ++q) {
+            float y = are[q] - cre[q];
+            float t = mre[q] + y;
+            cre[q] = (t - mre[q]) - y;
+            mre[q] = t;
+            y = aim[q] - cim[q];
+            t = mim[q] + y;
+            cim[q] = (t - mim[q]) - y;
+            mim[q] = t;
+        }
+    }
+    if (!valid) return;
+#pragma unroll
+    for (int q = 0; q < kFB; ++q)
+        if (q0 + q < n_freq) out[(int64_t)(q0 + q) * n_tgt + i] = make_float2(mre[q], mim[q]);
+}
+
+// S[j][q] = -(1/2pi) w_j T_j phi_q(Q_j) for q < n_freq, 0 for the padding.
+__global__ void __launch_bounds__(256) strength_multifreq_kernel(
+    int64_t n, int n_freq, int nf_pad, const double *__restrict__ w,
+    const float2 *__restrict__ field /* [n_freq][n] */, const double *__restrict__ tco,
+    float2 *__restrict__ S) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n * nf_pad) return;
+    const int64_t j = g / nf_pad;
+    const int q = (int)(g - j * nf_pad);
+    float2 r = make_float2(0.0f, 0.0f);
+    if (q < n_freq) {
+        const float2 f = field[(int64_t)q * n + j];
+        const double tre = tco[2 * j], tim = tco[2 * j + 1];
+        const double scale = -w[j] / kTwoPi;
+        r.x = (float)(scale * (tre * f.x - tim * f.y));
+        r.y = (float)(scale * (tre * f.y + tim * f.x));
+    }
+    S[g] = r;
+}
+
+bool uniform_grid(const double *freqs, int n, double &f0, double &df) {
+    if (n < 2) return false;
+    f0 = freqs[0];
+    df = (freqs[n - 1] - freqs[0]) / (n - 1);
+    if (!(df > 0.0)) return false;
+    for (int q = 0; q < n; ++q)
+        if (std::fabs(freqs[q] - (f0 + q * df)) > 1e-9 * std::fabs(freqs[n - 1])) return false;
+    return true;
+}
+
+rsi_status strength_multifreq(int64_t n, int n_freq, const double *w, const float2 *field,
+                              const double *tco, float2 *S, hipStream_t s) {
+    if (n == 0) return RSI_OK;
+    const int nf_pad = (n_freq + kFB - 1) / kFB * kFB;
+    const int64_t total = n * nf_pad;
+    hipLaunchKernelGGL(strength_multifreq_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
+                       0, s, n, n_freq, nf_pad, w, field, tco, S);
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+rsi_status pairsum_multifreq_f32(const SrcSetF &set, const float2 *S, const Targets &t,
+                                 rsi_kernel kind, bool planar_z, double c, double f0, double df,
+                                 int n_freq, float2 *out, hipStream_t s) {
+    if (t.n == 0 || n_freq == 0) return RSI_OK;
+    const int nfb = (n_freq + kFB - 1) / kFB;
+    const int nf_pad = nfb * kFB;
+    const int64_t bx = (t.n + kBlock - 1) / kBlock;
+    if (bx > 0x7fffffff || nfb > 65535) return RSI_ERR_SIZE;
+    const dim3 grid((unsigned)bx, (unsigned)nfb);
+    const double inv_c = 1.0 / c;
+    const bool shared = (S == nullptr);
+#define RSI_MF_LAUNCH(K, P, SH)                                                               \
+    hipLaunchKernelGGL((multifreq_f32_kernel<K, P, SH>), grid, dim3(kBlock), 0, s, set.rec, S, \
+                       set.n, nf_pad, t.x, t.y, t.z, t.n, set.anchor, f0, df, n_freq, inv_c, out)
+    if (kind == RSI_MONOPOLE) {
+        if (shared) {
+            if (planar_z) RSI_MF_LAUNCH(RSI_MONOPOLE, true, true);
+            else RSI_MF_LAUNCH(RSI_MONOPOLE, false, true);
+        } else {
+            if (planar_z) RSI_MF_LAUNCH(RSI_MONOPOLE, true, false);
+            else RSI_MF_LAUNCH(RSI_MONOPOLE, false, false);
+        }
+    } else {
+        if (!planar_z) return RSI_ERR_UNSUPPORTED;  // interface stages are planar (normal +z)
+        if (shared) RSI_MF_LAUNCH(RSI_DIPOLE, true, true);
+        else RSI_MF_LAUNCH(RSI_DIPOLE, true, false);
+    }
+#undef RSI_MF_LAUNCH
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+}  // namespace rsi

@@ -27,6 +27,7 @@
 // as the definition, in FP64.
 #include <cfloat>
 #include <cmath>
+#include <cstdlib>
 
 #include "rsi_device.h"
 
@@ -248,7 +249,7 @@ rsi_status set_strength_f64(SrcSetD &set, const double *w, const double *field,
 // ---------------------------------------------------------------------------
 // FP32 pair-sum kernel: grid (target tiles of kBlock*TPL, source splits).
 // ---------------------------------------------------------------------------
-template <int KIND, int TPL>
+template <int KIND, int TPL, bool PLANAR>
 __global__ void __launch_bounds__(kBlock) pairsum_f32_kernel(
     const SrcRecF *__restrict__ rec, int64_t n_src, int64_t chunk,
     const double *__restrict__ tx, const double *__restrict__ ty, const double *__restrict__ tz,
@@ -261,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) pairsum_f32_kernel(
     const int64_t j0 = (int64_t)blockIdx.y * chunk;
     const int64_t j1 = (j0 + chunk < n_src) ? j0 + chunk : n_src;
     float mre[TPL], mim[TPL];
-    sum_range_f32<KIND, TPL>(T, rec, j0, j1, (float)inv_lam, k, mre, mim);
+    sum_range_f32<KIND, TPL, PLANAR>(T, rec, j0, j1, (float)inv_lam, k, mre, mim);
     float2 *o = out + (int64_t)blockIdx.y * n_tgt;
 #pragma unroll
     for (int u = 0; u < TPL; ++u) {
@@ -321,12 +322,25 @@ __global__ void __launch_bounds__(256) zero_kernel(int64_t n, T2 *__restrict__ o
     }
 }
 
+// Optional overrides of the default launch shape, for tuning sweeps:
+// RSI_PAIRSUM_TPL (1, 2 or 4 targets per lane) and RSI_PAIRSUM_MIN_WG (workgroup goal).
+static int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    char *end = nullptr;
+    const long x = std::strtol(v, &end, 10);
+    return (end && *end == 0 && x > 0 && x < (1L << 30)) ? (int)x : dflt;
+}
+
 PairShape default_shape(int64_t n_src, int64_t n_tgt) {
+    static const int tpl_env = env_int("RSI_PAIRSUM_TPL", 2);
+    static const int min_wg = env_int("RSI_PAIRSUM_MIN_WG", 16384);
     PairShape sh;
-    sh.tpl = 2;
+    sh.tpl = (tpl_env == 1 || tpl_env == 4) ? tpl_env : 2;
     const int64_t bx = (n_tgt + kBlock * sh.tpl - 1) / (kBlock * sh.tpl);
-    // aim for >= 2048 workgroups (8 per CU) while keeping >= 4096 sources per split
-    int64_t splits = (2048 + bx - 1) / (bx > 0 ? bx : 1);
+    // aim for >= min_wg workgroups (64 per CU: small items balance the CUs at the end
+    // of the launch) while keeping >= 4096 sources per split
+    int64_t splits = (min_wg + bx - 1) / (bx > 0 ? bx : 1);
     const int64_t max_splits = (n_src + 4095) / 4096;
     if (splits > max_splits) splits = max_splits;
     if (splits < 1) splits = 1;
@@ -350,14 +364,18 @@ int64_t partial_slots(const PairShape &sh, int64_t n_src, int64_t n_tgt) {
 template <int KIND, int TPL>
 static void launch_f32(dim3 grid, hipStream_t s, const SrcSetF &set, int64_t chunk,
                        const Targets &t, double inv_lam, float k, double nx, double ny,
-                       double nz, float2 *dst) {
-    hipLaunchKernelGGL((pairsum_f32_kernel<KIND, TPL>), grid, dim3(kBlock), 0, s, set.rec, set.n,
-                       chunk, t.x, t.y, t.z, t.n, set.anchor, inv_lam, k, nx, ny, nz, dst);
+                       double nz, bool planar, float2 *dst) {
+    if (planar)
+        hipLaunchKernelGGL((pairsum_f32_kernel<KIND, TPL, true>), grid, dim3(kBlock), 0, s, set.rec,
+                           set.n, chunk, t.x, t.y, t.z, t.n, set.anchor, inv_lam, k, nx, ny, nz, dst);
+    else
+        hipLaunchKernelGGL((pairsum_f32_kernel<KIND, TPL, false>), grid, dim3(kBlock), 0, s, set.rec,
+                           set.n, chunk, t.x, t.y, t.z, t.n, set.anchor, inv_lam, k, nx, ny, nz, dst);
 }
 
 rsi_status pairsum_f32(const SrcSetF &set, const Targets &t, rsi_kernel kind,
                        const double *normal, double c, double freq, const PairShape &sh,
-                       float2 *partial, float2 *out, hipStream_t s) {
+                       float2 *partial, float2 *out, hipStream_t s, bool planar_z) {
     if (t.n == 0) return RSI_OK;
     if (set.n == 0) {
         hipLaunchKernelGGL(zero_kernel<float2>, dim3(blocks_for(t.n)), dim3(256), 0, s, t.n, out);
@@ -378,13 +396,13 @@ rsi_status pairsum_f32(const SrcSetF &set, const Targets &t, rsi_kernel kind,
     const double inv_lam = freq / c;
     const float k = (float)(kTwoPi * freq / c);
     if (kind == RSI_MONOPOLE) {
-        if (tpl == 1) launch_f32<RSI_MONOPOLE, 1>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
-        else if (tpl == 2) launch_f32<RSI_MONOPOLE, 2>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
-        else launch_f32<RSI_MONOPOLE, 4>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
+        if (tpl == 1) launch_f32<RSI_MONOPOLE, 1>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);
+        else if (tpl == 2) launch_f32<RSI_MONOPOLE, 2>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);
+        else launch_f32<RSI_MONOPOLE, 4>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);
     } else {
-        if (tpl == 1) launch_f32<RSI_DIPOLE, 1>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
-        else if (tpl == 2) launch_f32<RSI_DIPOLE, 2>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
-        else launch_f32<RSI_DIPOLE, 4>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, dst);
+        if (tpl == 1) launch_f32<RSI_DIPOLE, 1>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);
+        else if (tpl == 2) launch_f32<RSI_DIPOLE, 2>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);
+        else launch_f32<RSI_DIPOLE, 4>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);
     }
     RSI_HIP(hipGetLastError());
     if (ns > 1) {
@@ -434,11 +452,13 @@ rsi_status pairsum_f64(const SrcSetD &set, const Targets &t, rsi_kernel kind,
 
 using namespace rsi;
 
-extern "C" rsi_status rsi_propagate(const rsi_points *src, const double *src_w,
-                                    const double *src_vel, const double *normal,
-                                    const rsi_points *tgt, rsi_medium medium, double freq,
-                                    rsi_kernel kind, rsi_precision prec, void *out,
-                                    void *stream) {
+extern "C" rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_w,
+                                       const double *src_vel, const double *normal,
+                                       const rsi_points *tgt, rsi_medium medium, double freq,
+                                       rsi_kernel kind, rsi_precision prec, uint32_t flags,
+                                       void *out, void *stream) {
+    if ((flags & ~(uint32_t)RSI_FLAG_PLANAR_Z) != 0) return RSI_ERR_ARG;
+    const bool planar = (flags & RSI_FLAG_PLANAR_Z) != 0;
     if (!src || !tgt) return RSI_ERR_NULL;
     if (kind != RSI_MONOPOLE && kind != RSI_DIPOLE) return RSI_ERR_ARG;
     if (prec != RSI_FP32 && prec != RSI_FP64) return RSI_ERR_ARG;
@@ -452,6 +472,7 @@ extern "C" rsi_status rsi_propagate(const rsi_points *src, const double *src_w,
         if (!normal) return RSI_ERR_NULL;
         const double l2 = normal[0] * normal[0] + normal[1] * normal[1] + normal[2] * normal[2];
         if (!(l2 > 0.0) || !std::isfinite(l2)) return RSI_ERR_ARG;
+        if (planar && (normal[0] != 0.0 || normal[1] != 0.0)) return RSI_ERR_ARG;
     }
     hipStream_t s = as_stream(stream);
     Scratch scratch(s);
@@ -471,7 +492,7 @@ extern "C" rsi_status rsi_propagate(const rsi_points *src, const double *src_w,
         }
         if (nslots > 0) RSI_TRY(scratch.alloc(&partial, (size_t)nslots));
         return pairsum_f32(set, t, kind, normal, medium.c, freq, sh, partial,
-                           static_cast<float2 *>(out), s);
+                           static_cast<float2 *>(out), s, planar);
     }
     SrcSetD set;
     double2 *partial = nullptr;
@@ -482,4 +503,13 @@ extern "C" rsi_status rsi_propagate(const rsi_points *src, const double *src_w,
     if (nslots > 0) RSI_TRY(scratch.alloc(&partial, (size_t)nslots));
     return pairsum_f64(set, t, kind, normal, medium.c, freq, sh, partial,
                        static_cast<double2 *>(out), s);
+}
+
+extern "C" rsi_status rsi_propagate(const rsi_points *src, const double *src_w,
+                                    const double *src_vel, const double *normal,
+                                    const rsi_points *tgt, rsi_medium medium, double freq,
+                                    rsi_kernel kind, rsi_precision prec, void *out,
+                                    void *stream) {
+    return rsi_propagate_ex(src, src_w, src_vel, normal, tgt, medium, freq, kind, prec, 0u, out,
+                            stream);
 }

@@ -18,6 +18,7 @@ from . import _lib as L
 RSI_MONOPOLE, RSI_DIPOLE = 0, 1
 RSI_FP32, RSI_FP64 = 0, 1
 RSI_T_GLOBAL, RSI_T_LOCAL, RSI_T_UNITY = 0, 1, 2
+RSI_FLAG_PLANAR_Z = 1
 
 _OUT_DTYPE = {RSI_FP32: torch.complex64, RSI_FP64: torch.complex128}
 
@@ -105,6 +106,13 @@ def rsi_propagate(src, w: torch.Tensor, vel: torch.Tensor, tgt, c: float, freq: 
                   kind: int, prec: int, normal=None, rho: float = 1000.0,
                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """phi at the targets (complex64 for RSI_FP32, complex128 for RSI_FP64)."""
+    return rsi_propagate_ex(src, w, vel, tgt, c, freq, kind, prec, 0, normal, rho, out)
+
+
+def rsi_propagate_ex(src, w: torch.Tensor, vel: torch.Tensor, tgt, c: float, freq: float,
+                     kind: int, prec: int, flags: int, normal=None, rho: float = 1000.0,
+                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """rsi_propagate with RSI_FLAG_* flags."""
     sp = _points(*src, "src")
     tp = _points(*tgt, "tgt")
     _dev(w, torch.float64, "w")
@@ -113,9 +121,9 @@ def rsi_propagate(src, w: torch.Tensor, vel: torch.Tensor, tgt, c: float, freq: 
         out = torch.empty(tp.n, dtype=_OUT_DTYPE[prec], device=tgt[0].device)
     _dev(out, _OUT_DTYPE[prec], "out")
     nrm = _dvec(normal) if normal is not None else None
-    L.check(L.load().rsi_propagate(C.byref(sp), _ptr(w), _ptr(vel), nrm, C.byref(tp),
-                                   L.rsi_medium(c, rho), freq, kind, prec, _ptr(out), _stream()),
-            "rsi_propagate")
+    L.check(L.load().rsi_propagate_ex(C.byref(sp), _ptr(w), _ptr(vel), nrm, C.byref(tp),
+                                      L.rsi_medium(c, rho), freq, kind, prec, flags, _ptr(out),
+                                      _stream()), "rsi_propagate_ex")
     return out
 
 

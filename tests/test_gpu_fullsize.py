@@ -74,3 +74,56 @@ def test_one_interface_full_size_fp64(gpu):
     err = rel(out[np.array(g["index"])], ref)
     print(f"one_interface fp64: rel-L2 {err:.3e}")
     assert err <= 1e-10
+
+
+def test_layered_stack_full_size_plan_fp32(gpu):
+    """Three interfaces x 2^18 samples, 128^3 volume, 64 frequencies in multi-frequency
+    launches (chain plan), against the reference at 1 MHz and 10 MHz."""
+    import torch
+    g = golden("layered_stack")
+    cfg = W.LayeredStack()
+    xs = gpu.rsi_sample_disc(cfg.xd_seed, cfg.n_xd, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt)
+    ifs = []
+    for seed, (cx, cy), z in zip(cfg.if_seeds, cfg.patch_centres, cfg.z_if):
+        q = gpu.rsi_sample_square(seed, cfg.n_if, cx, cy, z, cfg.half_width)
+        ifs.append(gpu.Interface(*q[:3], q[3], z))
+    tgt = tuple(torch.as_tensor(a, device="cuda") for a in cfg.targets())
+    T = gpu.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    plan = gpu.Plan.chain(T, ifs, cfg.media, tgt, list(cfg.freqs), gpu.RSI_T_LOCAL, gpu.RSI_FP32)
+    plan.execute()
+    torch.cuda.synchronize()
+    idx = np.array(g["index"])
+    ref = np.array(g["re"]) + 1j * np.array(g["im"])
+    for fi, r in zip(g["freq_index"], ref):
+        got = plan.out[fi].cpu().numpy()[idx]
+        err = rel(got, r)
+        print(f"layered_stack f={cfg.freqs[fi] / 1e6:.3f} MHz fp32 rel-L2 {err:.3e}")
+        assert err <= 1e-4
+    plan.destroy()
+
+
+def test_scan_batch_full_size_plan(gpu, orc):
+    """256 uneven instances in one persistent launch (batched plan), 16 sampled field
+    points per instance against the reference (its own samples of each piston)."""
+    import torch
+    cfg = W.ScanBatch()
+    insts, meta = [], []
+    rng = np.random.default_rng(7)
+    for it in cfg.instances():
+        xs = gpu.rsi_sample_disc(it.seed, it.n_src, cfg.radius, (it.x_offset, 0.0, 0.0), it.tilt)
+        pts = cfg.field_points(it)
+        tgt = tuple(torch.as_tensor(a, device="cuda") for a in pts)
+        insts.append(gpu.Instance(xs[:3], xs[3], tgt, cfg.medium[0], cfg.freq, gpu.RSI_MONOPOLE))
+        meta.append((it, pts, np.sort(rng.choice(it.n_fld, min(16, it.n_fld), replace=False))))
+    plan = gpu.Plan.batched(insts, gpu.RSI_FP32)
+    plan.execute()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for inst, (it, pts, sel) in zip(insts, meta):
+        o = orc.sample_disc(it.seed, it.n_src, cfg.radius, (it.x_offset, 0.0, 0.0), it.tilt)
+        ref = orc.propagate(0, o[:3], o[3], 1.0, tuple(a[sel] for a in pts), cfg.medium[0], cfg.freq)
+        got = inst.out.cpu().numpy()[sel]
+        worst = max(worst, rel(got, ref))
+    print(f"scan_batch worst instance rel-L2 {worst:.3e}")
+    assert worst <= 1e-4
+    plan.destroy()

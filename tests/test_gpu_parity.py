@@ -90,6 +90,27 @@ def test_propagate_matches_reference(gpu, orc, kind, prec, ns, nt):
     assert rel(got, ref) <= TOL[prec], (kind, prec, ns, nt, rel(got, ref))
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("ns,nt", [(5, 3), (70001, 613)])
+def test_propagate_planar_flag(gpu, orc, kind, ns, nt):
+    """RSI_FLAG_PLANAR_Z (sources on one z plane): the reduced FP32 kernel keeps parity."""
+    src, w, s, tgt = _case(31 + ns, ns, nt, 1)
+    src = (src[0], src[1], np.full(ns, 0.0123))
+    tgt = (tgt[0], tgt[1], tgt[2] + 0.0123)
+    ref = orc.propagate(kind, src, w, s, tgt, 5900.0, 5e6, normal=(0.0, 0.0, 1.0))
+    got = host(gpu.rsi_propagate_ex(devpts(src), dev(w), dev(s), devpts(tgt), 5900.0, 5e6, kind, 0,
+                                    gpu.RSI_FLAG_PLANAR_Z, normal=(0.0, 0.0, 1.0)))
+    assert rel(got, ref) <= 1e-4
+
+
+def test_planar_flag_rejects_tilted_normal(gpu):
+    from paper_2408_06765_amd._lib import RSIError
+    src, w, s, tgt = _case(1, 10, 10, 1)
+    with pytest.raises(RSIError):
+        gpu.rsi_propagate_ex(devpts(src), dev(w), dev(s), devpts(tgt), 1480.0, 1e6, 1, 0,
+                             gpu.RSI_FLAG_PLANAR_Z, normal=(0.1, 0.0, 1.0))
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_propagate_empty_sources_give_zero(gpu, prec):
     import torch

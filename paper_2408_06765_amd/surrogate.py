@@ -1,0 +1,364 @@
+"""Learned surrogate of the post-interface field, with the RSI model as its fallback.
+
+Binding of include/rsi_mlp.h (argument marshalling only) plus the training recipe:
+fields from the RSI chain (rsi_chain, FP32) on a grid of configurations are demodulated
+by the ray carrier (rsi_surrogate_carrier) and fitted by the MLP (rsi_mlp_train_step);
+held-out configurations give a residual per parameter cell, and queries in cells whose
+residual exceeds the threshold are answered by the RSI chain instead.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import time
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import rsi
+from . import workloads as W
+
+_vp = C.c_void_p
+_fp = C.POINTER(C.c_float)
+
+SIGNATURES = {
+    "rsi_mlp_create": ([C.POINTER(_vp), C.c_int, C.c_int, C.c_int, _fp, _fp, _fp, C.c_int64], C.c_int),
+    "rsi_mlp_destroy": ([_vp], C.c_int),
+    "rsi_mlp_num_params": ([_vp], C.c_int64),
+    "rsi_mlp_set_params": ([_vp, _fp], C.c_int),
+    "rsi_mlp_get_params": ([_vp, _fp], C.c_int),
+    "rsi_mlp_forward": ([_vp, C.c_int64, _vp, _vp, _vp], C.c_int),
+    "rsi_mlp_gradients": ([_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "rsi_mlp_train_step": ([_vp, C.c_int64, _vp, _vp, C.c_float, _vp, _vp], C.c_int),
+    "rsi_mlp_save": ([_vp, C.c_char_p], C.c_int),
+    "rsi_mlp_load": ([_vp, C.c_char_p], C.c_int),
+    "rsi_surrogate_carrier": ([C.c_int64, _vp, L.rsi_medium, L.rsi_medium, C.c_int, _vp, _vp, _vp],
+                              C.c_int),
+}
+_bound = False
+
+
+def _load():
+    global _bound
+    lib = L.load()
+    if not _bound:
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _bound = True
+    return lib
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _dev(t, dtype, what):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"{what} must be a contiguous CUDA tensor of {dtype}")
+    return _vp(t.data_ptr())
+
+
+class MLP:
+    """rsi_mlp: Fourier features (n_ff) -> depth x width SiLU layers -> 2 outputs."""
+
+    def __init__(self, n_ff: int, width: int, depth: int, B, lo, hi, max_batch: int):
+        lib = _load()
+        self.n_ff, self.width, self.depth, self.max_batch = n_ff, width, depth, max_batch
+        self.B = _f32(B).reshape(n_ff, 5)
+        self.lo, self.hi = _f32(lo), _f32(hi)
+        h = _vp()
+        L.check(lib.rsi_mlp_create(C.byref(h), n_ff, width, depth, self.B.ctypes.data_as(_fp),
+                                   self.lo.ctypes.data_as(_fp), self.hi.ctypes.data_as(_fp), max_batch),
+                "rsi_mlp_create")
+        self._h = h
+        self.num_params = int(lib.rsi_mlp_num_params(h))
+
+    def set_params(self, p) -> None:
+        p = _f32(p)
+        assert p.size == self.num_params
+        L.check(_load().rsi_mlp_set_params(self._h, p.ctypes.data_as(_fp)), "rsi_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.num_params, dtype=np.float32)
+        L.check(_load().rsi_mlp_get_params(self._h, p.ctypes.data_as(_fp)), "rsi_mlp_get_params")
+        return p
+
+    def forward(self, q: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+        n = q.shape[0]
+        if y is None:
+            y = torch.empty((n, 2), dtype=torch.float32, device=q.device)
+        L.check(_load().rsi_mlp_forward(self._h, n, _dev(q, torch.float32, "q"), _dev(y, torch.float32, "y"),
+                                        _stream()), "rsi_mlp_forward")
+        return y
+
+    def gradients(self, q: torch.Tensor, t: torch.Tensor):
+        g = torch.empty(self.num_params, dtype=torch.float32, device=q.device)
+        loss = torch.empty(1, dtype=torch.float32, device=q.device)
+        L.check(_load().rsi_mlp_gradients(self._h, q.shape[0], _dev(q, torch.float32, "q"),
+                                          _dev(t, torch.float32, "t"), _dev(g, torch.float32, "grad"),
+                                          _dev(loss, torch.float32, "loss"), _stream()), "rsi_mlp_gradients")
+        return g, loss
+
+    def train_step(self, q: torch.Tensor, t: torch.Tensor, lr: float, loss: Optional[torch.Tensor] = None):
+        L.check(_load().rsi_mlp_train_step(self._h, q.shape[0], _dev(q, torch.float32, "q"),
+                                           _dev(t, torch.float32, "t"), float(lr),
+                                           _dev(loss, torch.float32, "loss") if loss is not None else None,
+                                           _stream()), "rsi_mlp_train_step")
+        return loss
+
+    def save(self, path: str) -> None:
+        L.check(_load().rsi_mlp_save(self._h, path.encode()), "rsi_mlp_save")
+
+    def load(self, path: str) -> None:
+        L.check(_load().rsi_mlp_load(self._h, path.encode()), "rsi_mlp_load")
+
+    def destroy(self) -> None:
+        if self._h:
+            L.check(_load().rsi_mlp_destroy(self._h), "rsi_mlp_destroy")
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def rsi_surrogate_carrier(q: torch.Tensor, m1, m2, mode: int, x: torch.Tensor) -> torch.Tensor:
+    """mode 0: field -> envelope; mode 1: envelope -> field (complex64 in and out)."""
+    out = torch.empty_like(x)
+    L.check(_load().rsi_surrogate_carrier(q.shape[0], _dev(q, torch.float32, "q"), L.rsi_medium(*m1),
+                                          L.rsi_medium(*m2), mode, _dev(x, torch.complex64, "in"),
+                                          _dev(out, torch.complex64, "out"), _stream()),
+            "rsi_surrogate_carrier")
+    return out
+
+
+# ------------------------------------------------------------------------------ recipe
+def glorot_params(n_ff: int, width: int, depth: int, seed: int) -> np.ndarray:
+    """Flat FP32 initial parameters: Glorot-uniform weights, zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    fan_in = 2 * n_ff
+    for _ in range(depth):
+        a = math.sqrt(6.0 / (fan_in + width))
+        parts += [rng.uniform(-a, a, (width, fan_in)).ravel(), np.zeros(width)]
+        fan_in = width
+    a = math.sqrt(6.0 / (width + 2))
+    parts += [rng.uniform(-a, a, (2, width)).ravel(), np.zeros(2)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def fourier_matrix(n_ff: int, scales: Sequence[float], seed: int) -> np.ndarray:
+    """B [n_ff][5]: Gaussian frequencies, column c scaled by scales[c] (cycles per unit)."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n_ff, 5)) * np.asarray(scales)[None, :]).astype(np.float32)
+
+
+@dataclass
+class SurrogateConfig:
+    box: W.SurrogateBox = W.SurrogateBox()
+    n_xd: int = 1 << 16
+    n_if: int = 1 << 18
+    half_width: float = 0.03
+    nx: int = 125
+    nz: int = 125
+    grid_f: int = 8
+    grid_depth: int = 8
+    grid_tilt: int = 10
+    cells: Tuple[int, int, int] = (4, 4, 4)
+    n_ff: int = 128
+    width: int = 256
+    depth: int = 5
+    ff_scales: Tuple[float, ...] = (6.0, 4.0, 2.0, 2.0, 2.0)
+    batch: int = 65536
+    epochs: int = 60
+    lr0: float = 2e-3
+    lr1: float = 2e-5
+    threshold: float = 1e-3
+    seed: int = 0
+
+
+def lohi(box: W.SurrogateBox):
+    lo = [box.x_range[0], box.z_below[0], box.f_range[0], box.depth_range[0], box.tilt_range[0]]
+    hi = [box.x_range[1], box.z_below[1], box.f_range[1], box.depth_range[1], box.tilt_range[1]]
+    return lo, hi
+
+
+def config_grid(cfg: SurrogateConfig) -> np.ndarray:
+    """Training configurations (f, depth, tilt) on a regular grid spanning the box."""
+    b = cfg.box
+    f = np.linspace(*b.f_range, cfg.grid_f)
+    d = np.linspace(*b.depth_range, cfg.grid_depth)
+    t = np.linspace(*b.tilt_range, cfg.grid_tilt)
+    F, D, T = np.meshgrid(f, d, t, indexing="ij")
+    return np.stack([F.ravel(), D.ravel(), T.ravel()], 1)
+
+
+def random_configs(cfg: SurrogateConfig, n: int, seed: int) -> np.ndarray:
+    """n configurations (f, depth, tilt) uniform in the box."""
+    rng = np.random.default_rng(seed)
+    b = cfg.box
+    return np.stack([rng.uniform(*b.f_range, n), rng.uniform(*b.depth_range, n),
+                     rng.uniform(*b.tilt_range, n)], 1)
+
+
+def cell_configs(cfg: SurrogateConfig, seed: int) -> np.ndarray:
+    """One random configuration inside every (f, depth, tilt) cell."""
+    rng = np.random.default_rng(seed)
+    b = cfg.box
+    out = []
+    nf, nd, nt = cfg.cells
+    for i in range(nf):
+        for j in range(nd):
+            for k in range(nt):
+                u = rng.uniform(0, 1, 3)
+                out.append([b.f_range[0] + (i + u[0]) / nf * (b.f_range[1] - b.f_range[0]),
+                            b.depth_range[0] + (j + u[1]) / nd * (b.depth_range[1] - b.depth_range[0]),
+                            b.tilt_range[0] + (k + u[2]) / nt * (b.tilt_range[1] - b.tilt_range[0])])
+    return np.array(out)
+
+
+def cell_of(cfg: SurrogateConfig, f: float, depth: float, tilt: float) -> int:
+    b = cfg.box
+    nf, nd, nt = cfg.cells
+    i = min(nf - 1, int((f - b.f_range[0]) / (b.f_range[1] - b.f_range[0]) * nf))
+    j = min(nd - 1, int((depth - b.depth_range[0]) / (b.depth_range[1] - b.depth_range[0]) * nd))
+    k = min(nt - 1, int((tilt - b.tilt_range[0]) / (b.tilt_range[1] - b.tilt_range[0]) * nt))
+    return (i * nd + j) * nt + k
+
+
+class FieldSource:
+    """RSI fields of one configuration family: the piston of the workload, one interface."""
+
+    def __init__(self, cfg: SurrogateConfig):
+        self.cfg = cfg
+        b = cfg.box
+        xs = np.linspace(*b.x_range, cfg.nx)
+        zs = np.linspace(*b.z_below, cfg.nz)
+        X, Z = np.meshgrid(xs, zs)
+        self.xg = X.ravel()
+        self.zg = Z.ravel()
+
+    def queries(self, f: float, depth: float, tilt: float, xz=None) -> torch.Tensor:
+        """Query rows (x, z_below, f, depth, tilt): the image grid, or the given (x, z) points."""
+        xg, zg = (self.xg, self.zg) if xz is None else xz
+        n = xg.size
+        q = np.stack([xg, zg, np.full(n, f), np.full(n, depth), np.full(n, tilt)], 1)
+        return torch.as_tensor(q.astype(np.float32), device="cuda")
+
+    def random_points(self, rng: np.random.Generator, n: int):
+        b = self.cfg.box
+        return rng.uniform(*b.x_range, n), rng.uniform(*b.z_below, n)
+
+    def rsi_pressure(self, f: float, depth: float, tilt: float, xz=None) -> torch.Tensor:
+        """p = i omega rho2 phi at the grid points from the RSI chain (FP32)."""
+        cfg, b = self.cfg, self.cfg.box
+        xs = rsi.rsi_sample_disc(0, cfg.n_xd, b.radius, (0.0, 0.0, 0.0), tilt)
+        qs = rsi.rsi_sample_square(1, cfg.n_if, depth * math.tan(tilt), 0.0, depth, cfg.half_width)
+        T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), (math.sin(tilt), 0.0, math.cos(tilt)))
+        I = [rsi.Interface(*qs[:3], qs[3], depth)]
+        # field points are the FP32 query coordinates widened to FP64, so that the
+        # surrogate and the RSI see exactly the same points
+        q = self.queries(f, depth, tilt, xz)
+        tgt = (q[:, 0].double().contiguous(), torch.zeros(q.shape[0], dtype=torch.float64, device="cuda"),
+               (q[:, 3].double() + q[:, 1].double()).contiguous())
+        phi = rsi.rsi_chain(T, I, b.media, tgt, [f], rsi.RSI_T_LOCAL, rsi.RSI_FP32)[0]
+        return rsi.rsi_to_pressure(phi, b.media[1][1], f)
+
+
+def rel_l2(a: torch.Tensor, b: torch.Tensor) -> float:
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+class Surrogate:
+    """Trained network + per-cell residuals + routing with RSI fallback."""
+
+    def __init__(self, cfg: SurrogateConfig):
+        self.cfg = cfg
+        lo, hi = lohi(cfg.box)
+        self.B = fourier_matrix(cfg.n_ff, cfg.ff_scales, cfg.seed)
+        self.net = MLP(cfg.n_ff, cfg.width, cfg.depth, self.B, lo, hi, cfg.batch)
+        self.net.set_params(glorot_params(cfg.n_ff, cfg.width, cfg.depth, cfg.seed + 1))
+        self.src = FieldSource(cfg)
+        self.cell_err: Dict[int, float] = {}
+        self.m1, self.m2 = cfg.box.media
+
+    # ---- data
+    def dataset(self, configs: np.ndarray, points_per_config: Optional[int] = None, seed: int = 11):
+        """Envelope targets from RSI fields: on the image grid of every configuration, or on
+        `points_per_config` random (x, z) points per configuration."""
+        rng = np.random.default_rng(seed)
+        qs, ts = [], []
+        for f, d, t in configs:
+            xz = None if points_per_config is None else self.src.random_points(rng, points_per_config)
+            q = self.src.queries(f, d, t, xz)
+            p = self.src.rsi_pressure(f, d, t, xz)
+            env = rsi_surrogate_carrier(q, self.m1, self.m2, 0, p)
+            qs.append(q)
+            ts.append(torch.view_as_real(env).contiguous())
+        return torch.cat(qs), torch.cat(ts)
+
+    # ---- training
+    def train(self, q: torch.Tensor, t: torch.Tensor, epochs: Optional[int] = None, log=None):
+        cfg = self.cfg
+        epochs = cfg.epochs if epochs is None else epochs
+        n = q.shape[0]
+        nb = max(1, n // cfg.batch)
+        total = epochs * nb
+        g = torch.Generator(device="cuda")
+        g.manual_seed(cfg.seed + 7)
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        step = 0
+        for ep in range(epochs):
+            perm = torch.randperm(n, device="cuda", generator=g)
+            for b in range(nb):
+                idx = perm[b * cfg.batch:(b + 1) * cfg.batch]
+                lr = cfg.lr1 + 0.5 * (cfg.lr0 - cfg.lr1) * (1 + math.cos(math.pi * step / total))
+                self.net.train_step(q[idx].contiguous(), t[idx].contiguous(), lr, loss)
+                step += 1
+            if log:
+                log(f"epoch {ep + 1}/{epochs} loss {float(loss):.3e}")
+        return float(loss)
+
+    # ---- inference
+    def predict(self, q: torch.Tensor) -> torch.Tensor:
+        """Field p (complex64) from the network and the carrier, in batches."""
+        out = torch.empty(q.shape[0], dtype=torch.complex64, device=q.device)
+        y = torch.empty((self.cfg.batch, 2), dtype=torch.float32, device=q.device)
+        for s in range(0, q.shape[0], self.cfg.batch):
+            e = min(q.shape[0], s + self.cfg.batch)
+            yy = self.net.forward(q[s:e].contiguous(), y[:e - s])
+            out[s:e] = rsi_surrogate_carrier(q[s:e].contiguous(), self.m1, self.m2, 1,
+                                             torch.view_as_complex(yy).contiguous())
+        return out
+
+    def validate(self, configs: np.ndarray) -> Dict[int, float]:
+        """Held-out residual (rel-L2 against RSI) per cell; the worst config in a cell counts."""
+        for f, d, t in configs:
+            q = self.src.queries(f, d, t)
+            err = rel_l2(self.predict(q), self.src.rsi_pressure(f, d, t))
+            c = cell_of(self.cfg, f, d, t)
+            self.cell_err[c] = max(self.cell_err.get(c, 0.0), err)
+        return self.cell_err
+
+    def answer(self, configs: np.ndarray):
+        """Fields for query configurations: surrogate in cells that passed validation,
+        RSI elsewhere (and in cells never validated).  Returns (fields, used_rsi flags)."""
+        out, used = [], []
+        for f, d, t in configs:
+            c = cell_of(self.cfg, f, d, t)
+            ok = self.cell_err.get(c, math.inf) <= self.cfg.threshold
+            q = self.src.queries(f, d, t)
+            out.append(self.predict(q) if ok else self.src.rsi_pressure(f, d, t))
+            used.append(not ok)
+        return out, used

@@ -25,6 +25,40 @@ def test_header_functions_exported_and_bound():
         assert n in _lib.SIGNATURES, f"{n} has no Python binding"
 
 
+def test_surrogate_header_functions_exported_and_bound():
+    from paper_2408_06765_amd import _lib, surrogate
+    lib = surrogate._load()
+    names = declared_functions("rsi_mlp.h")
+    assert "rsi_mlp_train_step" in names and "rsi_surrogate_carrier" in names
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in surrogate.SIGNATURES, f"{n} has no Python binding"
+
+
+def test_surrogate_argument_errors():
+    import ctypes as C
+    from paper_2408_06765_amd import surrogate
+    lib = surrogate._load()
+    h = C.c_void_p()
+    B = (C.c_float * 10)()
+    lo = (C.c_float * 5)(0, 0, 0, 0, 0)
+    hi = (C.c_float * 5)(1, 1, 1, 1, 1)
+    # width not a multiple of 64, depth out of range, empty box
+    assert lib.rsi_mlp_create(C.byref(h), 32, 100, 3, B, lo, hi, 64) == 2
+    assert lib.rsi_mlp_create(C.byref(h), 32, 64, 0, B, lo, hi, 64) == 2
+    assert lib.rsi_mlp_create(C.byref(h), 32, 64, 3, B, lo, lo, 64) == 2
+    assert lib.rsi_mlp_create(C.byref(h), 32, 64, 3, B, lo, hi, 0) == 3
+    assert lib.rsi_mlp_destroy(None) == 0
+    assert lib.rsi_mlp_forward(None, 1, None, None, None) == 1
+    assert lib.rsi_surrogate_carrier(4, None, _lib_medium(1480, 1000), _lib_medium(5900, 7800), 3, None, None,
+                                     None) == 2
+
+
+def _lib_medium(c, rho):
+    from paper_2408_06765_amd import _lib
+    return _lib.rsi_medium(c, rho)
+
+
 def test_status_strings_and_version():
     from paper_2408_06765_amd import _lib
     lib = _lib.load()

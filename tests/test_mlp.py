@@ -1,0 +1,230 @@
+"""The learned surrogate: its FP64 reference pinned on the CPU, and the GPU kernels
+(bf16 MFMA forward/backward, Adam, checkpoint, carrier) against that reference."""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as MO
+from paper_2408_06765_amd import workloads as W
+
+
+def tiny_net(seed, n_ff=4, width=6, depth=2):
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((n_ff, 5))
+    Ws, bs, fan = [], [], 2 * n_ff
+    for _ in range(depth):
+        Ws.append(rng.standard_normal((width, fan)) / math.sqrt(fan))
+        bs.append(0.1 * rng.standard_normal(width))
+        fan = width
+    return B, Ws, bs, rng.standard_normal((2, width)) / math.sqrt(width), 0.1 * rng.standard_normal(2)
+
+
+# ------------------------------------------------------------------ reference pins (CPU)
+def test_reference_gradients_match_finite_differences():
+    """Pure FP64 (no rounding): analytic gradients of the reference = central differences."""
+    B, Ws, bs, Wo, bo = tiny_net(0)
+    net = MO.MLPOracle(B, Ws, bs, Wo, bo, emulate_bf16=False)
+    rng = np.random.default_rng(1)
+    v = rng.uniform(-1, 1, (7, 5))
+    t = rng.standard_normal((7, 2))
+    _, _, g = net.loss_and_grads(v, t)
+    ga = net.flat_grads(g)
+    p0 = net.flat()
+    gn = np.zeros_like(p0)
+    h = 1e-6
+    for i in range(p0.size):
+        for sgn in (1, -1):
+            p = p0.copy()
+            p[i] += sgn * h
+            net.set_flat(p)
+            gn[i] += sgn * net.loss_and_grads(v, t)[0] / (2 * h)
+    net.set_flat(p0)
+    assert np.max(np.abs(ga - gn)) < 1e-7 * max(1.0, np.max(np.abs(ga)))
+
+
+def test_bf16_rounding_is_nearest_even():
+    x = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, -2.5, 3.0e38, 1e-40])
+    r = MO.bf16(x)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                       # tie -> even mantissa
+    assert r[2] == 1 + 2 ** -6               # tie -> even mantissa (upwards)
+    assert r[3] == 1 + 2 ** -7               # above the tie -> up
+    assert r[4] == -2.5
+    assert np.isfinite(r[5]) and abs(r[5] / 3.0e38 - 1) < 2 ** -8
+    assert r[6] == 2.0 ** -133              # subnormal: nearest multiple of 2^-133
+
+
+def test_adam_first_step_is_sign_step():
+    """Bias-corrected Adam moves every parameter by lr * g / (|g| + eps) on step 1."""
+    p = np.array([0.5, -1.0, 2.0])
+    g = np.array([1e-3, -4.0, 0.0])
+    p1, m, v = MO.adam_step(p, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    assert np.allclose(p1, p - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+# ------------------------------------------------------------------ GPU vs reference
+def _setup(gpu_ok, n_ff, width, depth, n, seed):
+    import torch
+    from paper_2408_06765_amd import surrogate as S
+    box = W.SurrogateBox()
+    lo, hi = S.lohi(box)
+    B = S.fourier_matrix(n_ff, (12.0, 8.0, 3.0, 3.0, 3.0), seed)
+    params = S.glorot_params(n_ff, width, depth, seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    q = np.stack([rng.uniform(lo[c], hi[c], n) for c in range(5)], 1).astype(np.float32)
+    t = rng.standard_normal((n, 2)).astype(np.float32)
+    net = S.MLP(n_ff, width, depth, B, lo, hi, max(n, 64))
+    net.set_params(params)
+    # the reference sees the same float32 inputs and parameters
+    v = MO.normalise(q.astype(np.float64), lo, hi)
+    o = _oracle_from_flat(B, params, n_ff, width, depth)
+    return net, o, torch.as_tensor(q, device="cuda"), torch.as_tensor(t, device="cuda"), v, t, params
+
+
+def _oracle_from_flat(B, p, n_ff, width, depth, noise=None):
+    Ws, bs, o, fan = [], [], 0, 2 * n_ff
+    p = p.astype(np.float64)
+    for _ in range(depth):
+        Ws.append(p[o:o + width * fan].reshape(width, fan))
+        o += width * fan
+        bs.append(p[o:o + width])
+        o += width
+        fan = width
+    Wo = p[o:o + 2 * width].reshape(2, width)
+    o += 2 * width
+    return MO.MLPOracle(B.astype(np.float64), Ws, bs, Wo, p[o:o + 2], noise=noise)
+
+
+def flip_tolerance(B, params, n_ff, width, depth, v, t, what):
+    """Parity bar for a bf16 network: 1e-3, or 3x the drift between the reference and the
+    same reference with FP32-sized perturbations (2^-24 sqrt(fan-in)) before each bf16
+    rounding, whichever is larger -- deep networks amplify rounding-boundary flips."""
+    a = _oracle_from_flat(B, params, n_ff, width, depth)
+    b = _oracle_from_flat(B, params, n_ff, width, depth,
+                          noise=(np.random.default_rng(123), 2.0 ** -24 * math.sqrt(width)))
+    if what == "y":
+        d = rel(b.forward(v)[0], a.forward(v)[0])
+    else:
+        ga = a.flat_grads(a.loss_and_grads(v, t)[2])
+        d = rel(b.flat_grads(b.loss_and_grads(v, t)[2]), ga)
+    return max(1e-3, 3.0 * d)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+SHAPES = [(32, 64, 3, 300), (128, 256, 5, 1000)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n_ff,width,depth,n", SHAPES)
+def test_mlp_forward_matches_reference(gpu, n_ff, width, depth, n):
+    net, o, q, t, v, tn, params = _setup(gpu, n_ff, width, depth, n, 3)
+    y = net.forward(q).cpu().numpy()
+    yr, _ = o.forward(v)
+    tol = flip_tolerance(net.B, params, n_ff, width, depth, v, tn.astype(np.float64), "y")
+    assert rel(y, yr) <= tol, (rel(y, yr), tol)
+    net.destroy()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n_ff,width,depth,n", SHAPES)
+def test_mlp_gradients_match_reference(gpu, n_ff, width, depth, n):
+    net, o, q, t, v, tn, params = _setup(gpu, n_ff, width, depth, n, 4)
+    g, loss = net.gradients(q, t)
+    lr_, _, gr = o.loss_and_grads(v, tn.astype(np.float64))
+    g = g.cpu().numpy()
+    flat = o.flat_grads(gr)
+    assert abs(float(loss.cpu()) / lr_ - 1) < 1e-3
+    tol = flip_tolerance(net.B, params, n_ff, width, depth, v, tn.astype(np.float64), "g")
+    assert rel(g, flat) <= tol, (rel(g, flat), tol)
+    # every weight matrix on its own
+    off = 0
+    for l, Wl in enumerate(gr["Ws"]):
+        assert rel(g[off:off + Wl.size], Wl.ravel()) <= tol, (l, rel(g[off:off + Wl.size], Wl.ravel()), tol)
+        off += Wl.size + gr["bs"][l].size
+    net.destroy()
+
+
+@pytest.mark.gpu
+def test_mlp_train_step_is_adam(gpu):
+    net, o, q, t, v, tn, p0 = _setup(gpu, 32, 64, 3, 500, 5)
+    net.train_step(q, t, 1e-3)
+    p1 = net.get_params().astype(np.float64)
+    _, _, gr = o.loss_and_grads(v, tn.astype(np.float64))
+    g = o.flat_grads(gr)
+    pr, _, _ = MO.adam_step(p0.astype(np.float64), g, 0.0, 0.0, 1, 1e-3)
+    d_gpu, d_ref = p1 - p0, pr - p0
+    # the first bias-corrected step is lr * g / (|g| + eps): a sign step, so compare where
+    # the reference gradient clearly exceeds the GPU-vs-reference gradient error
+    clear = np.abs(g) > 1e-2 * np.sqrt(np.mean(g * g))
+    assert clear.mean() > 0.9
+    assert rel(d_gpu[clear], d_ref[clear]) <= 1e-4
+    assert np.max(np.abs(d_gpu)) <= 1e-3 * (1 + 1e-5)
+    net.destroy()
+
+
+@pytest.mark.gpu
+def test_mlp_checkpoint_resume_is_exact(gpu):
+    import torch
+    from paper_2408_06765_amd import surrogate as S
+    net, o, q, t, v, tn, p0 = _setup(gpu, 32, 64, 3, 640, 6)
+    for _ in range(6):
+        net.train_step(q, t, 1e-3)
+    straight = net.get_params()
+    net.set_params(p0)
+    for _ in range(3):
+        net.train_step(q, t, 1e-3)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ckpt.bin")
+        net.save(path)
+        box = W.SurrogateBox()
+        lo, hi = S.lohi(box)
+        net2 = S.MLP(32, 64, 3, net.B, lo, hi, 640)
+        net2.load(path)
+        for _ in range(3):
+            net2.train_step(q, t, 1e-3)
+        resumed = net2.get_params()
+        net2.destroy()
+    assert np.array_equal(straight.view(np.uint32), resumed.view(np.uint32))
+    net.destroy()
+
+
+@pytest.mark.gpu
+def test_carrier_phase_and_inverse(gpu):
+    """The carrier is the refracted plane wave of the tilted piston: its phase gradient is
+    (2 pi f sin(tilt)/c1) along x and (2 pi f cos(a2)/c2) along z below the interface,
+    with sin(a2) = (c2/c1) sin(tilt) (Snell, eq. 15); modulate o demodulate = identity."""
+    import torch
+    from paper_2408_06765_amd import surrogate as S
+    m1, m2 = W.WATER, W.STEEL_5900
+    rng = np.random.default_rng(9)
+    n, h = 64, 1e-6
+    base = np.stack([rng.uniform(-0.01, 0.04, n), rng.uniform(0.002, 0.03, n), rng.uniform(1e6, 1e7, n),
+                     rng.uniform(0.03, 0.07, n), rng.uniform(0.0, math.radians(14.0), n)], 1)
+    qs = [base.copy(), base.copy(), base.copy()]
+    qs[1][:, 0] += h
+    qs[2][:, 1] += h
+    one = torch.ones(n, dtype=torch.complex64, device="cuda")
+    env = [S.rsi_surrogate_carrier(torch.as_tensor(q.astype(np.float32), device="cuda"), m1, m2, 0, one)
+           .cpu().numpy().astype(np.complex128) for q in qs]
+    qf = [q.astype(np.float32).astype(np.float64) for q in qs]
+    for i in range(n):
+        f, tilt = qf[0][i, 2], qf[0][i, 4]
+        kx = 2 * math.pi * f * math.sin(tilt) / m1[0]
+        s2 = m2[0] / m1[0] * math.sin(tilt)
+        kz = 2 * math.pi * f * math.sqrt(1 - s2 * s2) / m2[0]
+        # demodulation multiplies by e^{-i psi}: the phase decreases by k dx
+        dpx = -np.angle(env[1][i] / env[0][i]) / (qf[1][i, 0] - qf[0][i, 0])
+        dpz = -np.angle(env[2][i] / env[0][i]) / (qf[2][i, 1] - qf[0][i, 1])
+        assert abs(dpx - kx) < 2e-3 * (abs(kx) + 1e3)
+        assert abs(dpz - kz) < 2e-3 * kz
+        assert abs(abs(env[0][i]) * m1[0] * m1[1] - 1) < 1e-6
+    x = torch.as_tensor((rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64), device="cuda")
+    qd = torch.as_tensor(base.astype(np.float32), device="cuda")
+    back = S.rsi_surrogate_carrier(qd, m1, m2, 1, S.rsi_surrogate_carrier(qd, m1, m2, 0, x))
+    assert rel(back.cpu().numpy(), x.cpu().numpy()) < 1e-6

@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="one_interface",
-                    choices=["one_interface", "layered_stack", "scan_batch"],
+                    choices=["one_interface", "layered_stack", "scan_batch", "surrogate"],
                     help="one_interface is the benchmark line; the others are secondary "
                          "measurements printed in the same format")
     ap.add_argument("--autotune", action="store_true",
@@ -199,6 +199,61 @@ def scan_batch(args):
     plan.destroy()
 
 
+def surrogate(args):
+    """The learned surrogate: 10^7 RSI samples (5120 random configurations of the
+    one-interface piston family x 1953 points), 5 x 256 MLP trained with the MFMA kernels,
+    held-out residual per (f, depth, tilt) cell, 10^6 queries (64 configurations x 125^2)
+    answered by the network where its cell passes the threshold and by RSI elsewhere."""
+    import torch
+    from paper_2408_06765_amd import surrogate as S
+
+    cfg = S.SurrogateConfig()
+    sur = S.Surrogate(cfg)
+    t0 = time.perf_counter()
+    q, t = sur.dataset(S.random_configs(cfg, 5120, 3), points_per_config=1953)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss = sur.train(q, t, log=lambda s: print(s, file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del q, t
+    errs = sur.validate(S.cell_configs(cfg, 101))
+    e = np.array([errs[c] for c in sorted(errs)])
+    qc = S.cell_configs(cfg, 202)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    out, used = sur.answer(qc)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for f, d, tl in qc:
+        sur.src.rsi_pressure(f, d, tl)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    for f, d, tl in qc:
+        sur.predict(sur.src.queries(f, d, tl))
+    torch.cuda.synchronize()
+    t6 = time.perf_counter()
+    rsi_s, routed_s, net_s = t5 - t4, t4 - t3, t6 - t5
+    n_q = len(qc) * cfg.nx * cfg.nz
+    thresholds = [1e-3, 1e-2, 1e-1, 0.3, 1.0]
+    line = {
+        "metric": "surrogate speedup over RSI at <= 1e-3 rel-L2 (held-out, per cell)",
+        "value": round(rsi_s / routed_s, 3), "unit": "x", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1e3 * routed_s, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 (MFMA, FP32 accumulation)", "data": "synthetic",
+        "config": {"workload": "surrogate: piston + water/5900 m/s interface, x, z, f 1-10 MHz, depth "
+                               "30-70 mm, tilt 0-20 deg; 5 x 256 Fourier-feature MLP",
+                   "train_samples": 5120 * 1953, "queries": n_q},
+        "data_generation_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2), "final_loss": loss,
+        "cell_residual": {"min": float(e.min()), "median": float(np.median(e)), "max": float(e.max())},
+        "cells_passing": {str(th): int((e <= th).sum()) for th in thresholds}, "cells": int(e.size),
+        "queries_on_rsi_fallback": int(sum(used)),
+        "rsi_s_for_queries": round(rsi_s, 4), "network_s_for_queries": round(net_s, 4),
+        "network_only_speedup": round(rsi_s / net_s, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -210,6 +265,8 @@ def main():
         return layered_stack(args)
     if args.workload == "scan_batch":
         return scan_batch(args)
+    if args.workload == "surrogate":
+        return surrogate(args)
 
     from paper_2408_06765_amd import rsi
     from paper_2408_06765_amd import workloads as W

@@ -24,10 +24,11 @@
  *  - Precision: RSI_FP64 computes every operation in FP64 and excludes pairs closer
  *    than 1e-12 m, exactly as the FP64 reference does.  RSI_FP32 keeps FP64 for the
  *    per-target reference distance and the reduction of the phase k r to
- *    revolutions, and runs the per-pair arithmetic and the accumulation in FP32; it
- *    clamps r^2 from below instead of excluding close pairs, so it assumes no field
- *    point lies closer to a source than about 1e-6 of the source-set extent (the
- *    kernel is singular on the radiating surface, Sec. 3.2).
+ *    revolutions, and runs the per-pair arithmetic and the accumulation in FP32.  It
+ *    does not test for close pairs: field points must lie farther from every source
+ *    than about 1e-6 of the source-set extent (the kernel is singular on the radiating
+ *    surface, Sec. 3.2); a field point on a source gives an unspecified, possibly
+ *    non-finite value at that point.
  */
 #ifndef RSI_H
 #define RSI_H

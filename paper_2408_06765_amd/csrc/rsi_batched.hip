@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(256) batched_reduce_kernel(const InstDev *__re
 // Host side: batch tables.
 // ---------------------------------------------------------------------------
 struct BatchShape {
-    int tpl = 2;
+    int tpl = 1;
     int64_t chunk = 16384;
 };
 
@@ -545,9 +545,9 @@ static BatchShape default_batch_shape(const rsi_instance *inst, int n_inst) {
     BatchShape sh;
     double pairs = 0.0;
     for (int i = 0; i < n_inst; ++i) pairs += (double)inst[i].src.n * (double)inst[i].tgt.n;
-    sh.tpl = 2;
-    // aim for at least ~16 items per CU slot while keeping chunks >= 4096 sources
-    sh.chunk = 16384;
+    sh.tpl = 1;
+    // small items balance the CUs; chunks stay >= 4096 sources
+    sh.chunk = 8192;
     (void)pairs;
     return sh;
 }

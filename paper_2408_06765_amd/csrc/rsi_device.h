@@ -13,6 +13,11 @@ namespace rsi {
 constexpr int kSub = 64;  // sources per FP32 partial block before the compensated fold
 constexpr int kFB = 8;    // frequencies per block of the multi-frequency kernel
 
+// Sources per iteration of the FP32 inner loop (independent pair chains per wave).
+#ifndef RSI_SRC_UNROLL
+#define RSI_SRC_UNROLL 1
+#endif
+
 // Per-target constants of the FP32 path (see rsi_pairsum.hip for the derivation).
 template <int KIND, int TPL>
 struct TargetsF {
@@ -61,8 +66,10 @@ __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const Src
         t = fmaf(T.dmy[u], s.ey, t);
         if constexpr (!PLANAR) t = fmaf(T.dmz[u], s.ez, t);
         const float q = t + s.es2;                           // r^2 - r_ref^2
-        const float r2 = fmaxf(T.rr2[u] + q, kR2MinF);
-        const float ir = __builtin_amdgcn_rsqf(r2);           // 1/r
+        const float r2 = T.rr2[u] + q;
+        // |r^2|: the source modifier of v_rsq is free; r^2 < 0 only by rounding for a
+        // field point on a source, which the FP32 path excludes
+        const float ir = __builtin_amdgcn_rsqf(fabsf(r2));    // 1/r
         const float den = fmaf(r2, ir, T.rr[u]);              // r + r_ref
         const float dr = q * __builtin_amdgcn_rcpf(den);      // r - r_ref
         const float ph = __builtin_amdgcn_fractf(fmaf(dr, ilam, T.p0[u]));  // revolutions
@@ -102,7 +109,7 @@ __device__ __forceinline__ void sum_range_f32(const TargetsF<KIND, TPL> &T,
 #pragma unroll
         for (int u = 0; u < TPL; ++u) are[u] = aim[u] = 0.0f;
         if (je - jb == kSub) {
-#pragma unroll 4
+#pragma unroll RSI_SRC_UNROLL
             for (int jj = 0; jj < kSub; ++jj) pair_f32<KIND, TPL, PLANAR>(T, rec[jb + jj], ilam, k, are, aim);
         } else {
             for (int64_t j = jb; j < je; ++j) pair_f32<KIND, TPL, PLANAR>(T, rec[j], ilam, k, are, aim);

@@ -18,8 +18,6 @@ constexpr double kTwoPi = 6.28318530717958647692;
 // Pairs closer than this contribute nothing in the FP64 path (the kernel is
 // singular on the radiating surface).
 constexpr double kRMin = 1.0e-12;
-// Lower clamp of r^2 in the FP32 path (keeps rsqrt finite; see rsi.h).
-constexpr float kR2MinF = 1.0e-30f;
 
 // Threads per workgroup of the pair-sum kernels (four wave64s).
 constexpr int kBlock = 256;

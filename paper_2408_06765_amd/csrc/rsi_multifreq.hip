@@ -54,8 +54,8 @@ __global__ void __launch_bounds__(kBlock) multifreq_f32_kernel(
             t = fmaf(dmy, s.ey, t);
             if constexpr (!PLANAR) t = fmaf(dmz, s.ez, t);
             const float qq = t + s.es2;
-            const float r2 = fmaxf(rr2 + qq, kR2MinF);
-            const float ir = __builtin_amdgcn_rsqf(r2);
+            const float r2 = rr2 + qq;
+            const float ir = __builtin_amdgcn_rsqf(fabsf(r2));
             const float dr = qq * __builtin_amdgcn_rcpf(fmaf(r2, ir, rr));
             const float phb = __builtin_amdgcn_fractf(fmaf(dr, ilb, p0b));
             const float phd = __builtin_amdgcn_fractf(fmaf(dr, ild, p0d));

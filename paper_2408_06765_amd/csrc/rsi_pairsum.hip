@@ -333,12 +333,12 @@ static int env_int(const char *name, int dflt) {
 }
 
 PairShape default_shape(int64_t n_src, int64_t n_tgt) {
-    static const int tpl_env = env_int("RSI_PAIRSUM_TPL", 2);
-    static const int min_wg = env_int("RSI_PAIRSUM_MIN_WG", 16384);
+    static const int tpl_env = env_int("RSI_PAIRSUM_TPL", 1);
+    static const int min_wg = env_int("RSI_PAIRSUM_MIN_WG", 32768);
     PairShape sh;
-    sh.tpl = (tpl_env == 1 || tpl_env == 4) ? tpl_env : 2;
+    sh.tpl = (tpl_env == 2 || tpl_env == 4) ? tpl_env : 1;
     const int64_t bx = (n_tgt + kBlock * sh.tpl - 1) / (kBlock * sh.tpl);
-    // aim for >= min_wg workgroups (64 per CU: small items balance the CUs at the end
+    // aim for >= min_wg workgroups (128 per CU: small items balance the CUs at the end
     // of the launch) while keeping >= 4096 sources per split
     int64_t splits = (min_wg + bx - 1) / (bx > 0 ? bx : 1);
     const int64_t max_splits = (n_src + 4095) / 4096;

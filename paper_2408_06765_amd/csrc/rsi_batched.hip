@@ -38,6 +38,7 @@ struct InstDev {
 struct PrepDev {
     const double *x, *y, *z, *w, *vel;
     double v0, nx, ny, nz;
+    double lam;  // c / f of the instance (phase offset of complex strengths)
     int64_t n;
     double *partials;  // [kBBoxBlocks * 6]
     double *anchor;    // [4]
@@ -146,8 +147,7 @@ __global__ void __launch_bounds__(256) prep_batched_kernel(const PrepDev *__rest
         r.ey = ey;
         r.ez = ez;
         r.es2 = (float)(dex * dex + dey * dey + dez * dez);
-        r.sre = (float)(scale * sre);
-        r.sim = (float)(scale * sim);
+        polar_strength(scale * sre, scale * sim, p.lam, r.a, r.psil);
         r.h = (float)(p.nx * dex + p.ny * dey + p.nz * dez);
         r.pad = 0.0f;
         p.recf[j] = r;
@@ -343,6 +343,7 @@ static rsi_status build_tables(const rsi_instance *inst, int n_inst, rsi_precisi
         p.w = a.w;
         p.vel = a.vel;
         p.v0 = a.v0;
+        p.lam = a.medium.c / a.freq;
         p.nx = d.nx;
         p.ny = d.ny;
         p.nz = d.nz;

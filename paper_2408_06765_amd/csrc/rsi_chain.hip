@@ -240,8 +240,9 @@ rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, 
         if (prec == RSI_FP32) {
             if (sp.n > 0) {
                 RSI_TRY(bbox_partials(sp, W.bbox[m], s));
+                // real strengths (v0, or zero until set per frequency): no wavelength needed
                 RSI_TRY(prep_sources_f32(sp, w, nullptr, m == 0 ? xd->v0 : 0.0, m == 0 ? nullptr : nz,
-                                         W.bbox[m], W.setf[m], s));
+                                         W.bbox[m], 0.0, W.setf[m], s));
             } else {
                 W.setf[m].n = 0;
             }
@@ -290,7 +291,7 @@ rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, 
             if (prec == RSI_FP32) {
                 if (m > 0)
                     RSI_TRY(set_strength_f32(W.setf[m], ifaces[m - 1].w, W.field[cur], false,
-                                             W.tco[m - 1], s));
+                                             W.tco[m - 1], media[m].c / freqs[f], s));
                 // interface samples lie on their plane (ABI contract): planar kernel
                 RSI_TRY(pairsum_f32(W.setf[m], t, kind, m == 0 ? nullptr : nz, media[m].c, freqs[f],
                                     sh, static_cast<float2 *>(W.partial), static_cast<float2 *>(dst), s,

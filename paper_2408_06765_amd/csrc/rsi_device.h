@@ -53,13 +53,25 @@ __device__ __forceinline__ void setup_targets_f32(TargetsF<KIND, TPL> &T, const 
     }
 }
 
+// Accumulators of one lane's field point.  Monopole: A1 = sum a_j e^{i phi_j}/r_j.
+// Dipole: A1 = sum a_j c_j e^{i phi_j}/r_j^2 and A2 = sum a_j c_j e^{i phi_j}/r_j^3 with
+// c_j = n.(P - Q_j) (1 for planar sources, whose c_j is the field point's height and is
+// applied once at the end), so that the field is c (ik A1 - A2): the factor (ik - 1/r)
+// of eq. 7 splits into a per-target constant ik and one more power of 1/r.
+struct AccF {
+    float r1, i1, r2, i2;
+};
+
 // One source against the lane's TPL targets.  `s` is wave-uniform (SGPRs).  PLANAR:
 // every source lies in the plane z = C_z with normal +z (interface samples), so
 // e_z = 0 and n.e_j = 0, and the z terms drop out.
+//
+// The source strength enters as a signed magnitude a_j and a phase offset psi_j held as
+// the path length psi_j lambda, which is added to r - r_ref by the FMA that finishes
+// the path difference; the complex multiply by the strength disappears.
 template <int KIND, int TPL, bool PLANAR>
 __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const SrcRecF &s,
-                                         float ilam, float k, float (&are)[TPL],
-                                         float (&aim)[TPL]) {
+                                         float ilam, AccF (&A)[TPL]) {
 #pragma unroll
     for (int u = 0; u < TPL; ++u) {
         float t = T.dmx[u] * s.ex;
@@ -71,30 +83,29 @@ __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const Src
         // field point on a source, which the FP32 path excludes
         const float ir = __builtin_amdgcn_rsqf(fabsf(r2));    // 1/r
         const float den = fmaf(r2, ir, T.rr[u]);              // r + r_ref
-        const float dr = q * __builtin_amdgcn_rcpf(den);      // r - r_ref
-        const float ph = __builtin_amdgcn_fractf(fmaf(dr, ilam, T.p0[u]));  // revolutions
+        const float d = fmaf(q, __builtin_amdgcn_rcpf(den), s.psil);  // r - r_ref + psi lambda
+        const float ph = __builtin_amdgcn_fractf(fmaf(d, ilam, T.p0[u]));  // revolutions
         const float cs = __builtin_amdgcn_cosf(ph);
         const float sn = __builtin_amdgcn_sinf(ph);
-        float gr, gi;
+        const float m0 = ir * s.a;                            // a / r
         if constexpr (KIND == RSI_MONOPOLE) {
-            gr = cs * ir;  // e^{ikr}/r
-            gi = sn * ir;
+            A[u].r1 = fmaf(m0, cs, A[u].r1);
+            A[u].i1 = fmaf(m0, sn, A[u].i1);
         } else {
-            const float hh = PLANAR ? T.ht[u] : T.ht[u] - s.h;  // n.(P - Q)
-            const float g2 = hh * ir * ir;                      // cos(theta)/r
-            const float al = -g2 * ir, be = g2 * k;      // cos(theta)(ik - 1/r)/r
-            gr = al * cs - be * sn;
-            gi = fmaf(al, sn, be * cs);
+            float m1 = m0 * ir;                               // a / r^2
+            if constexpr (!PLANAR) m1 *= T.ht[u] - s.h;       // times n.(P - Q)
+            const float m2 = m1 * ir;
+            A[u].r1 = fmaf(m1, cs, A[u].r1);
+            A[u].i1 = fmaf(m1, sn, A[u].i1);
+            A[u].r2 = fmaf(m2, cs, A[u].r2);
+            A[u].i2 = fmaf(m2, sn, A[u].i2);
         }
-        are[u] = fmaf(s.sre, gr, are[u]);
-        are[u] = fmaf(-s.sim, gi, are[u]);
-        aim[u] = fmaf(s.sre, gi, aim[u]);
-        aim[u] = fmaf(s.sim, gr, aim[u]);
     }
 }
 
 // Sum of sources [j0, j1): FP32 blocks of kSub sources folded into a Kahan-compensated
-// running sum (mre, mim with compensation cre, cim).
+// running sum (mre, mim with compensation cre, cim).  For the dipole each block is
+// combined to ik A1 - A2 before the fold, and the planar height is applied at the end.
 template <int KIND, int TPL, bool PLANAR>
 __device__ __forceinline__ void sum_range_f32(const TargetsF<KIND, TPL> &T,
                                               const SrcRecF *__restrict__ rec, int64_t j0,
@@ -105,25 +116,37 @@ __device__ __forceinline__ void sum_range_f32(const TargetsF<KIND, TPL> &T,
     for (int u = 0; u < TPL; ++u) mre[u] = mim[u] = cre[u] = cim[u] = 0.0f;
     for (int64_t jb = j0; jb < j1; jb += kSub) {
         const int64_t je = (jb + kSub < j1) ? jb + kSub : j1;
-        float are[TPL], aim[TPL];
+        AccF A[TPL];
 #pragma unroll
-        for (int u = 0; u < TPL; ++u) are[u] = aim[u] = 0.0f;
+        for (int u = 0; u < TPL; ++u) A[u].r1 = A[u].i1 = A[u].r2 = A[u].i2 = 0.0f;
         if (je - jb == kSub) {
 #pragma unroll RSI_SRC_UNROLL
-            for (int jj = 0; jj < kSub; ++jj) pair_f32<KIND, TPL, PLANAR>(T, rec[jb + jj], ilam, k, are, aim);
+            for (int jj = 0; jj < kSub; ++jj) pair_f32<KIND, TPL, PLANAR>(T, rec[jb + jj], ilam, A);
         } else {
-            for (int64_t j = jb; j < je; ++j) pair_f32<KIND, TPL, PLANAR>(T, rec[j], ilam, k, are, aim);
+            for (int64_t j = jb; j < je; ++j) pair_f32<KIND, TPL, PLANAR>(T, rec[j], ilam, A);
         }
 #pragma unroll
         for (int u = 0; u < TPL; ++u) {
-            float y = are[u] - cre[u];
+            float br = A[u].r1, bi = A[u].i1;
+            if constexpr (KIND == RSI_DIPOLE) {  // ik A1 - A2
+                br = fmaf(-k, A[u].i1, -A[u].r2);
+                bi = fmaf(k, A[u].r1, -A[u].i2);
+            }
+            float y = br - cre[u];
             float t = mre[u] + y;
             cre[u] = (t - mre[u]) - y;
             mre[u] = t;
-            y = aim[u] - cim[u];
+            y = bi - cim[u];
             t = mim[u] + y;
             cim[u] = (t - mim[u]) - y;
             mim[u] = t;
+        }
+    }
+    if constexpr (KIND == RSI_DIPOLE && PLANAR) {
+#pragma unroll
+        for (int u = 0; u < TPL; ++u) {
+            mre[u] *= T.ht[u];
+            mim[u] *= T.ht[u];
         }
     }
 }

@@ -104,12 +104,32 @@ private:
 // ---------------------------------------------------------------------------
 // FP32 source records.  One record per source, read by wave-uniform (scalar)
 // loads: offsets from the set's anchor, |offset|^2, the folded strength
-// -(1/2pi) w_j s_j, and the normal offset n.e_j used by the dipole.
+// s'_j = -(1/2pi) w_j s_j in polar form, and the normal offset n.e_j used by the
+// dipole.  The strength is s'_j = a e^{2 pi i psi} with psi in (-1/4, 1/4]
+// revolutions and a signed, stored as a and the length psi lambda (metres, lambda =
+// c / f of the stage), so a real strength of either sign has psil = 0 at every
+// frequency.
 // ---------------------------------------------------------------------------
 struct alignas(32) SrcRecF {
     float ex, ey, ez, es2;
-    float sre, sim, h, pad;
+    float a, psil, h, pad;
 };
+
+// Polar form of a folded strength (sre + i sim) for wavelength lam.
+__device__ inline void polar_strength(double sre, double sim, double lam, float &a,
+                                      float &psil) {
+    double m = hypot(sre, sim);
+    double psi = atan2(sim, sre) / kTwoPi;  // (-1/2, 1/2]
+    if (psi > 0.25) {
+        psi -= 0.5;
+        m = -m;
+    } else if (psi <= -0.25) {
+        psi += 0.5;
+        m = -m;
+    }
+    a = (float)m;
+    psil = (float)(psi * lam);
+}
 
 // FP64 source records: absolute coordinates and folded strength.
 struct alignas(64) SrcRecD {
@@ -143,11 +163,12 @@ struct PairShape {
 rsi_status bbox_partials(const rsi_points &pts, double *partials /*[kBBoxBlocks*6]*/,
                          hipStream_t s);
 constexpr int kBBoxBlocks = 64;
+// lam = c / f of the stage: needed only for complex strengths (vel != NULL)
 rsi_status prep_sources_f32(const rsi_points &pts, const double *w, const double *vel,
                             double v0, const double *normal, const double *partials,
-                            SrcSetF &set, hipStream_t s);
+                            double lam, SrcSetF &set, hipStream_t s);
 rsi_status set_strength_f32(SrcSetF &set, const double *w, const void *field, bool field_fp64,
-                            const double *tco, hipStream_t s);
+                            const double *tco, double lam, hipStream_t s);
 rsi_status prep_sources_f64(const rsi_points &pts, const double *w, const double *vel,
                             double v0, SrcSetD &set, hipStream_t s);
 rsi_status set_strength_f64(SrcSetD &set, const double *w, const double *field,

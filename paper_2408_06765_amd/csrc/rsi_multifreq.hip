@@ -8,7 +8,9 @@
 // step) are evaluated once per block of kFB frequencies; each further frequency costs a
 // complex rotation and the complex multiply-accumulate with that frequency's strength.
 // The strengths of one source for a frequency block are contiguous (source-major,
-// frequency-minor), so a wave reads them with one wave-uniform load.
+// frequency-minor), so a wave reads them with one wave-uniform load.  SHARED_S: one
+// real strength per source for every frequency (the transducer stage), taken from the
+// record's signed magnitude; its phase offset is zero for real strengths.
 #include <cmath>
 
 #include "rsi_device.h"
@@ -65,27 +67,25 @@ __global__ void __launch_bounds__(kBlock) multifreq_f32_kernel(
                 const float hh = PLANAR ? ht : ht - s.h;
                 amp = hh * ir * ir;  // cos(theta)/r, times (ik - 1/r) per frequency below
             }
+            if constexpr (SHARED_S) amp *= s.a;  // one real strength for every frequency
             float er = __builtin_amdgcn_cosf(phb) * amp, ei = __builtin_amdgcn_sinf(phb) * amp;
 #pragma unroll
             for (int q = 0; q < kFB; ++q) {
-                float sre, sim;
-                if constexpr (SHARED_S) {
-                    sre = s.sre;
-                    sim = s.sim;
-                } else {
-                    const float2 sv = S[j * nf_pad + q0 + q];
-                    sre = sv.x;
-                    sim = sv.y;
-                }
                 float gr = er, gi = ei;
                 if constexpr (KIND == RSI_DIPOLE) {
                     gr = -ir * er - kq[q] * ei;
                     gi = fmaf(kq[q], er, -ir * ei);
                 }
-                are[q] = fmaf(sre, gr, are[q]);
-                are[q] = fmaf(-sim, gi, are[q]);
-                aim[q] = fmaf(sre, gi, aim[q]);
-                aim[q] = fmaf(sim, gr, aim[q]);
+                if constexpr (SHARED_S) {
+                    are[q] += gr;
+                    aim[q] += gi;
+                } else {
+                    const float2 sv = S[j * nf_pad + q0 + q];
+                    are[q] = fmaf(sv.x, gr, are[q]);
+                    are[q] = fmaf(-sv.y, gi, are[q]);
+                    aim[q] = fmaf(sv.x, gi, aim[q]);
+                    aim[q] = fmaf(sv.y, gr, aim[q]);
+                }
                 if (q + 1 < kFB) {  // advance to the next frequency: multiply by e^{i dk r}
                     const float nr = er * cd - ei * sd;
                     ei = fmaf(er, sd, ei * cd);

@@ -93,7 +93,7 @@ rsi_status bbox_partials(const rsi_points &pts, double *partials, hipStream_t s)
 __global__ void __launch_bounds__(256) prep_f32_kernel(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ w, const double *__restrict__ vel,
-    double v0, double nx, double ny, double nz, const double *__restrict__ partials,
+    double v0, double nx, double ny, double nz, double lam, const double *__restrict__ partials,
     double *__restrict__ anchor_out, SrcRecF *__restrict__ rec) {
     double ax, ay, az;
     anchor_from_partials(partials, ax, ay, az);
@@ -118,8 +118,7 @@ __global__ void __launch_bounds__(256) prep_f32_kernel(
     r.ey = ey;
     r.ez = ez;
     r.es2 = (float)(dex * dex + dey * dey + dez * dez);
-    r.sre = (float)(scale * sre);
-    r.sim = (float)(scale * sim);
+    polar_strength(scale * sre, scale * sim, lam, r.a, r.psil);
     r.h = (float)(nx * dex + ny * dey + nz * dez);
     r.pad = 0.0f;
     rec[j] = r;
@@ -130,7 +129,7 @@ template <typename FieldT>
 __global__ void __launch_bounds__(256) strength_f32_kernel(int64_t n, const double *__restrict__ w,
                                                            const FieldT *__restrict__ field,
                                                            const double *__restrict__ tco,
-                                                           SrcRecF *__restrict__ rec) {
+                                                           double lam, SrcRecF *__restrict__ rec) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     const double fre = field[2 * j], fim = field[2 * j + 1];
@@ -141,8 +140,10 @@ __global__ void __launch_bounds__(256) strength_f32_kernel(int64_t n, const doub
         sim = tre * fim + tim * fre;
     }
     const double scale = -w[j] / kTwoPi;
-    rec[j].sre = (float)(scale * sre);
-    rec[j].sim = (float)(scale * sim);
+    float a, psil;
+    polar_strength(scale * sre, scale * sim, lam, a, psil);
+    rec[j].a = a;
+    rec[j].psil = psil;
 }
 
 __global__ void __launch_bounds__(256) prep_f64_kernel(int64_t n, const double *__restrict__ x,
@@ -203,26 +204,26 @@ static void unit_normal(const double *normal, double &nx, double &ny, double &nz
 
 rsi_status prep_sources_f32(const rsi_points &pts, const double *w, const double *vel,
                             double v0, const double *normal, const double *partials,
-                            SrcSetF &set, hipStream_t s) {
+                            double lam, SrcSetF &set, hipStream_t s) {
     double nx, ny, nz;
     unit_normal(normal, nx, ny, nz);
     set.n = pts.n;
     if (pts.n == 0) return RSI_OK;
     hipLaunchKernelGGL(prep_f32_kernel, dim3(blocks_for(pts.n)), dim3(256), 0, s, pts.n, pts.x,
-                       pts.y, pts.z, w, vel, v0, nx, ny, nz, partials, set.anchor, set.rec);
+                       pts.y, pts.z, w, vel, v0, nx, ny, nz, lam, partials, set.anchor, set.rec);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }
 
 rsi_status set_strength_f32(SrcSetF &set, const double *w, const void *field, bool field_fp64,
-                            const double *tco, hipStream_t s) {
+                            const double *tco, double lam, hipStream_t s) {
     if (set.n == 0) return RSI_OK;
     if (field_fp64)
         hipLaunchKernelGGL(strength_f32_kernel<double>, dim3(blocks_for(set.n)), dim3(256), 0, s,
-                           set.n, w, static_cast<const double *>(field), tco, set.rec);
+                           set.n, w, static_cast<const double *>(field), tco, lam, set.rec);
     else
         hipLaunchKernelGGL(strength_f32_kernel<float>, dim3(blocks_for(set.n)), dim3(256), 0, s,
-                           set.n, w, static_cast<const float *>(field), tco, set.rec);
+                           set.n, w, static_cast<const float *>(field), tco, lam, set.rec);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }
@@ -488,7 +489,7 @@ extern "C" rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_
             RSI_TRY(scratch.alloc(&set.anchor, 4));
             RSI_TRY(scratch.alloc(&partials, kBBoxBlocks * 6));
             RSI_TRY(bbox_partials(*src, partials, s));
-            RSI_TRY(prep_sources_f32(*src, src_w, src_vel, 0.0, normal, partials, set, s));
+            RSI_TRY(prep_sources_f32(*src, src_w, src_vel, 0.0, normal, partials, medium.c / freq, set, s));
         }
         if (nslots > 0) RSI_TRY(scratch.alloc(&partial, (size_t)nslots));
         return pairsum_f32(set, t, kind, normal, medium.c, freq, sh, partial,

@@ -129,10 +129,11 @@ __global__ void __launch_bounds__(256) prep_batched_kernel(const PrepDev *__rest
         const double ax = 0.5 * (lo[0] + hi[0]), ay = 0.5 * (lo[1] + hi[1]),
                      az = 0.5 * (lo[2] + hi[2]);
         if (j == 0) {
+            const double sx = hi[0] - lo[0], sy = hi[1] - lo[1], sz = hi[2] - lo[2];
             p.anchor[0] = ax;
             p.anchor[1] = ay;
             p.anchor[2] = az;
-            p.anchor[3] = 0.0;
+            p.anchor[3] = 0.5 * sqrt(sx * sx + sy * sy + sz * sz);  // bounds |Q_j - C|
         }
         if (j >= p.n) return;
         if (p.vel) {
@@ -161,7 +162,12 @@ __device__ __forceinline__ void run_item_f32(const InstDev &I, const WorkItem &w
     setup_targets_f32<KIND, TPL>(T, I.tx, I.ty, I.tz, I.n_tgt, tbase, I.anchor[0], I.anchor[1],
                                  I.anchor[2], I.inv_lam, I.nx, I.ny, I.nz);
     float mre[TPL], mim[TPL];
-    sum_range_f32<KIND, TPL, false>(T, I.recf, w.j0, w.j1, (float)I.inv_lam, (float)I.k, mre, mim);
+    if (phase_in_sin_range(I.anchor[3], I.inv_lam))
+        sum_range_f32<KIND, TPL, false, false>(T, I.recf, w.j0, w.j1, (float)I.inv_lam, (float)I.k,
+                                               mre, mim);
+    else
+        sum_range_f32<KIND, TPL, false, true>(T, I.recf, w.j0, w.j1, (float)I.inv_lam, (float)I.k,
+                                              mre, mim);
     float2 *o = I.n_chunks > 1 ? static_cast<float2 *>(I.partial) + (int64_t)w.chunk * I.n_tgt
                                : static_cast<float2 *>(I.out);
 #pragma unroll

@@ -18,6 +18,16 @@ constexpr int kFB = 8;    // frequencies per block of the multi-frequency kernel
 #define RSI_SRC_UNROLL 1
 #endif
 
+// The phase argument p_ref + (r - r_ref + psi lambda)/lambda lies within 1 + R/lambda + 1/4
+// revolutions of zero (|r - r_ref| <= |Q_j - C| <= R, the set's half diagonal).
+// v_sin_f32 / v_cos_f32 take revolutions and reduce arguments up to 256 in magnitude
+// themselves (measured on gfx950: max abs error 1.22e-7 over [-256, 256], the same as
+// over [-1, 1]), so below that bound the explicit fract is dropped.  The FMA result is
+// rounded at the argument's magnitude in both cases, so the values are the same.
+__device__ __forceinline__ bool phase_in_sin_range(double radius, double inv_lam) {
+    return radius * inv_lam < 250.0;
+}
+
 // Per-target constants of the FP32 path (see rsi_pairsum.hip for the derivation).
 template <int KIND, int TPL>
 struct TargetsF {
@@ -69,7 +79,7 @@ struct AccF {
 // The source strength enters as a signed magnitude a_j and a phase offset psi_j held as
 // the path length psi_j lambda, which is added to r - r_ref by the FMA that finishes
 // the path difference; the complex multiply by the strength disappears.
-template <int KIND, int TPL, bool PLANAR>
+template <int KIND, int TPL, bool PLANAR, bool FRACT>
 __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const SrcRecF &s,
                                          float ilam, AccF (&A)[TPL]) {
 #pragma unroll
@@ -84,7 +94,8 @@ __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const Src
         const float ir = __builtin_amdgcn_rsqf(fabsf(r2));    // 1/r
         const float den = fmaf(r2, ir, T.rr[u]);              // r + r_ref
         const float d = fmaf(q, __builtin_amdgcn_rcpf(den), s.psil);  // r - r_ref + psi lambda
-        const float ph = __builtin_amdgcn_fractf(fmaf(d, ilam, T.p0[u]));  // revolutions
+        float ph = fmaf(d, ilam, T.p0[u]);  // revolutions
+        if constexpr (FRACT) ph = __builtin_amdgcn_fractf(ph);
         const float cs = __builtin_amdgcn_cosf(ph);
         const float sn = __builtin_amdgcn_sinf(ph);
         const float m0 = ir * s.a;                            // a / r
@@ -106,7 +117,7 @@ __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const Src
 // Sum of sources [j0, j1): FP32 blocks of kSub sources folded into a Kahan-compensated
 // running sum (mre, mim with compensation cre, cim).  For the dipole each block is
 // combined to ik A1 - A2 before the fold, and the planar height is applied at the end.
-template <int KIND, int TPL, bool PLANAR>
+template <int KIND, int TPL, bool PLANAR, bool FRACT>
 __device__ __forceinline__ void sum_range_f32(const TargetsF<KIND, TPL> &T,
                                               const SrcRecF *__restrict__ rec, int64_t j0,
                                               int64_t j1, float ilam, float k,
@@ -121,9 +132,9 @@ __device__ __forceinline__ void sum_range_f32(const TargetsF<KIND, TPL> &T,
         for (int u = 0; u < TPL; ++u) A[u].r1 = A[u].i1 = A[u].r2 = A[u].i2 = 0.0f;
         if (je - jb == kSub) {
 #pragma unroll RSI_SRC_UNROLL
-            for (int jj = 0; jj < kSub; ++jj) pair_f32<KIND, TPL, PLANAR>(T, rec[jb + jj], ilam, A);
+            for (int jj = 0; jj < kSub; ++jj) pair_f32<KIND, TPL, PLANAR, FRACT>(T, rec[jb + jj], ilam, A);
         } else {
-            for (int64_t j = jb; j < je; ++j) pair_f32<KIND, TPL, PLANAR>(T, rec[j], ilam, A);
+            for (int64_t j = jb; j < je; ++j) pair_f32<KIND, TPL, PLANAR, FRACT>(T, rec[j], ilam, A);
         }
 #pragma unroll
         for (int u = 0; u < TPL; ++u) {

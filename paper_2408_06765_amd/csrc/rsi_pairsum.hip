@@ -67,8 +67,9 @@ __global__ void __launch_bounds__(256) bbox_kernel(const double *__restrict__ x,
     }
 }
 
+// Anchor C = centre of the bounding box, and its half diagonal, which bounds |Q_j - C|.
 __device__ inline void anchor_from_partials(const double *__restrict__ partials, double &ax,
-                                            double &ay, double &az) {
+                                            double &ay, double &az, double &radius) {
     double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
     for (int b = 0; b < kBBoxBlocks; ++b)
         for (int k = 0; k < 3; ++k) {
@@ -78,6 +79,8 @@ __device__ inline void anchor_from_partials(const double *__restrict__ partials,
     ax = 0.5 * (lo[0] + hi[0]);
     ay = 0.5 * (lo[1] + hi[1]);
     az = 0.5 * (lo[2] + hi[2]);
+    const double sx = hi[0] - lo[0], sy = hi[1] - lo[1], sz = hi[2] - lo[2];
+    radius = 0.5 * sqrt(sx * sx + sy * sy + sz * sz);
 }
 
 rsi_status bbox_partials(const rsi_points &pts, double *partials, hipStream_t s) {
@@ -95,13 +98,13 @@ __global__ void __launch_bounds__(256) prep_f32_kernel(
     const double *__restrict__ z, const double *__restrict__ w, const double *__restrict__ vel,
     double v0, double nx, double ny, double nz, double lam, const double *__restrict__ partials,
     double *__restrict__ anchor_out, SrcRecF *__restrict__ rec) {
-    double ax, ay, az;
-    anchor_from_partials(partials, ax, ay, az);
+    double ax, ay, az, radius;
+    anchor_from_partials(partials, ax, ay, az, radius);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         anchor_out[0] = ax;
         anchor_out[1] = ay;
         anchor_out[2] = az;
-        anchor_out[3] = 0.0;
+        anchor_out[3] = radius;
     }
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
@@ -263,7 +266,10 @@ __global__ void __launch_bounds__(kBlock) pairsum_f32_kernel(
     const int64_t j0 = (int64_t)blockIdx.y * chunk;
     const int64_t j1 = (j0 + chunk < n_src) ? j0 + chunk : n_src;
     float mre[TPL], mim[TPL];
-    sum_range_f32<KIND, TPL, PLANAR>(T, rec, j0, j1, (float)inv_lam, k, mre, mim);
+    if (phase_in_sin_range(anchor[3], inv_lam))
+        sum_range_f32<KIND, TPL, PLANAR, false>(T, rec, j0, j1, (float)inv_lam, k, mre, mim);
+    else
+        sum_range_f32<KIND, TPL, PLANAR, true>(T, rec, j0, j1, (float)inv_lam, k, mre, mim);
     float2 *o = out + (int64_t)blockIdx.y * n_tgt;
 #pragma unroll
     for (int u = 0; u < TPL; ++u) {

@@ -140,6 +140,24 @@ def test_high_frequency_phase_accuracy(gpu, orc):
     assert rel(got, ref) <= 1e-4
 
 
+@pytest.mark.parametrize("f", [12.0e6, 14.0e6])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_phase_argument_on_both_sides_of_sin_range(gpu, orc, f, flags):
+    """The FP32 kernels skip the explicit fract of the phase when the source set's half
+    diagonal R satisfies R f / c < 250 revolutions: a 40 mm square in water has
+    R f / c ~ 230 at 12 MHz and ~ 270 at 14 MHz, one case on each side."""
+    src = W.random_cloud(41, 20000, (0.0, 0.0, 0.0), (0.02, 0.02, 0.0))
+    tgt = W.random_cloud(42, 700, (0.0, 0.0, 0.045), (0.02, 0.02, 0.015))
+    s = W.random_complex(43, 20000)
+    w = W.random_weights(44, 20000)
+    half_diag = 0.5 * math.sqrt(sum((float(np.ptp(v))) ** 2 for v in src))
+    assert (half_diag * f / 1480.0 < 250.0) == (f < 13e6)
+    ref = orc.propagate(1, src, w, s, tgt, 1480.0, f, normal=(0, 0, 1))
+    got = host(gpu.rsi_propagate_ex(devpts(src), dev(w), dev(s), devpts(tgt), 1480.0, f, 1, 0, flags,
+                                    normal=(0, 0, 1)))
+    assert rel(got, ref) <= 1e-4
+
+
 # ----------------------------------------------------------------------------- a5
 def _small_chain(orc, n_if_pts, ifaces_z, media, tilt, n_tgt, seed=0):
     a = W.PISTON_RADIUS

@@ -79,8 +79,8 @@ struct AccF {
 // The source strength enters as a signed magnitude a_j and a phase offset psi_j held as
 // the path length psi_j lambda, which is added to r - r_ref by the FMA that finishes
 // the path difference; the complex multiply by the strength disappears.
-template <int KIND, int TPL, bool PLANAR, bool FRACT>
-__device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const SrcRecF &s,
+template <int KIND, int TPL, bool PLANAR, bool FRACT, class Rec>
+__device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const Rec &s,
                                          float ilam, AccF (&A)[TPL]) {
 #pragma unroll
     for (int u = 0; u < TPL; ++u) {
@@ -114,14 +114,20 @@ __device__ __forceinline__ void pair_f32(const TargetsF<KIND, TPL> &T, const Src
     }
 }
 
+// Source records are read through the constant address space: no kernel writes them,
+// and loads from that space may go through the scalar cache, so a wave-uniform record
+// index gives s_load even when the pointer itself came from memory (batched items).
+typedef const __attribute__((address_space(4))) SrcRecF *SrcRecConstPtr;
+
 // Sum of sources [j0, j1): FP32 blocks of kSub sources folded into a Kahan-compensated
 // running sum (mre, mim with compensation cre, cim).  For the dipole each block is
 // combined to ik A1 - A2 before the fold, and the planar height is applied at the end.
 template <int KIND, int TPL, bool PLANAR, bool FRACT>
 __device__ __forceinline__ void sum_range_f32(const TargetsF<KIND, TPL> &T,
-                                              const SrcRecF *__restrict__ rec, int64_t j0,
+                                              const SrcRecF *recs, int64_t j0,
                                               int64_t j1, float ilam, float k,
                                               float (&mre)[TPL], float (&mim)[TPL]) {
+    const SrcRecConstPtr rec = (SrcRecConstPtr)recs;
     float cre[TPL], cim[TPL];
 #pragma unroll
     for (int u = 0; u < TPL; ++u) mre[u] = mim[u] = cre[u] = cim[u] = 0.0f;

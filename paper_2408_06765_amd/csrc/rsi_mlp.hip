@@ -30,12 +30,15 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTileM = 64, kTileN = 64, kTileK = 32;
+constexpr int kTileK = 32;  // K step of the GEMM (one MFMA)
 constexpr int kMaxLayers = 16;
 
-__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware reciprocal (1 ulp in FP32; the results are
+// rounded to bfloat16 next).  exp(-z) = inf for very negative z gives s = 0 as it should.
+__device__ inline float sigmoid_f(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ inline float silu_f(float z) { return z * sigmoid_f(z); }
 __device__ inline float silu_grad_f(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigmoid_f(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -57,38 +60,88 @@ struct GemmArgs {
     float *P;           // EPI_DW: partials [split][M][N]
 };
 
-template <int EPI>
+// NT GEMM on one workgroup tile BM x BN: four waves in a 2 x 2 grid, each computing a
+// (BM/2) x (BN/2) block as (BM/32) x (BN/32) MFMA fragments of 16 x 16.  K advances in
+// steps of 32 (one MFMA): both operand slices are staged in LDS (rows padded to 40
+// bfloat16 = 80 bytes, so the 16 lanes that read one 16-byte column chunk of 16 rows
+// hit 16 disjoint bank quadruples), double-buffered, with the global loads of step k+1
+// issued before the MFMAs of step k.
+template <int EPI, int BM, int BN>
 __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t m0 = (int64_t)blockIdx.x * kTileM + (wave >> 1) * 32;
-    const int64_t n0 = (int64_t)blockIdx.y * kTileN + (wave & 1) * 32;
+    constexpr int BK = 32, LDK = BK + 8;
+    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+    constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;  // 16-byte chunks per thread
+    static_assert(CA >= 1 && CB >= 1, "tile too small for 256 threads");
+    __shared__ __attribute__((aligned(16))) bf16 sA[2][BM][LDK];
+    __shared__ __attribute__((aligned(16))) bf16 sB[2][BN][LDK];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
     const int64_t kb = (int64_t)blockIdx.z * g.k_per_split;
     const int64_t ke = (kb + g.k_per_split < g.K) ? kb + g.k_per_split : g.K;
+    const int nk = (int)((ke - kb) / BK);
+    bf16x8 ra[CA], rb[CB];
+    auto gload = [&](int64_t k) {
+#pragma unroll
+        for (int i = 0; i < CA; ++i) {
+            const int c = tid + 256 * i;
+            ra[i] = *reinterpret_cast<const bf16x8 *>(g.A + (m0 + (c >> 2)) * g.lda + k + (c & 3) * 8);
+        }
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            const int c = tid + 256 * i;
+            rb[i] = *reinterpret_cast<const bf16x8 *>(g.B + (n0 + (c >> 2)) * g.ldb + k + (c & 3) * 8);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < CA; ++i) {
+            const int c = tid + 256 * i;
+            *reinterpret_cast<bf16x8 *>(&sA[buf][c >> 2][(c & 3) * 8]) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            const int c = tid + 256 * i;
+            *reinterpret_cast<bf16x8 *>(&sB[buf][c >> 2][(c & 3) * 8]) = rb[i];
+        }
+    };
+    f32x4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const int r = lane & 15, kq = (lane >> 4) * 8;
-    f32x4 acc[2][2];
+    if (nk > 0) {
+        gload(kb);
+        sstore(0);
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) gload(kb + (int64_t)(kt + 1) * BK);
+        bf16x8 af[FM], bfr[FN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < FM; ++i)
+            af[i] = *reinterpret_cast<const bf16x8 *>(&sA[buf][wm * WM + 16 * i + r][kq]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const bf16 *pa0 = g.A + (m0 + r) * g.lda + kq, *pa1 = pa0 + 16 * g.lda;
-    const bf16 *pb0 = g.B + (n0 + r) * g.ldb + kq, *pb1 = pb0 + 16 * g.ldb;
-    for (int64_t k = kb; k < ke; k += kTileK) {
-        const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(pa0 + k);
-        const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(pa1 + k);
-        const bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(pb0 + k);
-        const bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(pb1 + k);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        for (int j = 0; j < FN; ++j)
+            bfr[j] = *reinterpret_cast<const bf16x8 *>(&sB[buf][wn * WN + 16 * j + r][kq]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        // the other buffer was last read before the barrier that ended step kt - 1
+        if (kt + 1 < nk) sstore(buf ^ 1);
+        __syncthreads();
     }
     const int cn = lane & 15, cm = (lane >> 4) * 4;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int64_t n = n0 + 16 * j + cn;
-            const int64_t mb = m0 + 16 * i + cm;
+        for (int j = 0; j < FN; ++j) {
+            const int64_t n = n0 + wn * WN + 16 * j + cn;
+            const int64_t mb = m0 + wm * WM + 16 * i + cm;
             if constexpr (EPI == EPI_DW) {
                 float *p = g.P + (int64_t)blockIdx.z * g.M * g.N;
 #pragma unroll
@@ -120,27 +173,35 @@ struct Box {
     double lo[5], inv[5];  // v = 2 (q - lo) * inv - 1, inv = 1 / (hi - lo)
 };
 
+// One thread: 8 consecutive features of one row (16-byte stores of sin and of cos);
+// block = (m/8) x (256 / (m/8)) threads, rows past n get u = 0.
 __global__ void __launch_bounds__(256) features_kernel(int64_t n, int64_t Mp, int m,
                                                        const float *__restrict__ q, Box box,
                                                        const float *__restrict__ Bff,
                                                        bf16 *__restrict__ H0, int64_t ld) {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= Mp * m) return;
-    const int64_t b = g / m;
-    const int j = (int)(g - b * m);
-    // u and its reduction to one revolution in FP64: the bf16 features then round the
-    // same values the FP64 reference rounds (|u| reaches tens of revolutions)
-    double u = 0.0;
-    if (b < n) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+    if (b >= Mp) return;
+    const int j0 = threadIdx.x * 8;
+    // v and u = B v, and u's reduction to one revolution, in FP64: the bf16 features then
+    // round the same values the FP64 reference rounds (|u| reaches tens of revolutions)
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool live = b < n;
+    if (live)
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            const double v = 2.0 * ((double)q[b * 5 + c] - box.lo[c]) * box.inv[c] - 1.0;
-            u = fma((double)Bff[j * 5 + c], v, u);
-        }
+        for (int c = 0; c < 5; ++c) v[c] = 2.0 * ((double)q[b * 5 + c] - box.lo[c]) * box.inv[c] - 1.0;
+    bf16x8 hs, hc;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        double u = 0.0;
+        if (live)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) u = fma((double)Bff[(j0 + t) * 5 + c], v[c], u);
+        const float ph = (float)(u - floor(u));  // sin(2 pi u): revolutions
+        hs[t] = (bf16)__builtin_amdgcn_sinf(ph);
+        hc[t] = (bf16)__builtin_amdgcn_cosf(ph);
     }
-    const float ph = (float)(u - floor(u));  // sin(2 pi u): revolutions
-    H0[b * ld + j] = (bf16)__builtin_amdgcn_sinf(ph);
-    H0[b * ld + m + j] = (bf16)__builtin_amdgcn_cosf(ph);
+    *reinterpret_cast<bf16x8 *>(H0 + b * ld + j0) = hs;
+    *reinterpret_cast<bf16x8 *>(H0 + b * ld + m + j0) = hc;
 }
 
 // bf16 transpose [R][C] -> [C][R] through LDS, 64 x 64 tiles.
@@ -154,98 +215,119 @@ __global__ void __launch_bounds__(256) transpose_bf16_kernel(const bf16 *__restr
     for (int cc = ty; cc < 64; cc += 4) out[(c0 + cc) * R + r0 + tx] = tile[tx][cc];
 }
 
-// Output layer (FP32), loss and its gradient, one wave per row.  Training when t != NULL:
-// dZ_L = bf16((dy Wo) * silu'(Z_L)), per-block partial sums of dWo, dbo and the loss.
-__global__ void __launch_bounds__(256) head_kernel(int64_t n, int W, const bf16 *__restrict__ H,
-                                                   const float *__restrict__ Z,
-                                                   const float *__restrict__ Wo,
-                                                   const float *__restrict__ bo,
-                                                   const float *__restrict__ t, float *__restrict__ y,
-                                                   bf16 *__restrict__ dZ, float *__restrict__ part) {
-    constexpr int kMaxPerLane = 16;  // W <= 1024
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int per = W / 64;
-    float gw0[kMaxPerLane], gw1[kMaxPerLane];
-    for (int q = 0; q < per; ++q) gw0[q] = gw1[q] = 0.0f;
-    float gb0 = 0.0f, gb1 = 0.0f, loss = 0.0f;
-    for (int rr = 0; rr < 16; ++rr) {
-        const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + rr;
-        float hv[kMaxPerLane];
-        float y0 = 0.0f, y1 = 0.0f;
-        for (int q = 0; q < per; ++q) {
-            const int f = lane + 64 * q;
-            hv[q] = (float)H[row * W + f];
-            y0 = fmaf(Wo[f], hv[q], y0);
-            y1 = fmaf(Wo[W + f], hv[q], y1);
-        }
+// Output layer (FP32), one thread per row: y = Wo h + bo.  Training (t != NULL): the
+// row's loss and output gradient dy = (y - t)/n go to dyl [Mp][3] (0 for padding rows)
+// and dZ_L = bf16((dy Wo) * silu'(Z_L)).  Wo is read through the constant address space
+// (scalar loads: every lane uses the same weights).
+typedef const __attribute__((address_space(4))) float *ConstF;
+
+__global__ void __launch_bounds__(256) head_kernel(int64_t n, int64_t Mp, int W,
+                                                   const bf16 *__restrict__ H,
+                                                   const float *__restrict__ Z, const float *Wo_,
+                                                   const float *bo_, const float *__restrict__ t,
+                                                   float *__restrict__ y, bf16 *__restrict__ dZ,
+                                                   float *__restrict__ dyl) {
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= Mp) return;
+    const ConstF Wo = (ConstF)Wo_, bo = (ConstF)bo_;
+    const bf16 *h = H + row * W;
+    float y0 = 0.0f, y1 = 0.0f;
+    for (int f = 0; f < W; f += 8) {
+        const bf16x8 hv = *reinterpret_cast<const bf16x8 *>(h + f);
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            y0 += __shfl_xor(y0, off);
-            y1 += __shfl_xor(y1, off);
+        for (int u = 0; u < 8; ++u) {
+            y0 = fmaf(Wo[f + u], (float)hv[u], y0);
+            y1 = fmaf(Wo[W + f + u], (float)hv[u], y1);
         }
-        y0 += bo[0];
-        y1 += bo[1];
-        if (row < n && lane == 0 && y) {
-            y[2 * row] = y0;
-            y[2 * row + 1] = y1;
-        }
-        if (!t) continue;
-        float d0 = 0.0f, d1 = 0.0f;
-        if (row < n) {
-            const float e0 = y0 - t[2 * row], e1 = y1 - t[2 * row + 1];
-            d0 = e0 / (float)n;
-            d1 = e1 / (float)n;
-            loss += 0.5f * (e0 * e0 + e1 * e1) / (float)n;
-        }
-        gb0 += d0;
-        gb1 += d1;
-        for (int q = 0; q < per; ++q) {
-            const int f = lane + 64 * q;
-            gw0[q] = fmaf(d0, hv[q], gw0[q]);
-            gw1[q] = fmaf(d1, hv[q], gw1[q]);
-            const float dh = d0 * Wo[f] + d1 * Wo[W + f];
-            dZ[row * W + f] = (bf16)(dh * silu_grad_f(Z[row * W + f]));
-        }
+    }
+    y0 += bo[0];
+    y1 += bo[1];
+    const bool live = row < n;
+    if (live && y) {
+        y[2 * row] = y0;
+        y[2 * row + 1] = y1;
     }
     if (!t) return;
-    // block partials: [2W] weight grads, [2] bias grads, [1] loss (fixed-order sums)
-    __shared__ float sh[4][2 * 1024 + 3];
-    for (int q = 0; q < per; ++q) {
-        sh[wave][lane + 64 * q] = gw0[q];
-        sh[wave][W + lane + 64 * q] = gw1[q];
+    float d0 = 0.0f, d1 = 0.0f, loss = 0.0f;
+    if (live) {
+        const float e0 = y0 - t[2 * row], e1 = y1 - t[2 * row + 1];
+        d0 = e0 / (float)n;
+        d1 = e1 / (float)n;
+        loss = 0.5f * (e0 * e0 + e1 * e1) / (float)n;
     }
-    if (lane == 0) {
-        sh[wave][2 * W] = gb0;
-        sh[wave][2 * W + 1] = gb1;
-        sh[wave][2 * W + 2] = loss;
+    dyl[3 * row] = d0;
+    dyl[3 * row + 1] = d1;
+    dyl[3 * row + 2] = loss;
+    const float *z = Z + row * W;
+    bf16 *dz = dZ + row * W;
+    for (int f = 0; f < W; f += 8) {
+        bf16x8 o;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float dh = d0 * Wo[f + u] + d1 * Wo[W + f + u];
+            o[u] = (bf16)(dh * silu_grad_f(z[f + u]));
+        }
+        *reinterpret_cast<bf16x8 *>(dz + f) = o;
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < 2 * W + 3; idx += 256)
-        part[(int64_t)blockIdx.x * (2 * W + 3) + idx] =
-            ((sh[0][idx] + sh[1][idx]) + sh[2][idx]) + sh[3][idx];
 }
 
-// Fixed-order column sums: out[c] = sum_r in[r * ld + c] (r < R), accumulated in FP64.
+// Head gradients, first level, one thread per column c of [dWo_0 (W), dWo_1 (W), dbo_0,
+// dbo_1, loss] over the rows of chunk blockIdx.y (kHeadRows rows):
+// part[chunk][c] = sum over the chunk of dy_k h_c, dy_k or the row loss.
+constexpr int kHeadRows = 256;
+__global__ void __launch_bounds__(256) head_grad_kernel(int64_t Mp, int W, const bf16 *__restrict__ H,
+                                                        const float *dyl_, float *__restrict__ part) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int C = 2 * W + 3;
+    if (c >= C) return;
+    const ConstF dyl = (ConstF)dyl_;
+    const int64_t r0 = (int64_t)blockIdx.y * kHeadRows;
+    const int64_t r1 = (r0 + kHeadRows < Mp) ? r0 + kHeadRows : Mp;
+    float acc = 0.0f;
+    if (c < 2 * W) {
+        const int k = c / W, f = c - k * W;
+        for (int64_t r = r0; r < r1; ++r) acc = fmaf(dyl[3 * r + k], (float)H[r * W + f], acc);
+    } else {
+        const int k = c - 2 * W;  // 0, 1: dy; 2: loss
+        for (int64_t r = r0; r < r1; ++r) acc += dyl[3 * r + k];
+    }
+    part[(int64_t)blockIdx.y * C + c] = acc;
+}
+
+// Fixed-order column sums: out[c] = sum_r in[r * ld + c] (r < R), in FP64.  A block covers
+// 64 columns with 4 row groups (rows = g mod 4) whose sums are added in order.
 __global__ void __launch_bounds__(256) colsum_kernel(const float *__restrict__ in, int64_t R, int64_t C,
                                                      int64_t ld, float *__restrict__ out) {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= C) return;
-    double s = 0.0;
-    for (int64_t r = 0; r < R; ++r) s += (double)in[r * ld + c];
-    out[c] = (float)s;
+    __shared__ double sh[4][64];
+    const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 64 + cx;
+    double acc = 0.0;
+    if (c < C)
+        for (int64_t r = ry; r < R; r += 4) acc += (double)in[r * ld + c];
+    sh[ry][cx] = acc;
+    __syncthreads();
+    if (ry == 0 && c < C) out[c] = (float)(((sh[0][cx] + sh[1][cx]) + sh[2][cx]) + sh[3][cx]);
 }
 
-// Bias gradient, first level: part[chunk][c] = sum of dZ[r][c] over the chunk's rows.
-constexpr int kBiasRows = 1024;
-__global__ void __launch_bounds__(256) bias_partial_kernel(const bf16 *__restrict__ dZ, int64_t Mp, int W,
-                                                           float *__restrict__ part) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= W) return;
-    const int64_t r0 = (int64_t)blockIdx.y * kBiasRows;
-    const int64_t r1 = (r0 + kBiasRows < Mp) ? r0 + kBiasRows : Mp;
-    float s = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) s += (float)dZ[r * W + c];
-    part[(int64_t)blockIdx.y * W + c] = s;
+// Bias gradient: out[o] = sum_b dZ^T[o][b] (rows of the transposed copy the weight
+// gradient already uses), one block per row, FP32 lanes then a fixed-order tree.
+__global__ void __launch_bounds__(256) rowsum_bf16_kernel(const bf16 *__restrict__ X, int64_t cols,
+                                                          float *__restrict__ out) {
+    __shared__ float sh[256];
+    const bf16 *x = X + (int64_t)blockIdx.x * cols;
+    float acc = 0.0f;
+    for (int64_t k = (int64_t)threadIdx.x * 8; k < cols; k += 256 * 8) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(x + k);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (float)v[u];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
 }
 
 __global__ void __launch_bounds__(256) adam_kernel(int64_t P, float *__restrict__ p,
@@ -319,7 +401,7 @@ struct rsi_mlp {
     rsi::DeviceBuffer Bff, params, grads, adam_m, adam_v;
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> Wb, WTb;  // bf16 weights and transposes
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> H, Z;    // activations [L+1], pre-acts [L]
-    rsi::DeviceBuffer HT, dZ[2], dZT, dwpart, headpart, lossbuf;
+    rsi::DeviceBuffer HT, dZ[2], dZT, dwpart, headpart, dyl, lossbuf;
     int dw_splits = 1;
 };
 
@@ -327,14 +409,28 @@ namespace rsi {
 
 static int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
 
-static rsi_status gemm(int epi, const GemmArgs &g, int splits, hipStream_t s) {
-    const dim3 grid((unsigned)(g.M / kTileM), (unsigned)(g.N / kTileN), (unsigned)splits);
+template <int BM, int BN>
+static void launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s) {
+    const dim3 grid((unsigned)(g.M / BM), (unsigned)(g.N / BN), (unsigned)splits);
     switch (epi) {
-        case EPI_FWD: hipLaunchKernelGGL(gemm_nt_kernel<EPI_FWD>, grid, dim3(256), 0, s, g); break;
-        case EPI_FWD_INFER: hipLaunchKernelGGL(gemm_nt_kernel<EPI_FWD_INFER>, grid, dim3(256), 0, s, g); break;
-        case EPI_DX: hipLaunchKernelGGL(gemm_nt_kernel<EPI_DX>, grid, dim3(256), 0, s, g); break;
-        default: hipLaunchKernelGGL(gemm_nt_kernel<EPI_DW>, grid, dim3(256), 0, s, g); break;
+        case EPI_FWD: hipLaunchKernelGGL((gemm_nt_kernel<EPI_FWD, BM, BN>), grid, dim3(256), 0, s, g); break;
+        case EPI_FWD_INFER:
+            hipLaunchKernelGGL((gemm_nt_kernel<EPI_FWD_INFER, BM, BN>), grid, dim3(256), 0, s, g);
+            break;
+        case EPI_DX: hipLaunchKernelGGL((gemm_nt_kernel<EPI_DX, BM, BN>), grid, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL((gemm_nt_kernel<EPI_DW, BM, BN>), grid, dim3(256), 0, s, g); break;
     }
+}
+
+// Tile: 128 rows / columns where the dimension allows it (M, N are multiples of 64 and
+// the K range of every split a multiple of 32, checked by the callers' padding).
+static rsi_status gemm(int epi, const GemmArgs &g, int splits, hipStream_t s) {
+    if (g.M % 64 || g.N % 64 || g.k_per_split % 32 || (g.K % g.k_per_split)) return RSI_ERR_SIZE;
+    const bool bm = g.M % 128 == 0, bn = g.N % 128 == 0;
+    if (bm && bn) launch_gemm<128, 128>(epi, g, splits, s);
+    else if (bm) launch_gemm<128, 64>(epi, g, splits, s);
+    else if (bn) launch_gemm<64, 128>(epi, g, splits, s);
+    else launch_gemm<64, 64>(epi, g, splits, s);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }
@@ -361,9 +457,10 @@ static rsi_status refresh_bf16(rsi_mlp *net, hipStream_t s) {
 // Forward through the hidden layers (training keeps Z and nothing else is needed).
 static rsi_status forward_hidden(rsi_mlp *net, int64_t n, const float *q, bool train, hipStream_t s) {
     const int64_t Mp = pad64(n);
-    const int64_t tot = Mp * net->m;
-    hipLaunchKernelGGL(features_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, Mp, net->m,
-                       q, net->box, net->Bff.as<float>(), net->H[0]->as<bf16>(), (int64_t)net->F);
+    const int cx = net->m / 8, rows = 256 / cx;  // m is a multiple of 32, at most 512
+    hipLaunchKernelGGL(features_kernel, dim3((unsigned)((Mp + rows - 1) / rows)), dim3(cx, rows), 0, s, n,
+                       Mp, net->m, q, net->box, net->Bff.as<float>(), net->H[0]->as<bf16>(),
+                       (int64_t)net->F);
     RSI_HIP(hipGetLastError());
     for (int l = 0; l < net->L; ++l) {
         GemmArgs g{};
@@ -390,21 +487,23 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
                            hipStream_t s) {
     const int64_t Mp = pad64(n);
     const int W = net->W;
-    const unsigned hb = (unsigned)(Mp / 64);
     const float *params = net->params.as<float>();
-    hipLaunchKernelGGL(head_kernel, dim3(hb), dim3(256), 0, s, n, W, net->H[net->L]->as<bf16>(),
-                       net->Z[net->L - 1]->as<float>(), params + net->offWo, params + net->offbo, t,
-                       (float *)nullptr, net->dZ[0].as<bf16>(), net->headpart.as<float>());
+    hipLaunchKernelGGL(head_kernel, dim3((unsigned)((Mp + 255) / 256)), dim3(256), 0, s, n, Mp, W,
+                       net->H[net->L]->as<bf16>(), net->Z[net->L - 1]->as<float>(), params + net->offWo,
+                       params + net->offbo, t, (float *)nullptr, net->dZ[0].as<bf16>(), net->dyl.as<float>());
     RSI_HIP(hipGetLastError());
-    // head partials [hb][2W + 3] -> dWo, dbo (columns 0..2W+1) and the loss (column 2W+2)
+    // head partials [chunks][2W + 3] -> dWo, dbo (columns 0..2W+1) and the loss (column 2W+2)
     {
-        const int64_t C = 2 * W + 3;
-        float *lossdst = loss ? loss : net->lossbuf.as<float>();
-        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C - 1 + 255) / 256)), dim3(256), 0, s,
-                           net->headpart.as<float>(), (int64_t)hb, C - 1, C, grad + net->offWo);
+        const int64_t C = 2 * W + 3, chunks = (Mp + kHeadRows - 1) / kHeadRows;
+        hipLaunchKernelGGL(head_grad_kernel, dim3((unsigned)((C + 255) / 256), (unsigned)chunks), dim3(256), 0,
+                           s, Mp, W, net->H[net->L]->as<bf16>(), net->dyl.as<float>(), net->headpart.as<float>());
         RSI_HIP(hipGetLastError());
-        hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, net->headpart.as<float>() + (C - 1),
-                           (int64_t)hb, (int64_t)1, C, lossdst);
+        float *lossdst = loss ? loss : net->lossbuf.as<float>();
+        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C - 1 + 63) / 64)), dim3(256), 0, s,
+                           net->headpart.as<float>(), chunks, C - 1, C, grad + net->offWo);
+        RSI_HIP(hipGetLastError());
+        hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, net->headpart.as<float>() + (C - 1), chunks,
+                           (int64_t)1, C, lossdst);
         RSI_HIP(hipGetLastError());
     }
     int cur = 0;
@@ -427,17 +526,12 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
         g.P = net->dwpart.as<float>();
         RSI_TRY(gemm(EPI_DW, g, splits, s));
         const int64_t C = (int64_t)W * I;
-        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C + 63) / 64)), dim3(256), 0, s,
                            net->dwpart.as<float>(), (int64_t)splits, C, C, grad + net->offW[l]);
         RSI_HIP(hipGetLastError());
-        // bias gradient: chunked column sums of dZ, then a fixed-order sum of the chunks
-        // (the weight partials are consumed above, so their buffer is reused here)
-        const int64_t nch = (Mp + kBiasRows - 1) / kBiasRows;
-        hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)((W + 255) / 256), (unsigned)nch), dim3(256),
-                           0, s, net->dZ[cur].as<bf16>(), Mp, W, net->dwpart.as<float>());
-        RSI_HIP(hipGetLastError());
-        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, s,
-                           net->dwpart.as<float>(), nch, (int64_t)W, (int64_t)W, grad + net->offb[l]);
+        // bias gradient: row sums of dZ^T
+        hipLaunchKernelGGL(rowsum_bf16_kernel, dim3((unsigned)W), dim3(256), 0, s, net->dZT.as<bf16>(), Mp,
+                           grad + net->offb[l]);
         RSI_HIP(hipGetLastError());
         if (l == 0) break;
         GemmArgs d{};
@@ -533,14 +627,15 @@ rsi_status rsi_mlp_create(rsi_mlp **out, int n_ff, int width, int depth, const f
     RSI_TRY(net->dZ[0].alloc(sizeof(bf16) * Mp * maxdim));
     RSI_TRY(net->dZ[1].alloc(sizeof(bf16) * Mp * maxdim));
     RSI_TRY(net->dZT.alloc(sizeof(bf16) * Mp * maxdim));
-    // weight-gradient split over the batch: about 1024 rows per split, at most 128 splits
+    // weight-gradient split over the batch: at least 256 rows per split, at most 256
+    // splits (about 1024 workgroups for 256 x 256 weights at a batch of 65536)
     int splits = 1;
-    while (splits < 128 && Mp / (splits * 2) >= 1024) splits *= 2;
+    while (splits < 256 && Mp / (splits * 2) >= 256) splits *= 2;
     net->dw_splits = splits;
-    const size_t bias_chunks = (size_t)((Mp + kBiasRows - 1) / kBiasRows);
     const size_t dw_elems = (size_t)splits * width * maxdim;
-    RSI_TRY(net->dwpart.alloc(sizeof(float) * std::max(dw_elems, bias_chunks * width)));
-    RSI_TRY(net->headpart.alloc(sizeof(float) * (size_t)(Mp / 64) * (2 * width + 3)));
+    RSI_TRY(net->dwpart.alloc(sizeof(float) * dw_elems));
+    RSI_TRY(net->headpart.alloc(sizeof(float) * (size_t)((Mp + kHeadRows - 1) / kHeadRows) * (2 * width + 3)));
+    RSI_TRY(net->dyl.alloc(sizeof(float) * 3 * (size_t)Mp));
     RSI_TRY(net->lossbuf.alloc(sizeof(float) * 4));
     RSI_TRY(refresh_bf16(net.get(), nullptr));
     RSI_HIP(hipDeviceSynchronize());
@@ -583,7 +678,7 @@ rsi_status rsi_mlp_forward(rsi_mlp *net, int64_t n, const float *q, float *y, vo
     RSI_TRY(forward_hidden(net, n, q, false, s));
     const int64_t Mp = pad64(n);
     const float *params = net->params.as<float>();
-    hipLaunchKernelGGL(head_kernel, dim3((unsigned)(Mp / 64)), dim3(256), 0, s, n, net->W,
+    hipLaunchKernelGGL(head_kernel, dim3((unsigned)((Mp + 255) / 256)), dim3(256), 0, s, n, Mp, net->W,
                        net->H[net->L]->as<bf16>(), (const float *)nullptr, params + net->offWo,
                        params + net->offbo, (const float *)nullptr, y, (bf16 *)nullptr, (float *)nullptr);
     RSI_HIP(hipGetLastError());

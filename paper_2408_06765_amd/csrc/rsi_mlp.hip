@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -52,7 +53,7 @@ struct GemmArgs {
     int64_t M, N, K, k_per_split;
     const float *bias;  // EPI_FWD*: [N]
     float *Z;           // EPI_FWD: pre-activation out; EPI_DX: previous pre-activation in
-    int64_t ldz;
+    int64_t ldz;        // row pitch of Z, or 0: Z in the tile-native order (see below)
     bf16 *H;            // EPI_FWD*: activation out; EPI_DX: previous dZ out
     int64_t ldh;
     bf16 *HT;           // optional transposed copy [N][M]
@@ -72,8 +73,13 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
     constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
     constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;  // 16-byte chunks per thread
     static_assert(CA >= 1 && CB >= 1, "tile too small for 256 threads");
-    __shared__ __attribute__((aligned(16))) bf16 sA[2][BM][LDK];
-    __shared__ __attribute__((aligned(16))) bf16 sB[2][BN][LDK];
+    // operand buffers, reused after the K loop as the staging tile of the bf16 output
+    constexpr int LDT = BN + 8;  // staging row pitch (bf16)
+    constexpr int kOps = 2 * (BM + BN) * LDK * 2, kStage = BM * LDT * 2;
+    __shared__ __attribute__((aligned(16))) char smem[kOps > kStage ? kOps : kStage];
+    auto sA = reinterpret_cast<bf16 (*)[BM][LDK]>(smem);
+    auto sB = reinterpret_cast<bf16 (*)[BN][LDK]>(smem + 2 * BM * LDK * 2);
+    auto st = reinterpret_cast<bf16 (*)[LDT]>(smem);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
@@ -136,36 +142,79 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
         __syncthreads();
     }
     const int cn = lane & 15, cm = (lane >> 4) * 4;
+    if constexpr (EPI == EPI_DW) {
+        float *p = g.P + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int64_t n = n0 + wn * WN + 16 * j + cn;
+                const int64_t mb = m0 + wm * WM + 16 * i + cm;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) p[(mb + e) * g.N + n] = acc[i][j][e];
+            }
+        return;
+    }
+    // Tile-native order of Z: fragment (i, j) of wave w holds 4 values per lane, stored as
+    // one 16-byte chunk at ((tile * 4 + w) * FM * FN + i * FN + j) * 256 + lane * 4, so the
+    // forward GEMM writes and the input-gradient GEMM of the same shape reads it with
+    // fully coalesced accesses.
+    const int64_t tile = (int64_t)blockIdx.x * gridDim.y + blockIdx.y;
+    auto znat = [&](int i, int j) { return ((tile * 4 + wave) * (FM * FN) + i * FN + j) * 256 + lane * 4; };
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int64_t n = n0 + wn * WN + 16 * j + cn;
-            const int64_t mb = m0 + wm * WM + 16 * i + cm;
-            if constexpr (EPI == EPI_DW) {
-                float *p = g.P + (int64_t)blockIdx.z * g.M * g.N;
+            const int nl = wn * WN + 16 * j + cn, ml = wm * WM + 16 * i + cm;
+            const int64_t n = n0 + nl, mb = m0 + ml;
+            f32x4 zin;
+            if constexpr (EPI == EPI_DX) {
+                if (g.ldz == 0) {
+                    zin = *reinterpret_cast<const f32x4 *>(g.Z + znat(i, j));
+                } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) p[(mb + e) * g.N + n] = acc[i][j][e];
-            } else {
-                bf16x4 hv;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int64_t m = mb + e;
-                    float v;
-                    if constexpr (EPI == EPI_DX) {
-                        v = acc[i][j][e] * silu_grad_f(g.Z[m * g.ldz + n]);
-                    } else {
-                        const float z = acc[i][j][e] + g.bias[n];
-                        if constexpr (EPI == EPI_FWD) g.Z[m * g.ldz + n] = z;
-                        v = silu_f(z);
-                    }
-                    const bf16 h = (bf16)v;
-                    g.H[m * g.ldh + n] = h;
-                    hv[e] = h;
+                    for (int e = 0; e < 4; ++e) zin[e] = g.Z[(mb + e) * g.ldz + n];
                 }
-                if (g.HT) *reinterpret_cast<bf16x4 *>(g.HT + n * g.ldht + mb) = hv;
+            }
+            f32x4 zout;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float v;
+                if constexpr (EPI == EPI_DX) {
+                    v = acc[i][j][e] * silu_grad_f(zin[e]);
+                } else {
+                    const float z = acc[i][j][e] + g.bias[n];
+                    zout[e] = z;
+                    v = silu_f(z);
+                }
+                st[ml + e][nl] = (bf16)v;
+            }
+            if constexpr (EPI == EPI_FWD) {
+                if (g.ldz == 0) {
+                    *reinterpret_cast<f32x4 *>(g.Z + znat(i, j)) = zout;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) g.Z[(mb + e) * g.ldz + n] = zout[e];
+                }
             }
         }
+    __syncthreads();
+    // row-major output in 16-byte chunks
+    for (int c = tid; c < BM * BN / 8; c += 256) {
+        const int row = c / (BN / 8), c8 = (c - row * (BN / 8)) * 8;
+        *reinterpret_cast<bf16x8 *>(g.H + (m0 + row) * g.ldh + n0 + c8) =
+            *reinterpret_cast<const bf16x8 *>(&st[row][c8]);
+    }
+    // transposed copy [N][M] in 16-byte chunks of 8 consecutive rows
+    if (g.HT) {
+        for (int c = tid; c < BM * BN / 8; c += 256) {
+            const int col = c / (BM / 8), r8 = (c - col * (BM / 8)) * 8;
+            bf16x8 v;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = st[r8 + t][col];
+            *reinterpret_cast<bf16x8 *>(g.HT + (n0 + col) * g.ldht + m0 + r8) = v;
+        }
+    }
 }
 
 // Fourier features of the normalised query: h0 = [sin 2 pi u, cos 2 pi u], u = B v.
@@ -173,15 +222,19 @@ struct Box {
     double lo[5], inv[5];  // v = 2 (q - lo) * inv - 1, inv = 1 / (hi - lo)
 };
 
-// One thread: 8 consecutive features of one row (16-byte stores of sin and of cos);
-// block = (m/8) x (256 / (m/8)) threads, rows past n get u = 0.
+// One thread: 8 consecutive features of one row.  Block = 64 rows (x) x 4 chunks of 8
+// features (y); grid.y covers the m/32 groups of chunks.  Writes the row-major features
+// (16-byte stores) and, when HT != NULL, the transposed copy [2m][Mp] the first layer's
+// weight gradient reads (consecutive lanes write consecutive rows).  Rows past n get
+// u = 0.
 __global__ void __launch_bounds__(256) features_kernel(int64_t n, int64_t Mp, int m,
                                                        const float *__restrict__ q, Box box,
                                                        const float *__restrict__ Bff,
-                                                       bf16 *__restrict__ H0, int64_t ld) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
-    if (b >= Mp) return;
-    const int j0 = threadIdx.x * 8;
+                                                       bf16 *__restrict__ H0, int64_t ld,
+                                                       bf16 *__restrict__ HT) {
+    const int64_t b = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int j0 = (blockIdx.y * 4 + threadIdx.y) * 8;
+    if (b >= Mp || j0 >= m) return;
     // v and u = B v, and u's reduction to one revolution, in FP64: the bf16 features then
     // round the same values the FP64 reference rounds (|u| reaches tens of revolutions)
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -202,22 +255,18 @@ __global__ void __launch_bounds__(256) features_kernel(int64_t n, int64_t Mp, in
     }
     *reinterpret_cast<bf16x8 *>(H0 + b * ld + j0) = hs;
     *reinterpret_cast<bf16x8 *>(H0 + b * ld + m + j0) = hc;
-}
-
-// bf16 transpose [R][C] -> [C][R] through LDS, 64 x 64 tiles.
-__global__ void __launch_bounds__(256) transpose_bf16_kernel(const bf16 *__restrict__ in, int64_t R,
-                                                             int64_t C, bf16 *__restrict__ out) {
-    __shared__ bf16 tile[64][66];
-    const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int rr = ty; rr < 64; rr += 4) tile[rr][tx] = in[(r0 + rr) * C + c0 + tx];
-    __syncthreads();
-    for (int cc = ty; cc < 64; cc += 4) out[(c0 + cc) * R + r0 + tx] = tile[tx][cc];
+    if (HT) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            HT[(int64_t)(j0 + t) * Mp + b] = hs[t];
+            HT[(int64_t)(m + j0 + t) * Mp + b] = hc[t];
+        }
+    }
 }
 
 // Output layer (FP32), one thread per row: y = Wo h + bo.  Training (t != NULL): the
 // row's loss and output gradient dy = (y - t)/n go to dyl [Mp][3] (0 for padding rows)
-// and dZ_L = bf16((dy Wo) * silu'(Z_L)).  Wo is read through the constant address space
+// and dZ_L = bf16((dy Wo) * silu'(Z_L)), row-major and transposed.  Wo is read through the constant address space
 // (scalar loads: every lane uses the same weights).
 typedef const __attribute__((address_space(4))) float *ConstF;
 
@@ -226,7 +275,7 @@ __global__ void __launch_bounds__(256) head_kernel(int64_t n, int64_t Mp, int W,
                                                    const float *__restrict__ Z, const float *Wo_,
                                                    const float *bo_, const float *__restrict__ t,
                                                    float *__restrict__ y, bf16 *__restrict__ dZ,
-                                                   float *__restrict__ dyl) {
+                                                   bf16 *__restrict__ dZT, float *__restrict__ dyl) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (row >= Mp) return;
     const ConstF Wo = (ConstF)Wo_, bo = (ConstF)bo_;
@@ -266,32 +315,58 @@ __global__ void __launch_bounds__(256) head_kernel(int64_t n, int64_t Mp, int W,
         for (int u = 0; u < 8; ++u) {
             const float dh = d0 * Wo[f + u] + d1 * Wo[W + f + u];
             o[u] = (bf16)(dh * silu_grad_f(z[f + u]));
+            dZT[(int64_t)(f + u) * Mp + row] = o[u];  // transposed copy [W][Mp]
         }
         *reinterpret_cast<bf16x8 *>(dz + f) = o;
     }
 }
 
-// Head gradients, first level, one thread per column c of [dWo_0 (W), dWo_1 (W), dbo_0,
-// dbo_1, loss] over the rows of chunk blockIdx.y (kHeadRows rows):
-// part[chunk][c] = sum over the chunk of dy_k h_c, dy_k or the row loss.
+// Head gradients, first level, over the rows of chunk blockIdx.x (kHeadRows rows):
+// part[chunk][c] for c < 2W = sum of dy_k h_f (c = k W + f), then dy_0, dy_1 and the loss.
+// The chunk's dy and losses are staged in LDS; a thread covers 8 features (16-byte
+// loads) of every 4th row, and the 4 row groups are added in a fixed order.
 constexpr int kHeadRows = 256;
 __global__ void __launch_bounds__(256) head_grad_kernel(int64_t Mp, int W, const bf16 *__restrict__ H,
-                                                        const float *dyl_, float *__restrict__ part) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    const int C = 2 * W + 3;
-    if (c >= C) return;
-    const ConstF dyl = (ConstF)dyl_;
-    const int64_t r0 = (int64_t)blockIdx.y * kHeadRows;
-    const int64_t r1 = (r0 + kHeadRows < Mp) ? r0 + kHeadRows : Mp;
-    float acc = 0.0f;
-    if (c < 2 * W) {
-        const int k = c / W, f = c - k * W;
-        for (int64_t r = r0; r < r1; ++r) acc = fmaf(dyl[3 * r + k], (float)H[r * W + f], acc);
-    } else {
-        const int k = c - 2 * W;  // 0, 1: dy; 2: loss
-        for (int64_t r = r0; r < r1; ++r) acc += dyl[3 * r + k];
+                                                        const float *__restrict__ dyl, float *__restrict__ part) {
+    __shared__ float sdy[kHeadRows * 3];
+    __shared__ float sacc[4][2 * 1024];
+    const int64_t r0 = (int64_t)blockIdx.x * kHeadRows;
+    const int rows = (int)((Mp - r0 < kHeadRows) ? Mp - r0 : kHeadRows);
+    for (int i = threadIdx.x; i < rows * 3; i += 256) sdy[i] = dyl[3 * r0 + i];
+    __syncthreads();
+    const int nfc = W / 8, tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int fc = tx; fc < nfc; fc += 64) {
+        float a0[8], a1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a0[u] = a1[u] = 0.0f;
+        for (int r = ty; r < rows; r += 4) {
+            const bf16x8 h = *reinterpret_cast<const bf16x8 *>(H + (r0 + r) * W + 8 * fc);
+            const float d0 = sdy[3 * r], d1 = sdy[3 * r + 1];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                a0[u] = fmaf(d0, (float)h[u], a0[u]);
+                a1[u] = fmaf(d1, (float)h[u], a1[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sacc[ty][8 * fc + u] = a0[u];
+            sacc[ty][W + 8 * fc + u] = a1[u];
+        }
     }
-    part[(int64_t)blockIdx.y * C + c] = acc;
+    __syncthreads();
+    const int C = 2 * W + 3;
+    float *out = part + (int64_t)blockIdx.x * C;
+    for (int c = threadIdx.x; c < 2 * W; c += 256) {
+        float v = sacc[0][c];
+        for (int g = 1; g < 4; ++g) v += sacc[g][c];
+        out[c] = v;
+    }
+    if (threadIdx.x < 3) {
+        float v = 0.0f;
+        for (int r = 0; r < rows; ++r) v += sdy[3 * r + threadIdx.x];
+        out[2 * W + threadIdx.x] = v;
+    }
 }
 
 // Fixed-order column sums: out[c] = sum_r in[r * ld + c] (r < R), in FP64.  A block covers
@@ -401,7 +476,8 @@ struct rsi_mlp {
     rsi::DeviceBuffer Bff, params, grads, adam_m, adam_v;
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> Wb, WTb;  // bf16 weights and transposes
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> H, Z;    // activations [L+1], pre-acts [L]
-    rsi::DeviceBuffer HT, dZ[2], dZT, dwpart, headpart, dyl, lossbuf;
+    std::vector<std::unique_ptr<rsi::DeviceBuffer>> HT;      // transposed layer inputs [L]
+    rsi::DeviceBuffer dZ[2], dZT[2], dwpart, headpart, dyl, lossbuf;
     int dw_splits = 1;
 };
 
@@ -435,13 +511,6 @@ static rsi_status gemm(int epi, const GemmArgs &g, int splits, hipStream_t s) {
     return RSI_OK;
 }
 
-static rsi_status transpose(const bf16 *in, int64_t R, int64_t C, bf16 *out, hipStream_t s) {
-    hipLaunchKernelGGL(transpose_bf16_kernel, dim3((unsigned)(R / 64), (unsigned)(C / 64)), dim3(256), 0, s,
-                       in, R, C, out);
-    RSI_HIP(hipGetLastError());
-    return RSI_OK;
-}
-
 static rsi_status refresh_bf16(rsi_mlp *net, hipStream_t s) {
     for (int l = 0; l < net->L; ++l) {
         const int O = net->W, I = net->in_dim[l];
@@ -457,10 +526,10 @@ static rsi_status refresh_bf16(rsi_mlp *net, hipStream_t s) {
 // Forward through the hidden layers (training keeps Z and nothing else is needed).
 static rsi_status forward_hidden(rsi_mlp *net, int64_t n, const float *q, bool train, hipStream_t s) {
     const int64_t Mp = pad64(n);
-    const int cx = net->m / 8, rows = 256 / cx;  // m is a multiple of 32, at most 512
-    hipLaunchKernelGGL(features_kernel, dim3((unsigned)((Mp + rows - 1) / rows)), dim3(cx, rows), 0, s, n,
-                       Mp, net->m, q, net->box, net->Bff.as<float>(), net->H[0]->as<bf16>(),
-                       (int64_t)net->F);
+    // m is a multiple of 32: m / 32 groups of 4 chunks of 8 features
+    hipLaunchKernelGGL(features_kernel, dim3((unsigned)(Mp / 64), (unsigned)(net->m / 32)), dim3(64, 4), 0, s,
+                       n, Mp, net->m, q, net->box, net->Bff.as<float>(), net->H[0]->as<bf16>(),
+                       (int64_t)net->F, train ? net->HT[0]->as<bf16>() : (bf16 *)nullptr);
     RSI_HIP(hipGetLastError());
     for (int l = 0; l < net->L; ++l) {
         GemmArgs g{};
@@ -474,10 +543,12 @@ static rsi_status forward_hidden(rsi_mlp *net, int64_t n, const float *q, bool t
         g.k_per_split = g.K;
         g.bias = net->params.as<float>() + net->offb[l];
         g.Z = train ? net->Z[l]->as<float>() : nullptr;
-        g.ldz = net->W;
+        g.ldz = (l + 1 == net->L) ? net->W : 0;  // tile-native except for the head's input
         g.H = net->H[l + 1]->as<bf16>();
         g.ldh = net->W;
-        g.HT = nullptr;
+        // training: the transposed activations feed the next layer's weight gradient
+        g.HT = (train && l + 1 < net->L) ? net->HT[l + 1]->as<bf16>() : nullptr;
+        g.ldht = Mp;
         RSI_TRY(gemm(train ? EPI_FWD : EPI_FWD_INFER, g, 1, s));
     }
     return RSI_OK;
@@ -490,13 +561,14 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
     const float *params = net->params.as<float>();
     hipLaunchKernelGGL(head_kernel, dim3((unsigned)((Mp + 255) / 256)), dim3(256), 0, s, n, Mp, W,
                        net->H[net->L]->as<bf16>(), net->Z[net->L - 1]->as<float>(), params + net->offWo,
-                       params + net->offbo, t, (float *)nullptr, net->dZ[0].as<bf16>(), net->dyl.as<float>());
+                       params + net->offbo, t, (float *)nullptr, net->dZ[0].as<bf16>(), net->dZT[0].as<bf16>(),
+                       net->dyl.as<float>());
     RSI_HIP(hipGetLastError());
     // head partials [chunks][2W + 3] -> dWo, dbo (columns 0..2W+1) and the loss (column 2W+2)
     {
         const int64_t C = 2 * W + 3, chunks = (Mp + kHeadRows - 1) / kHeadRows;
-        hipLaunchKernelGGL(head_grad_kernel, dim3((unsigned)((C + 255) / 256), (unsigned)chunks), dim3(256), 0,
-                           s, Mp, W, net->H[net->L]->as<bf16>(), net->dyl.as<float>(), net->headpart.as<float>());
+        hipLaunchKernelGGL(head_grad_kernel, dim3((unsigned)chunks), dim3(256), 0, s, Mp, W,
+                           net->H[net->L]->as<bf16>(), net->dyl.as<float>(), net->headpart.as<float>());
         RSI_HIP(hipGetLastError());
         float *lossdst = loss ? loss : net->lossbuf.as<float>();
         hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C - 1 + 63) / 64)), dim3(256), 0, s,
@@ -509,15 +581,14 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
     int cur = 0;
     for (int l = net->L - 1; l >= 0; --l) {
         const int I = net->in_dim[l];
-        // transposes for the weight gradient: dZ^T [W][Mp], H_{l}^T [I][Mp]
-        RSI_TRY(transpose(net->dZ[cur].as<bf16>(), Mp, W, net->dZT.as<bf16>(), s));
-        RSI_TRY(transpose(net->H[l]->as<bf16>(), Mp, I, net->HT.as<bf16>(), s));
+        // the weight gradient reads the transposed copies dZ_l^T [W][Mp] and H_l^T [I][Mp],
+        // written by the epilogues that produced dZ_l and H_l
         int splits = net->dw_splits;
         while (splits > 1 && (Mp % ((int64_t)splits * kTileK) != 0)) splits >>= 1;
         GemmArgs g{};
-        g.A = net->dZT.as<bf16>();
+        g.A = net->dZT[cur].as<bf16>();
         g.lda = Mp;
-        g.B = net->HT.as<bf16>();
+        g.B = net->HT[l]->as<bf16>();
         g.ldb = Mp;
         g.M = W;
         g.N = I;
@@ -530,7 +601,7 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
                            net->dwpart.as<float>(), (int64_t)splits, C, C, grad + net->offW[l]);
         RSI_HIP(hipGetLastError());
         // bias gradient: row sums of dZ^T
-        hipLaunchKernelGGL(rowsum_bf16_kernel, dim3((unsigned)W), dim3(256), 0, s, net->dZT.as<bf16>(), Mp,
+        hipLaunchKernelGGL(rowsum_bf16_kernel, dim3((unsigned)W), dim3(256), 0, s, net->dZT[cur].as<bf16>(), Mp,
                            grad + net->offb[l]);
         RSI_HIP(hipGetLastError());
         if (l == 0) break;
@@ -544,10 +615,11 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
         d.K = W;
         d.k_per_split = W;
         d.Z = net->Z[l - 1]->as<float>();
-        d.ldz = W;
+        d.ldz = 0;  // written tile-native by the forward GEMM of the same shape
         d.H = net->dZ[cur ^ 1].as<bf16>();
         d.ldh = I;
-        d.HT = nullptr;
+        d.HT = net->dZT[cur ^ 1].as<bf16>();
+        d.ldht = Mp;
         RSI_TRY(gemm(EPI_DX, d, 1, s));
         cur ^= 1;
     }
@@ -623,14 +695,24 @@ rsi_status rsi_mlp_create(rsi_mlp **out, int n_ff, int width, int depth, const f
         net->H.emplace_back(new DeviceBuffer);
         RSI_TRY(net->H.back()->alloc(sizeof(bf16) * Mp * (l == 0 ? F : width)));
     }
-    RSI_TRY(net->HT.alloc(sizeof(bf16) * Mp * maxdim));
-    RSI_TRY(net->dZ[0].alloc(sizeof(bf16) * Mp * maxdim));
-    RSI_TRY(net->dZ[1].alloc(sizeof(bf16) * Mp * maxdim));
-    RSI_TRY(net->dZT.alloc(sizeof(bf16) * Mp * maxdim));
-    // weight-gradient split over the batch: at least 256 rows per split, at most 256
-    // splits (about 1024 workgroups for 256 x 256 weights at a batch of 65536)
+    for (int l = 0; l < depth; ++l) {
+        net->HT.emplace_back(new DeviceBuffer);
+        RSI_TRY(net->HT.back()->alloc(sizeof(bf16) * Mp * net->in_dim[l]));
+    }
+    for (int k = 0; k < 2; ++k) {
+        RSI_TRY(net->dZ[k].alloc(sizeof(bf16) * Mp * maxdim));
+        RSI_TRY(net->dZT[k].alloc(sizeof(bf16) * Mp * maxdim));
+    }
+    // weight-gradient split over the batch: at least 256 rows per split, at most 64
+    // splits (measured best for 256 x 256 weights at a batch of 65536: 256 workgroups
+    // of 1024-row K ranges; more splits cost more in partial traffic than they gain)
+    int max_splits = 64;
+    if (const char *e = std::getenv("RSI_MLP_DW_SPLITS")) {  // tuning sweeps: a power of two
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 4096 && (v & (v - 1)) == 0) max_splits = v;
+    }
     int splits = 1;
-    while (splits < 256 && Mp / (splits * 2) >= 256) splits *= 2;
+    while (splits < max_splits && Mp / (splits * 2) >= 256) splits *= 2;
     net->dw_splits = splits;
     const size_t dw_elems = (size_t)splits * width * maxdim;
     RSI_TRY(net->dwpart.alloc(sizeof(float) * dw_elems));
@@ -680,7 +762,8 @@ rsi_status rsi_mlp_forward(rsi_mlp *net, int64_t n, const float *q, float *y, vo
     const float *params = net->params.as<float>();
     hipLaunchKernelGGL(head_kernel, dim3((unsigned)((Mp + 255) / 256)), dim3(256), 0, s, n, Mp, net->W,
                        net->H[net->L]->as<bf16>(), (const float *)nullptr, params + net->offWo,
-                       params + net->offbo, (const float *)nullptr, y, (bf16 *)nullptr, (float *)nullptr);
+                       params + net->offbo, (const float *)nullptr, y, (bf16 *)nullptr, (bf16 *)nullptr,
+                       (float *)nullptr);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }

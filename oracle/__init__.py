@@ -52,6 +52,8 @@ def _load():
                               _i64p, C.POINTER(_dp), C.POINTER(_dp), C.POINTER(_dp),
                               C.POINTER(_dp), _dp, _dp, _dp, C.c_int64, _dp, _dp, _dp,
                               C.c_int, _dp, C.c_int, _dp]
+    lib.orc_chain_ex.argtypes = lib.orc_chain.argtypes[:-1] + [C.c_int, _dp]
+    lib.orc_reflection.argtypes = lib.orc_transmission.argtypes
     lib.orc_to_pressure.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _dp]
     lib.orc_to_pressure.restype = None
     lib.orc_num_threads.restype = C.c_int
@@ -109,8 +111,9 @@ def sample_square(seed: int, n: int, cx: float, cy: float, z0: float, half_width
     return tuple(bufs)
 
 
-MONOPOLE, DIPOLE = 0, 1
+MONOPOLE, DIPOLE, OMNI = 0, 1, 2
 T_GLOBAL, T_LOCAL, T_UNITY = 0, 1, 2
+CHAIN_OMNI, CHAIN_ABOVE = 1, 2
 
 
 def propagate(kind: int, src, weights, strength, tgt, c: float, freq: float, normal=None):
@@ -172,12 +175,27 @@ def transmission(tmode: int, m: int, zif, c, rho, xc, axis, qx, qy) -> np.ndarra
     return _cplx_out(out)
 
 
-def chain(xd, v0: float, xc, axis, ifaces, zif, c, rho, tgt, freqs, tmode: int) -> np.ndarray:
+def reflection(tmode: int, m: int, zif, c, rho, xc, axis, qx, qy) -> np.ndarray:
+    """Per-point reflection coefficient R (eq. 8) at interface m (1-based); 0 in the
+    display mode."""
+    lib = _load()
+    zif, zp = _d(zif); c, cp = _d(c); rho, rp = _d(rho)
+    xc, xcp = _d(xc); axis, ap = _d(axis)
+    qx, qxp = _d(qx); qy, qyp = _d(qy)
+    out = np.zeros(2 * qx.shape[0])
+    _check(lib.orc_reflection(tmode, m, zp, cp, rp, xcp, ap, qx.shape[0], qxp, qyp,
+                              out.ctypes.data_as(_dp)), "reflection")
+    return _cplx_out(out)
+
+
+def chain(xd, v0: float, xc, axis, ifaces, zif, c, rho, tgt, freqs, tmode: int,
+          flags: int = 0) -> np.ndarray:
     """Transducer -> interfaces -> field points (eqs. 3, 7, 11 chained).
 
     xd: (x, y, z, w) of the transducer samples; ifaces: list of (x, y, z, w), one per
     interface plane z = zif[m] (normal +z); c, rho: media 0..n_if.  Returns complex
-    [n_freq, n_tgt].
+    [n_freq, n_tgt].  flags: CHAIN_OMNI (interface samples as omnidirectional sources),
+    CHAIN_ABOVE (field points above the last interface: incident + reflected field).
     """
     lib = _load()
     keep = []
@@ -193,10 +211,10 @@ def chain(xd, v0: float, xc, axis, ifaces, zif, c, rho, tgt, freqs, tmode: int) 
     freqs = np.atleast_1d(np.asarray(freqs, dtype=np.float64))
     tx = np.ascontiguousarray(tgt[0], dtype=np.float64)
     out = np.zeros(2 * len(freqs) * tx.shape[0])
-    rc = lib.orc_chain(len(xd[0]), p(xd[0]), p(xd[1]), p(xd[2]), p(xd[3]), v0, p(xc), p(axis),
-                       n_if, nq.ctypes.data_as(_i64p), *arrs, p(zif if n_if else [0.0]), p(c),
-                       p(rho), tx.shape[0], p(tgt[0]), p(tgt[1]), p(tgt[2]), len(freqs),
-                       p(freqs), tmode, out.ctypes.data_as(_dp))
+    rc = lib.orc_chain_ex(len(xd[0]), p(xd[0]), p(xd[1]), p(xd[2]), p(xd[3]), v0, p(xc), p(axis),
+                          n_if, nq.ctypes.data_as(_i64p), *arrs, p(zif if n_if else [0.0]), p(c),
+                          p(rho), tx.shape[0], p(tgt[0]), p(tgt[1]), p(tgt[2]), len(freqs),
+                          p(freqs), tmode, flags, out.ctypes.data_as(_dp))
     _check(rc, "chain")
     return _cplx_out(out).reshape(len(freqs), tx.shape[0])
 

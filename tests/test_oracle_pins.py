@@ -195,6 +195,140 @@ def test_transparent_interface_reproduces_direct_field(orc):
         assert rel(ch, direct) < 1e-2
 
 
+# ----------------------------------------------------------------------------- reflection, eqs. 4-6
+def radial_rule(rmax, r0=1e-10, n_geo=160, n_lin=2000):
+    """Radial Gauss rule on [0, rmax] with geometric panels near 0 (resolves kernels
+    concentrated within a few r0 of the foot point) and a cos^2 window at the far end."""
+    edges = np.concatenate([[0.0], np.geomspace(r0, 1e-3, n_geo)])
+    r1, w1 = [], []
+    x, w = leggauss(16)
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        r1.append((lo + hi) / 2 + (hi - lo) / 2 * x)
+        w1.append((hi - lo) / 2 * w)
+    r2, w2 = gl_panels(1e-3, rmax, n_lin, 16)
+    r = np.concatenate(r1 + [r2])
+    wr = np.concatenate(w1 + [w2])
+    win = np.where(r < rmax / 2, 1.0, np.cos(0.5 * math.pi * (r - rmax / 2) / (rmax / 2)) ** 2)
+    return r, 2 * math.pi * r * wr * win
+
+
+def _point_source(k, S, P):
+    d = np.sqrt((P[0] - S[0]) ** 2 + (P[1] - S[1]) ** 2 + (P[2] - S[2]) ** 2)
+    return np.exp(1j * k * d) / d
+
+
+@pytest.mark.parametrize("z0", [0.005, 0.02])
+def test_reflected_field_equals_image_source(orc, z0):
+    """The reflected field radiates the boundary values back into the first medium
+    (normal -z).  For a point source S at height d above the plane, boundary values
+    phi_S continued upward are exactly the field of the image source S' mirrored below
+    the plane (method of images): phi(P) = e^{ik|P-S'|}/|P-S'|.  Pins the normal's sign
+    and the kernel for the reflected stage."""
+    f = 1.0e6
+    k = 2 * math.pi * f / C_W
+    d = 0.02
+    r, w = radial_rule(0.6)
+    s = _point_source(k, (0, 0, -d), (r, 0 * r, 0 * r))
+    P = (np.array([0.0]), np.array([0.0]), np.array([-z0]))
+    phi = orc.propagate(orc.DIPOLE, (r, 0 * r, 0 * r), w, s, P, C_W, f, normal=(0.0, 0.0, -1.0))
+    assert abs(phi[0] / (np.exp(1j * k * (z0 + d)) / (z0 + d)) - 1) < 1e-7
+
+
+@pytest.mark.parametrize("c2,rho2", [(5900.0, 7800.0), (2700.0, 2700.0)])
+def test_pressure_continuous_across_interface(orc, c2, rho2):
+    """eq. (6): rho1 (phi_i + phi_r) = rho2 phi_t on the interface.  Point source at normal
+    incidence (constant R and T of eqs. 8 and 11): just above the plane the total field is
+    phi_i + (reflected field of R phi_i, normal -z); just below it is the transmitted
+    field of T phi_i (normal +z, medium 2).  Both sides, 1e-9 m from the plane, must carry
+    the same pressure.  A wrong sign of the reflected stage, of the transmitted stage, or
+    a density ratio on the wrong side breaks it."""
+    f = 1.0e6
+    k1, k2 = 2 * math.pi * f / C_W, 2 * math.pi * f / c2
+    d, delta = 0.02, 1e-9
+    R = orc.reflection_coefficient(0.0, C_W, RHO_W, c2, rho2)
+    T = orc.transmission_coefficient(0.0, C_W, RHO_W, c2, rho2)
+    r, w = radial_rule(0.6, r0=1e-11)
+    Q = (r, 0 * r, 0 * r)
+    s = _point_source(k1, (0, 0, -d), Q)
+    above = (np.array([0.0]), np.array([0.0]), np.array([-delta]))
+    below = (np.array([0.0]), np.array([0.0]), np.array([delta]))
+    phi_a = _point_source(k1, (0, 0, -d), above)[0] + orc.propagate(
+        orc.DIPOLE, Q, w, R * s, above, C_W, f, normal=(0.0, 0.0, -1.0))[0]
+    phi_b = orc.propagate(orc.DIPOLE, Q, w, T * s, below, c2, f, normal=(0.0, 0.0, 1.0))[0]
+    p_a = orc.to_pressure(np.array([phi_a]), RHO_W, f)[0]
+    p_b = orc.to_pressure(np.array([phi_b]), rho2, f)[0]
+    assert abs(p_a / p_b - 1) < 1e-5
+    # and both equal the boundary value: p = i omega rho1 (1 + R) phi_S(Q0)
+    p0 = orc.to_pressure(np.array([(1 + R) / d]) * np.exp(1j * k1 * d), RHO_W, f)[0]
+    assert abs(p_b / p0 - 1) < 1e-5
+
+
+def test_reflection_coefficient_per_sample(orc):
+    """R per sample (eq. 8) uses the same incidence angle as T per sample (eq. 11):
+    T = (rho1/rho2)(1 + R) at every point, for both angle modes; R = 0 in the display
+    mode (matched media, T = 1)."""
+    cfg = W.LayeredStack()
+    c = [m[0] for m in cfg.media]
+    rho = [m[1] for m in cfg.media]
+    qx, qy = W.random_cloud(5, 500, (0.01, 0.0, 0.0), (0.03, 0.03, 0.0))[:2]
+    for tmode in (orc.T_GLOBAL, orc.T_LOCAL):
+        for m in (1, 2, 3):
+            R = orc.reflection(tmode, m, cfg.z_if[:m], c[:m + 1], rho[:m + 1], (0, 0, 0), cfg.axis, qx, qy)
+            T = orc.transmission(tmode, m, cfg.z_if[:m], c[:m + 1], rho[:m + 1], (0, 0, 0), cfg.axis, qx, qy)
+            assert np.max(np.abs(T - rho[m - 1] / rho[m] * (1 + R))) < 1e-12
+    R = orc.reflection(orc.T_UNITY, 1, cfg.z_if[:1], c[:2], rho[:2], (0, 0, 0), cfg.axis, qx, qy)
+    assert np.all(R == 0)
+
+
+def test_above_mode_transparent_interface_is_direct_field(orc):
+    """Field points above the interface: incident + reflected.  Matched media give R = 0
+    exactly, so the result is the transducer's direct field at those points (to rounding);
+    with a second interface in between, the incident part is the field transmitted
+    through the first (checked against the plain chain evaluated at the same points)."""
+    f = 1.0e6
+    xd = orc.sample_disc(0, 1024, A)
+    q1 = orc.sample_square(1, 4096, 0.0, 0.0, 0.03, 0.02)
+    q2 = orc.sample_square(2, 4096, 0.0, 0.0, 0.04, 0.02)
+    tgt = (np.linspace(-0.003, 0.003, 8), np.zeros(8), np.linspace(0.01, 0.025, 8))
+    for tmode in (orc.T_GLOBAL, orc.T_LOCAL):
+        got = orc.chain(xd, 1.0, (0, 0, 0), (0, 0, 1), [q1], [0.03], [C_W, C_W], [RHO_W, RHO_W], tgt,
+                        [f], tmode, flags=orc.CHAIN_ABOVE)[0]
+        direct = orc.propagate(orc.MONOPOLE, xd[:3], xd[3], 1.0, tgt, C_W, f)
+        assert rel(got, direct) < 1e-13
+    tgt2 = (np.linspace(-0.003, 0.003, 8), np.zeros(8), np.linspace(0.032, 0.038, 8))
+    media_c, media_r = [C_W, 5900.0, 5900.0], [RHO_W, 7800.0, 7800.0]
+    got = orc.chain(xd, 1.0, (0, 0, 0), (0, 0, 1), [q1, q2], [0.03, 0.04], media_c, media_r, tgt2,
+                    [f], orc.T_LOCAL, flags=orc.CHAIN_ABOVE)[0]
+    plain = orc.chain(xd, 1.0, (0, 0, 0), (0, 0, 1), [q1], [0.03], media_c[:2], media_r[:2], tgt2,
+                      [f], orc.T_LOCAL)[0]
+    assert rel(got, plain) < 1e-13
+
+
+def test_omnidirectional_interface_sources(orc):
+    """Interface samples as omnidirectional point sources (the form Sec. 2.1 attributes to
+    Zhang et al.): on the beam axis far below a transparent plane the omitted factors
+    tend to 1 (stationary phase: cos(theta) -> 1, 1/(kr) -> 0) and the chain tends to the
+    direct field; off the axis the omitted directivity makes the transmitted field
+    stronger than the true (direct) field, which the dipole sources reproduce (Sec. 2.1)."""
+    f = 1.0e6
+    xd = orc.sample_disc(0, 4096, A)
+    q = orc.sample_square(1, 1 << 16, 0.0, 0.0, 0.03, 0.03)
+    args = ((0, 0, 0), (0, 0, 1), [q], [0.03], [C_W, C_W], [RHO_W, RHO_W])
+    far = (np.zeros(6), np.zeros(6), np.linspace(0.08, 0.13, 6))
+    omni = orc.chain(xd, 1.0, *args, far, [f], orc.T_UNITY, flags=orc.CHAIN_OMNI)[0]
+    direct = orc.propagate(orc.MONOPOLE, xd[:3], xd[3], 1.0, far, C_W, f)
+    assert rel(omni, direct) < 2e-2
+    # 10 mm below the plane, 20-30 mm off the axis (30-45 deg from the beam region): the
+    # dipole sources reproduce the direct field, the omnidirectional ones exceed it
+    side = (np.linspace(0.02, 0.03, 16), np.zeros(16), np.full(16, 0.04))
+    omni = orc.chain(xd, 1.0, *args, side, [f], orc.T_UNITY, flags=orc.CHAIN_OMNI)[0]
+    dip = orc.chain(xd, 1.0, *args, side, [f], orc.T_UNITY)[0]
+    direct = orc.propagate(orc.MONOPOLE, xd[:3], xd[3], 1.0, side, C_W, f)
+    nd = np.linalg.norm(direct)
+    assert abs(np.linalg.norm(dip) / nd - 1) < 2e-2
+    assert np.linalg.norm(omni) / nd > 1.1
+
+
 # ----------------------------------------------------------------------------- eqs. 8, 11, 15
 IMPEDANCE_CASES = [(1480.0, 1000.0, 5900.0, 7800.0), (5900.0, 7800.0, 2700.0, 2700.0),
                    (1480.0, 1000.0, 6409.0, 2700.0)]

@@ -50,7 +50,7 @@ typedef enum {
     RSI_ERR_UNSUPPORTED = 7  /* the combination of options is not implemented       */
 } rsi_status;
 
-typedef enum { RSI_MONOPOLE = 0, RSI_DIPOLE = 1 } rsi_kernel;
+typedef enum { RSI_MONOPOLE = 0, RSI_DIPOLE = 1, RSI_OMNI = 2 } rsi_kernel;
 typedef enum { RSI_FP32 = 0, RSI_FP64 = 1 } rsi_precision;
 typedef enum { RSI_T_GLOBAL = 0, RSI_T_LOCAL = 1, RSI_T_UNITY = 2 } rsi_tmode;
 
@@ -151,6 +151,15 @@ rsi_status rsi_transmission(rsi_tmode tmode, int m, const double *zif,
                             int64_t n, const double *qx, const double *qy, double *out,
                             void *stream);
 
+/* Velocity-potential reflection coefficient at each sample of interface m (eq. 8):
+ *     R12 = (rho2 c2 cos a1 - rho1 c1 cos a2) / (rho2 c2 cos a1 + rho1 c1 cos a2),
+ * same arguments, incidence angles and complex branch as rsi_transmission
+ * (T = (rho1/rho2)(1 + R12) holds sample by sample); R = 0 for RSI_T_UNITY (the media
+ * matched).  The reflected field of rsi_chain_ex(RSI_CHAIN_ABOVE) uses it. */
+rsi_status rsi_reflection(rsi_tmode tmode, int m, const double *zif, const rsi_medium *media,
+                          const double *xc, const double *axis, int64_t n, const double *qx,
+                          const double *qy, double *out, void *stream);
+
 /* ------------------------------------------------------------------------------
  * a3/a4. The pair sum (eqs. 3, 7; estimator eq. 16).
  * ------------------------------------------------------------------------------ */
@@ -161,6 +170,10 @@ rsi_status rsi_transmission(rsi_tmode tmode, int m, const double *zif,
  *                 (the first Rayleigh-Sommerfeld solution, eqs. 2 and 7, with the
  *                 overall sign that reproduces a field continued through a
  *                 transparent plane)
+ *   RSI_OMNI:     K = ik e^{ikr}/r: an interface sample as an omnidirectional point
+ *                 source, without the directivity cos(theta) and the near-field term
+ *                 -1/r (the formulation Sec. 2.1 contrasts with eq. 2, attributed to
+ *                 Zhang et al. 2022; kept for the ablation)
  * k = 2 pi freq / medium.c.  src_vel: device complex FP64 [src->n] (s_j, e.g.
  * T_j phi_in(Q_j)); normal: host double[3], required for RSI_DIPOLE (need not be
  * unit: it is normalised), ignored otherwise.  out: device complex [tgt->n] of the
@@ -208,6 +221,30 @@ rsi_status rsi_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int 
                      int n_freq, rsi_tmode tmode, rsi_precision prec, void *out,
                      void *stream);
 
+/* Flags of rsi_chain_ex and rsi_plan_create_chain_ex. */
+enum {
+    /* Interface samples radiate with RSI_OMNI instead of RSI_DIPOLE (the ablation of
+     * the dipole and directivity terms, Sec. 2.1). */
+    RSI_CHAIN_OMNI = 1u,
+    /* The field points lie in medium n_if - 1, above the last interface (n_if >= 1).
+     * out = incident + reflected field there: the incident field is the chain through
+     * interfaces 1..n_if-1 evaluated at the points (the transducer's own field for
+     * n_if = 1); the reflected field radiates the boundary values R(Q_j) phi_inc(Q_j)
+     * of the last interface (rsi_reflection with `tmode`; the approximation
+     * phi_r = R12 phi_i that also yields eq. 7) back into medium n_if - 1, i.e. the
+     * interface kernel with normal -z (eqs. 4-5).  With the fields below the
+     * interface from rsi_chain, p = i omega rho phi on both sides gives the pressure
+     * continuity of eq. 6. */
+    RSI_CHAIN_ABOVE = 2u
+};
+
+/* rsi_chain with flags (a bitwise OR of RSI_CHAIN_*; 0 is rsi_chain).  RSI_ERR_ARG
+ * for unknown flags or RSI_CHAIN_ABOVE with n_if = 0. */
+rsi_status rsi_chain_ex(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
+                        const rsi_medium *media, const rsi_points *tgt, const double *freqs,
+                        int n_freq, rsi_tmode tmode, rsi_precision prec, uint32_t flags,
+                        void *out, void *stream);
+
 /* ------------------------------------------------------------------------------
  * a7. Batching: persistent launches, plans and graph replay.
  * ------------------------------------------------------------------------------ */
@@ -230,6 +267,11 @@ rsi_status rsi_plan_create_chain(rsi_plan **plan, const rsi_transducer *xd,
                                  const rsi_medium *media, const rsi_points *tgt,
                                  const double *freqs, int n_freq, rsi_tmode tmode,
                                  rsi_precision prec, void *out);
+rsi_status rsi_plan_create_chain_ex(rsi_plan **plan, const rsi_transducer *xd,
+                                    const rsi_interface *ifaces, int n_if,
+                                    const rsi_medium *media, const rsi_points *tgt,
+                                    const double *freqs, int n_freq, rsi_tmode tmode,
+                                    rsi_precision prec, uint32_t flags, void *out);
 rsi_status rsi_plan_create_batched(rsi_plan **plan, const rsi_instance *inst, int n_inst,
                                    rsi_precision prec);
 rsi_status rsi_plan_execute(rsi_plan *plan, void *stream);

@@ -38,7 +38,8 @@ struct InstDev {
 struct PrepDev {
     const double *x, *y, *z, *w, *vel;
     double v0, nx, ny, nz;
-    double lam;  // c / f of the instance (phase offset of complex strengths)
+    double lam;       // c / f of the instance (phase offset of complex strengths)
+    double Fre, Fim;  // strength factor: 1, or ik for RSI_OMNI
     int64_t n;
     double *partials;  // [kBBoxBlocks * 6]
     double *anchor;    // [4]
@@ -115,8 +116,8 @@ __global__ void __launch_bounds__(256) prep_batched_kernel(const PrepDev *__rest
         r.y = p.y[j];
         r.z = p.z[j];
         r.pad0 = 0.0;
-        r.sre = scale * sre;
-        r.sim = scale * sim;
+        r.sre = scale * (sre * p.Fre - sim * p.Fim);
+        r.sim = scale * (sre * p.Fim + sim * p.Fre);
         r.pad1 = r.pad2 = 0.0;
         p.recd[j] = r;
     } else {
@@ -148,7 +149,8 @@ __global__ void __launch_bounds__(256) prep_batched_kernel(const PrepDev *__rest
         r.ey = ey;
         r.ez = ez;
         r.es2 = (float)(dex * dex + dey * dey + dez * dez);
-        polar_strength(scale * sre, scale * sim, p.lam, r.a, r.psil);
+        polar_strength(scale * (sre * p.Fre - sim * p.Fim), scale * (sre * p.Fim + sim * p.Fre), p.lam, r.a,
+                       r.psil);
         r.h = (float)(p.nx * dex + p.ny * dey + p.nz * dez);
         r.pad = 0.0f;
         p.recf[j] = r;
@@ -280,7 +282,7 @@ static rsi_status validate_instances(const rsi_instance *inst, int n_inst, rsi_p
     if (prec != RSI_FP32 && prec != RSI_FP64) return RSI_ERR_ARG;
     for (int i = 0; i < n_inst; ++i) {
         const rsi_instance &a = inst[i];
-        if (a.kind != RSI_MONOPOLE && a.kind != RSI_DIPOLE) return RSI_ERR_ARG;
+        if (a.kind != RSI_MONOPOLE && a.kind != RSI_DIPOLE && a.kind != RSI_OMNI) return RSI_ERR_ARG;
         if (!(a.freq > 0.0) || !(a.medium.c > 0.0) || !std::isfinite(a.freq)) return RSI_ERR_ARG;
         if (a.src.n < 0 || a.tgt.n < 0) return RSI_ERR_SIZE;
         if (a.tgt.n > 0 && (!a.out || !a.tgt.x || !a.tgt.y || !a.tgt.z)) return RSI_ERR_NULL;
@@ -323,7 +325,7 @@ static rsi_status build_tables(const rsi_instance *inst, int n_inst, rsi_precisi
             d.ny = a.normal[1] / l;
             d.nz = a.normal[2] / l;
         }
-        d.kind = a.kind;
+        d.kind = a.kind == RSI_OMNI ? RSI_MONOPOLE : a.kind;  // omni: monopole of strengths x ik
         d.out = a.out;
         const int64_t nchunks = a.src.n > 0 ? (a.src.n + chunk - 1) / chunk : 1;
         d.n_chunks = (int32_t)nchunks;
@@ -350,6 +352,8 @@ static rsi_status build_tables(const rsi_instance *inst, int n_inst, rsi_precisi
         p.vel = a.vel;
         p.v0 = a.v0;
         p.lam = a.medium.c / a.freq;
+        p.Fre = a.kind == RSI_OMNI ? 0.0 : 1.0;
+        p.Fim = a.kind == RSI_OMNI ? d.k : 0.0;
         p.nx = d.nx;
         p.ny = d.ny;
         p.nz = d.nz;
@@ -621,13 +625,13 @@ using namespace rsi;
 
 extern "C" {
 
-rsi_status rsi_plan_create_chain(rsi_plan **plan, const rsi_transducer *xd,
-                                 const rsi_interface *ifaces, int n_if, const rsi_medium *media,
-                                 const rsi_points *tgt, const double *freqs, int n_freq,
-                                 rsi_tmode tmode, rsi_precision prec, void *out) {
+rsi_status rsi_plan_create_chain_ex(rsi_plan **plan, const rsi_transducer *xd,
+                                    const rsi_interface *ifaces, int n_if, const rsi_medium *media,
+                                    const rsi_points *tgt, const double *freqs, int n_freq,
+                                    rsi_tmode tmode, rsi_precision prec, uint32_t flags, void *out) {
     if (!plan) return RSI_ERR_NULL;
     *plan = nullptr;
-    RSI_TRY(validate_chain(xd, ifaces, n_if, media, tgt, freqs, n_freq, tmode, prec, out));
+    RSI_TRY(validate_chain(xd, ifaces, n_if, media, tgt, freqs, n_freq, tmode, prec, flags, out));
     std::unique_ptr<rsi_plan> p(new rsi_plan);
     p->type = 0;
     auto alloc = [&](void **ptr, size_t bytes) -> rsi_status {
@@ -636,7 +640,7 @@ rsi_status rsi_plan_create_chain(rsi_plan **plan, const rsi_transducer *xd,
         *ptr = p->bufs.back()->as<void>();
         return RSI_OK;
     };
-    RSI_TRY(alloc_chain(alloc, xd, ifaces, n_if, tgt, freqs, n_freq, prec, p->W));
+    RSI_TRY(alloc_chain(alloc, xd, ifaces, n_if, tgt, freqs, n_freq, prec, flags, p->W));
     // copies of the host descriptors: the captured graph keeps only device pointers and
     // kernel arguments, so nothing here needs to outlive the call
     if (tgt->n > 0 && n_freq > 0) {
@@ -647,6 +651,14 @@ rsi_status rsi_plan_create_chain(rsi_plan **plan, const rsi_transducer *xd,
     }
     *plan = p.release();
     return RSI_OK;
+}
+
+rsi_status rsi_plan_create_chain(rsi_plan **plan, const rsi_transducer *xd,
+                                 const rsi_interface *ifaces, int n_if, const rsi_medium *media,
+                                 const rsi_points *tgt, const double *freqs, int n_freq,
+                                 rsi_tmode tmode, rsi_precision prec, void *out) {
+    return rsi_plan_create_chain_ex(plan, xd, ifaces, n_if, media, tgt, freqs, n_freq, tmode, prec, 0u,
+                                    out);
 }
 
 rsi_status rsi_plan_create_batched(rsi_plan **plan, const rsi_instance *inst, int n_inst,

@@ -163,16 +163,21 @@ struct PairShape {
 rsi_status bbox_partials(const rsi_points &pts, double *partials /*[kBBoxBlocks*6]*/,
                          hipStream_t s);
 constexpr int kBBoxBlocks = 64;
-// lam = c / f of the stage: needed only for complex strengths (vel != NULL)
+// Strengths are folded as -(1/2pi) w_j s_j F with a stage factor F (1; ik for RSI_OMNI
+// sources; -1 for a dipole radiating along -z).  lam = c / f of the stage: needed only
+// for complex strengths (vel != NULL or F not real).
+struct Cplx {
+    double re, im;
+};
 rsi_status prep_sources_f32(const rsi_points &pts, const double *w, const double *vel,
                             double v0, const double *normal, const double *partials,
-                            double lam, SrcSetF &set, hipStream_t s);
+                            double lam, Cplx F, SrcSetF &set, hipStream_t s);
 rsi_status set_strength_f32(SrcSetF &set, const double *w, const void *field, bool field_fp64,
-                            const double *tco, double lam, hipStream_t s);
+                            const double *tco, double lam, Cplx F, hipStream_t s);
 rsi_status prep_sources_f64(const rsi_points &pts, const double *w, const double *vel,
-                            double v0, SrcSetD &set, hipStream_t s);
+                            double v0, Cplx F, SrcSetD &set, hipStream_t s);
 rsi_status set_strength_f64(SrcSetD &set, const double *w, const double *field,
-                            const double *tco, hipStream_t s);
+                            const double *tco, Cplx F, hipStream_t s);
 PairShape default_shape(int64_t n_src, int64_t n_tgt);
 int64_t partial_slots(const PairShape &sh, int64_t n_src, int64_t n_tgt);
 // planar_z: every source lies on the plane z = const through the set's anchor (normal
@@ -188,8 +193,10 @@ rsi_status pairsum_f64(const SrcSetD &set, const Targets &t, rsi_kernel kind,
 // True when freqs[0..n) is a uniform grid f0 + q df (n >= 2, df > 0).
 bool uniform_grid(const double *freqs, int n, double &f0, double &df);
 // S [n][n_freq rounded up to the frequency block] of -(1/2pi) w T phi from field [n_freq][n].
+// S[j][q] = -(1/2pi) w_j T_j field_q(Q_j) (Fa + i Fb k_q), k_q = 2 pi (f0 + q df) / c
 rsi_status strength_multifreq(int64_t n, int n_freq, const double *w, const float2 *field,
-                              const double *tco, float2 *S, hipStream_t s);
+                              const double *tco, double Fa, double Fb, double c, double f0,
+                              double df, float2 *S, hipStream_t s);
 // One stage for all frequencies; S == nullptr: the record strengths serve every frequency.
 rsi_status pairsum_multifreq_f32(const SrcSetF &set, const float2 *S, const Targets &t,
                                  rsi_kernel kind, bool planar_z, double c, double f0, double df,
@@ -207,18 +214,27 @@ struct ChainWork {
     float2 *S = nullptr;      // multi-frequency strengths
     bool multifreq = false;   // FP32 on a uniform frequency grid: one launch per stage
     double f0 = 0.0, df = 0.0;
+    uint32_t flags = 0;       // RSI_CHAIN_*
+    double *rco = nullptr;    // RSI_CHAIN_ABOVE: reflection coefficients of the last interface
+    void *above = nullptr;    // RSI_CHAIN_ABOVE: reflected field at the points
 };
 using AllocFn = std::function<rsi_status(void **, size_t)>;
 rsi_status validate_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
                           const rsi_medium *media, const rsi_points *tgt, const double *freqs,
-                          int n_freq, rsi_tmode tmode, rsi_precision prec, void *out);
+                          int n_freq, rsi_tmode tmode, rsi_precision prec, uint32_t flags,
+                          void *out);
 rsi_status alloc_chain(const AllocFn &alloc, const rsi_transducer *xd,
                        const rsi_interface *ifaces, int n_if, const rsi_points *tgt,
-                       const double *freqs, int n_freq, rsi_precision prec, ChainWork &W);
+                       const double *freqs, int n_freq, rsi_precision prec, uint32_t flags,
+                       ChainWork &W);
 rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
                          const rsi_medium *media, const rsi_points *tgt, const double *freqs,
                          int n_freq, rsi_tmode tmode, rsi_precision prec, void *out,
                          ChainWork &W, hipStream_t s);
+rsi_status coefficient_device(bool reflect, rsi_tmode tmode, int m, const double *zif,
+                              const rsi_medium *media, const double *xc, const double *axis,
+                              int64_t n, const double *qx, const double *qy, double *out,
+                              hipStream_t s);
 rsi_status transmission_device(rsi_tmode tmode, int m, const double *zif,
                                const rsi_medium *media, const double *xc, const double *axis,
                                int64_t n, const double *qx, const double *qy, double *out,

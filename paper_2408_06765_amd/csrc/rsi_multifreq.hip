@@ -111,11 +111,13 @@ __global__ void __launch_bounds__(kBlock) multifreq_f32_kernel(
         if (q0 + q < n_freq) out[(int64_t)(q0 + q) * n_tgt + i] = make_float2(mre[q], mim[q]);
 }
 
-// S[j][q] = -(1/2pi) w_j T_j phi_q(Q_j) for q < n_freq, 0 for the padding.
+// S[j][q] = -(1/2pi) w_j T_j phi_q(Q_j) F_q for q < n_freq, 0 for the padding, with the
+// stage factor F_q = Fa + i Fb k_q (1; ik_q for omnidirectional sources; -1 for a dipole
+// radiating along -z), k_q = 2 pi (f0 + q df) / c.
 __global__ void __launch_bounds__(256) strength_multifreq_kernel(
     int64_t n, int n_freq, int nf_pad, const double *__restrict__ w,
     const float2 *__restrict__ field /* [n_freq][n] */, const double *__restrict__ tco,
-    float2 *__restrict__ S) {
+    double Fa, double Fb, double c, double f0, double df, float2 *__restrict__ S) {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= n * nf_pad) return;
     const int64_t j = g / nf_pad;
@@ -125,8 +127,10 @@ __global__ void __launch_bounds__(256) strength_multifreq_kernel(
         const float2 f = field[(int64_t)q * n + j];
         const double tre = tco[2 * j], tim = tco[2 * j + 1];
         const double scale = -w[j] / kTwoPi;
-        r.x = (float)(scale * (tre * f.x - tim * f.y));
-        r.y = (float)(scale * (tre * f.y + tim * f.x));
+        const double sre = tre * f.x - tim * f.y, sim = tre * f.y + tim * f.x;
+        const double Fi = Fb * kTwoPi * (f0 + q * df) / c;
+        r.x = (float)(scale * (sre * Fa - sim * Fi));
+        r.y = (float)(scale * (sre * Fi + sim * Fa));
     }
     S[g] = r;
 }
@@ -142,12 +146,13 @@ bool uniform_grid(const double *freqs, int n, double &f0, double &df) {
 }
 
 rsi_status strength_multifreq(int64_t n, int n_freq, const double *w, const float2 *field,
-                              const double *tco, float2 *S, hipStream_t s) {
+                              const double *tco, double Fa, double Fb, double c, double f0,
+                              double df, float2 *S, hipStream_t s) {
     if (n == 0) return RSI_OK;
     const int nf_pad = (n_freq + kFB - 1) / kFB * kFB;
     const int64_t total = n * nf_pad;
     hipLaunchKernelGGL(strength_multifreq_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
-                       0, s, n, n_freq, nf_pad, w, field, tco, S);
+                       0, s, n, n_freq, nf_pad, w, field, tco, Fa, Fb, c, f0, df, S);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }

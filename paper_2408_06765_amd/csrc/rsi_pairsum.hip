@@ -96,8 +96,8 @@ rsi_status bbox_partials(const rsi_points &pts, double *partials, hipStream_t s)
 __global__ void __launch_bounds__(256) prep_f32_kernel(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ w, const double *__restrict__ vel,
-    double v0, double nx, double ny, double nz, double lam, const double *__restrict__ partials,
-    double *__restrict__ anchor_out, SrcRecF *__restrict__ rec) {
+    double v0, double nx, double ny, double nz, double lam, double fre, double fim,
+    const double *__restrict__ partials, double *__restrict__ anchor_out, SrcRecF *__restrict__ rec) {
     double ax, ay, az, radius;
     anchor_from_partials(partials, ax, ay, az, radius);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -121,18 +121,21 @@ __global__ void __launch_bounds__(256) prep_f32_kernel(
     r.ey = ey;
     r.ez = ez;
     r.es2 = (float)(dex * dex + dey * dey + dez * dez);
-    polar_strength(scale * sre, scale * sim, lam, r.a, r.psil);
+    polar_strength(scale * (sre * fre - sim * fim), scale * (sre * fim + sim * fre), lam, r.a, r.psil);
     r.h = (float)(nx * dex + ny * dey + nz * dez);
     r.pad = 0.0f;
     rec[j] = r;
 }
 
-// s_j = T_j phi_j (interface strength, eq. 7) folded with -(1/2pi) w_j.
+// s_j = T_j phi_j (interface strength, eq. 7; R_j phi_j for a reflection) times the
+// stage factor F (1; ik for omnidirectional sources; -1 for a dipole radiating along
+// -z), folded with -(1/2pi) w_j.
 template <typename FieldT>
 __global__ void __launch_bounds__(256) strength_f32_kernel(int64_t n, const double *__restrict__ w,
                                                            const FieldT *__restrict__ field,
                                                            const double *__restrict__ tco,
-                                                           double lam, SrcRecF *__restrict__ rec) {
+                                                           double lam, double Fre, double Fim,
+                                                           SrcRecF *__restrict__ rec) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     const double fre = field[2 * j], fim = field[2 * j + 1];
@@ -144,7 +147,7 @@ __global__ void __launch_bounds__(256) strength_f32_kernel(int64_t n, const doub
     }
     const double scale = -w[j] / kTwoPi;
     float a, psil;
-    polar_strength(scale * sre, scale * sim, lam, a, psil);
+    polar_strength(scale * (sre * Fre - sim * Fim), scale * (sre * Fim + sim * Fre), lam, a, psil);
     rec[j].a = a;
     rec[j].psil = psil;
 }
@@ -154,6 +157,7 @@ __global__ void __launch_bounds__(256) prep_f64_kernel(int64_t n, const double *
                                                        const double *__restrict__ z,
                                                        const double *__restrict__ w,
                                                        const double *__restrict__ vel, double v0,
+                                                       double Fre, double Fim,
                                                        SrcRecD *__restrict__ rec) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
@@ -168,8 +172,8 @@ __global__ void __launch_bounds__(256) prep_f64_kernel(int64_t n, const double *
     r.y = y[j];
     r.z = z[j];
     r.pad0 = 0.0;
-    r.sre = scale * sre;
-    r.sim = scale * sim;
+    r.sre = scale * (sre * Fre - sim * Fim);
+    r.sim = scale * (sre * Fim + sim * Fre);
     r.pad1 = r.pad2 = 0.0;
     rec[j] = r;
 }
@@ -177,6 +181,7 @@ __global__ void __launch_bounds__(256) prep_f64_kernel(int64_t n, const double *
 __global__ void __launch_bounds__(256) strength_f64_kernel(int64_t n, const double *__restrict__ w,
                                                            const double *__restrict__ field,
                                                            const double *__restrict__ tco,
+                                                           double Fre, double Fim,
                                                            SrcRecD *__restrict__ rec) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
@@ -188,8 +193,8 @@ __global__ void __launch_bounds__(256) strength_f64_kernel(int64_t n, const doub
         sim = tre * fim + tim * fre;
     }
     const double scale = -w[j] / kTwoPi;
-    rec[j].sre = scale * sre;
-    rec[j].sim = scale * sim;
+    rec[j].sre = scale * (sre * Fre - sim * Fim);
+    rec[j].sim = scale * (sre * Fim + sim * Fre);
 }
 
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -207,45 +212,45 @@ static void unit_normal(const double *normal, double &nx, double &ny, double &nz
 
 rsi_status prep_sources_f32(const rsi_points &pts, const double *w, const double *vel,
                             double v0, const double *normal, const double *partials,
-                            double lam, SrcSetF &set, hipStream_t s) {
+                            double lam, Cplx F, SrcSetF &set, hipStream_t s) {
     double nx, ny, nz;
     unit_normal(normal, nx, ny, nz);
     set.n = pts.n;
     if (pts.n == 0) return RSI_OK;
     hipLaunchKernelGGL(prep_f32_kernel, dim3(blocks_for(pts.n)), dim3(256), 0, s, pts.n, pts.x,
-                       pts.y, pts.z, w, vel, v0, nx, ny, nz, lam, partials, set.anchor, set.rec);
+                       pts.y, pts.z, w, vel, v0, nx, ny, nz, lam, F.re, F.im, partials, set.anchor, set.rec);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }
 
 rsi_status set_strength_f32(SrcSetF &set, const double *w, const void *field, bool field_fp64,
-                            const double *tco, double lam, hipStream_t s) {
+                            const double *tco, double lam, Cplx F, hipStream_t s) {
     if (set.n == 0) return RSI_OK;
     if (field_fp64)
         hipLaunchKernelGGL(strength_f32_kernel<double>, dim3(blocks_for(set.n)), dim3(256), 0, s,
-                           set.n, w, static_cast<const double *>(field), tco, lam, set.rec);
+                           set.n, w, static_cast<const double *>(field), tco, lam, F.re, F.im, set.rec);
     else
         hipLaunchKernelGGL(strength_f32_kernel<float>, dim3(blocks_for(set.n)), dim3(256), 0, s,
-                           set.n, w, static_cast<const float *>(field), tco, lam, set.rec);
+                           set.n, w, static_cast<const float *>(field), tco, lam, F.re, F.im, set.rec);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }
 
 rsi_status prep_sources_f64(const rsi_points &pts, const double *w, const double *vel,
-                            double v0, SrcSetD &set, hipStream_t s) {
+                            double v0, Cplx F, SrcSetD &set, hipStream_t s) {
     set.n = pts.n;
     if (pts.n == 0) return RSI_OK;
     hipLaunchKernelGGL(prep_f64_kernel, dim3(blocks_for(pts.n)), dim3(256), 0, s, pts.n, pts.x,
-                       pts.y, pts.z, w, vel, v0, set.rec);
+                       pts.y, pts.z, w, vel, v0, F.re, F.im, set.rec);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }
 
 rsi_status set_strength_f64(SrcSetD &set, const double *w, const double *field,
-                            const double *tco, hipStream_t s) {
+                            const double *tco, Cplx F, hipStream_t s) {
     if (set.n == 0) return RSI_OK;
     hipLaunchKernelGGL(strength_f64_kernel, dim3(blocks_for(set.n)), dim3(256), 0, s, set.n, w,
-                       field, tco, set.rec);
+                       field, tco, F.re, F.im, set.rec);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }
@@ -467,7 +472,7 @@ extern "C" rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_
     if ((flags & ~(uint32_t)RSI_FLAG_PLANAR_Z) != 0) return RSI_ERR_ARG;
     const bool planar = (flags & RSI_FLAG_PLANAR_Z) != 0;
     if (!src || !tgt) return RSI_ERR_NULL;
-    if (kind != RSI_MONOPOLE && kind != RSI_DIPOLE) return RSI_ERR_ARG;
+    if (kind != RSI_MONOPOLE && kind != RSI_DIPOLE && kind != RSI_OMNI) return RSI_ERR_ARG;
     if (prec != RSI_FP32 && prec != RSI_FP64) return RSI_ERR_ARG;
     if (!(freq > 0.0) || !(medium.c > 0.0) || !std::isfinite(freq) || !std::isfinite(medium.c))
         return RSI_ERR_ARG;
@@ -484,6 +489,9 @@ extern "C" rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_
     hipStream_t s = as_stream(stream);
     Scratch scratch(s);
     const Targets t{tgt->x, tgt->y, tgt->z, tgt->n};
+    // RSI_OMNI = the monopole sum of strengths times ik
+    const Cplx F = kind == RSI_OMNI ? Cplx{0.0, kTwoPi * freq / medium.c} : Cplx{1.0, 0.0};
+    const rsi_kernel kk = kind == RSI_OMNI ? RSI_MONOPOLE : kind;
     const PairShape sh = default_shape(src->n, tgt->n);
     const int64_t nslots = partial_slots(sh, src->n, tgt->n);
     if (prec == RSI_FP32) {
@@ -495,20 +503,21 @@ extern "C" rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_
             RSI_TRY(scratch.alloc(&set.anchor, 4));
             RSI_TRY(scratch.alloc(&partials, kBBoxBlocks * 6));
             RSI_TRY(bbox_partials(*src, partials, s));
-            RSI_TRY(prep_sources_f32(*src, src_w, src_vel, 0.0, normal, partials, medium.c / freq, set, s));
+            RSI_TRY(prep_sources_f32(*src, src_w, src_vel, 0.0, normal, partials, medium.c / freq, F,
+                                     set, s));
         }
         if (nslots > 0) RSI_TRY(scratch.alloc(&partial, (size_t)nslots));
-        return pairsum_f32(set, t, kind, normal, medium.c, freq, sh, partial,
+        return pairsum_f32(set, t, kk, normal, medium.c, freq, sh, partial,
                            static_cast<float2 *>(out), s, planar);
     }
     SrcSetD set;
     double2 *partial = nullptr;
     if (src->n > 0) {
         RSI_TRY(scratch.alloc(&set.rec, (size_t)src->n));
-        RSI_TRY(prep_sources_f64(*src, src_w, src_vel, 0.0, set, s));
+        RSI_TRY(prep_sources_f64(*src, src_w, src_vel, 0.0, F, set, s));
     }
     if (nslots > 0) RSI_TRY(scratch.alloc(&partial, (size_t)nslots));
-    return pairsum_f64(set, t, kind, normal, medium.c, freq, sh, partial,
+    return pairsum_f64(set, t, kk, normal, medium.c, freq, sh, partial,
                        static_cast<double2 *>(out), s);
 }
 

@@ -136,7 +136,7 @@ const char *rsi_status_string(rsi_status s) {
 
 const char *rsi_last_error(void) { return g_last_error.c_str(); }
 
-int rsi_version(void) { return (1 << 16) | 0; }
+int rsi_version(void) { return (1 << 16) | 1; }
 
 rsi_status rsi_sobol2d(uint32_t seed, int64_t first, int64_t n, uint32_t *out, void *stream) {
     if (first < 0 || n < 0 || first + n > (int64_t(1) << 32)) return RSI_ERR_SIZE;

@@ -15,10 +15,11 @@ import torch
 
 from . import _lib as L
 
-RSI_MONOPOLE, RSI_DIPOLE = 0, 1
+RSI_MONOPOLE, RSI_DIPOLE, RSI_OMNI = 0, 1, 2
 RSI_FP32, RSI_FP64 = 0, 1
 RSI_T_GLOBAL, RSI_T_LOCAL, RSI_T_UNITY = 0, 1, 2
 RSI_FLAG_PLANAR_Z = 1
+RSI_CHAIN_OMNI, RSI_CHAIN_ABOVE = 1, 2
 
 _OUT_DTYPE = {RSI_FP32: torch.complex64, RSI_FP64: torch.complex128}
 
@@ -101,6 +102,18 @@ def rsi_transmission(tmode: int, m: int, zif: Sequence[float], media, xc, axis,
     return out
 
 
+def rsi_reflection(tmode: int, m: int, zif: Sequence[float], media, xc, axis,
+                   qx: torch.Tensor, qy: torch.Tensor) -> torch.Tensor:
+    """Per-sample reflection coefficient (eq. 8) at interface m (1-based), complex128."""
+    _dev(qx, torch.float64, "qx")
+    _dev(qy, torch.float64, "qy")
+    out = torch.empty(qx.numel(), dtype=torch.complex128, device=qx.device)
+    L.check(L.load().rsi_reflection(tmode, m, _dvec(zif), _media(media), _dvec(xc), _dvec(axis),
+                                    qx.numel(), _ptr(qx), _ptr(qy), _ptr(out), _stream()),
+            "rsi_reflection")
+    return out
+
+
 # ---------------------------------------------------------------------------- a3/a4
 def rsi_propagate(src, w: torch.Tensor, vel: torch.Tensor, tgt, c: float, freq: float,
                   kind: int, prec: int, normal=None, rho: float = 1000.0,
@@ -171,14 +184,16 @@ def _chain_args(xd: Transducer, ifaces: Sequence[Interface], media, tgt, freqs):
 
 
 def rsi_chain(xd: Transducer, ifaces: Sequence[Interface], media, tgt, freqs, tmode: int,
-              prec: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Field after the whole stack, complex [n_freq, n_tgt]."""
+              prec: int, out: Optional[torch.Tensor] = None, flags: int = 0) -> torch.Tensor:
+    """Field after the whole stack, complex [n_freq, n_tgt] (rsi_chain_ex with
+    RSI_CHAIN_* flags: omnidirectional interface sources, or field points above the
+    last interface with the reflected field)."""
     xs, arr, med, tp, fr = _chain_args(xd, ifaces, media, tgt, freqs)
     if out is None:
         out = torch.empty((len(freqs), tp.n), dtype=_OUT_DTYPE[prec], device=tgt[0].device)
     _dev(out, _OUT_DTYPE[prec], "out")
-    L.check(L.load().rsi_chain(C.byref(xs), arr, len(ifaces), med, C.byref(tp), fr, len(freqs),
-                               tmode, prec, _ptr(out), _stream()), "rsi_chain")
+    L.check(L.load().rsi_chain_ex(C.byref(xs), arr, len(ifaces), med, C.byref(tp), fr, len(freqs),
+                                  tmode, prec, flags, _ptr(out), _stream()), "rsi_chain_ex")
     return out
 
 
@@ -238,14 +253,15 @@ class Plan:
 
     @classmethod
     def chain(cls, xd: Transducer, ifaces: Sequence[Interface], media, tgt, freqs, tmode: int,
-              prec: int, out: Optional[torch.Tensor] = None) -> "Plan":
+              prec: int, out: Optional[torch.Tensor] = None, flags: int = 0) -> "Plan":
         xs, arr, med, tp, fr = _chain_args(xd, ifaces, media, tgt, freqs)
         if out is None:
             out = torch.empty((len(freqs), tp.n), dtype=_OUT_DTYPE[prec], device=tgt[0].device)
         h = C.c_void_p()
-        L.check(L.load().rsi_plan_create_chain(C.byref(h), C.byref(xs), arr, len(ifaces), med,
-                                               C.byref(tp), fr, len(freqs), tmode, prec, _ptr(out)),
-                "rsi_plan_create_chain")
+        L.check(L.load().rsi_plan_create_chain_ex(C.byref(h), C.byref(xs), arr, len(ifaces), med,
+                                                  C.byref(tp), fr, len(freqs), tmode, prec, flags,
+                                                  _ptr(out)),
+                "rsi_plan_create_chain_ex")
         plan = cls(h, [xd, list(ifaces), tgt])
         plan.out = out
         return plan

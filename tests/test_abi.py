@@ -81,8 +81,9 @@ def test_argument_errors_before_any_device_work():
     assert lib.rsi_propagate(C.byref(pts), None, None, None, C.byref(pts), med, -1.0, 0, 0, None, None) == 2
     assert lib.rsi_propagate(C.byref(pts), None, None, None, C.byref(pts), L.rsi_medium(0.0, 1.0), 1e6, 0, 0,
                              None, None) == 2
-    # unknown kind / precision
+    # unknown kind / precision (0 monopole, 1 dipole, 2 omnidirectional)
     assert lib.rsi_propagate(C.byref(pts), None, None, None, C.byref(pts), med, 1e6, 7, 0, None, None) == 2
+    assert lib.rsi_propagate(C.byref(pts), None, None, None, C.byref(empty), med, 1e6, 2, 0, None, None) == 0
     assert lib.rsi_propagate(C.byref(pts), None, None, None, C.byref(pts), med, 1e6, 0, 9, None, None) == 2
     # negative sizes
     neg = L.rsi_points(None, None, None, -1)
@@ -117,6 +118,17 @@ def test_chain_validation():
     assert lib.rsi_chain(C.byref(xd), ifs, 1, media, C.byref(tgt), fr, 1, 5, 0, None, None) == 2
     # too many interfaces
     assert lib.rsi_chain(C.byref(xd), ifs, 1000, media, C.byref(tgt), fr, 1, 1, 0, None, None) == 3
+    # chain flags: unknown bits, and the above mode without an interface
+    assert lib.rsi_chain_ex(C.byref(xd), ifs, 1, media, C.byref(tgt), fr, 1, 1, 0, 4, None, None) == 2
+    assert lib.rsi_chain_ex(C.byref(xd), ifs, 0, media, C.byref(tgt), fr, 1, 1, 0, 2, None, None) == 2
+    plan0 = C.c_void_p()
+    assert lib.rsi_plan_create_chain_ex(C.byref(plan0), C.byref(xd), ifs, 1, media, C.byref(tgt), fr, 1, 1, 0,
+                                        8, None) == 2
+    # valid flags with no field points: nothing to do
+    assert lib.rsi_chain_ex(C.byref(xd), ifs, 1, media, C.byref(tgt), fr, 1, 1, 0, 3, None, None) == 0
+    # reflection coefficients: same argument checks as the transmission coefficients
+    assert lib.rsi_reflection(5, 1, (C.c_double * 1)(0.05), media, None, None, 0, None, None, None, None) == 2
+    assert lib.rsi_reflection(0, 0, (C.c_double * 1)(0.05), media, None, None, 0, None, None, None, None) == 3
     # batched: bad kind is rejected before any allocation
     inst = (L.rsi_instance * 1)()
     inst[0].kind = 5

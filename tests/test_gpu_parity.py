@@ -66,6 +66,19 @@ def test_transmission_matches(gpu, orc, tmode):
         assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("tmode", [0, 1, 2])
+def test_reflection_matches(gpu, orc, tmode):
+    cfg = W.LayeredStack()
+    c = [m[0] for m in cfg.media]
+    rho = [m[1] for m in cfg.media]
+    xc, axis = (0.0, 0.0, 0.0), cfg.axis
+    qx, qy = W.random_cloud(6, 3000, (0.01, 0.0, 0.0), (0.03, 0.03, 0.0))[:2]
+    for m in (1, 2, 3):
+        got = host(gpu.rsi_reflection(tmode, m, cfg.z_if[:m], cfg.media[:m + 1], xc, axis, dev(qx), dev(qy)))
+        ref = orc.reflection(tmode, m, cfg.z_if[:m], c[:m + 1], rho[:m + 1], xc, axis, qx, qy)
+        assert np.max(np.abs(got - ref)) < 1e-12
+
+
 # ----------------------------------------------------------------------------- a3/a4
 SIZES = [(1, 1), (37, 5), (1000, 1237), (5000, 3001), (70001, 613)]
 
@@ -79,11 +92,11 @@ def _case(seed, ns, nt, kind):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1, 2])
 @pytest.mark.parametrize("ns,nt", SIZES)
 def test_propagate_matches_reference(gpu, orc, kind, prec, ns, nt):
     src, w, s, tgt = _case(11 + ns, ns, nt, kind)
-    c, f = (1480.0, 5.0e6) if kind == 0 else (5900.0, 5.0e6)
+    c, f = (5900.0, 5.0e6) if kind == 1 else (1480.0, 5.0e6)
     ref = orc.propagate(kind, src, w, s, tgt, c, f, normal=(0.0, 0.0, 1.0))
     got = host(gpu.rsi_propagate(devpts(src), dev(w), dev(s), devpts(tgt), c, f, kind, prec,
                                  normal=(0.0, 0.0, 1.0)))
@@ -202,6 +215,65 @@ def test_layered_chain_three_frequencies(gpu, orc, prec):
         assert rel(got[f], ref[f]) <= TOL[prec], (f, rel(got[f], ref[f]))
 
 
+def _above_targets(ifs, zs, n, seed):
+    """Field points in the medium above the last interface (between it and the one
+    before, or the transducer)."""
+    z_hi = zs[-1] - 0.0005
+    z_lo = zs[-2] + 0.0005 if len(zs) > 1 else zs[-1] - 0.02
+    cx = float(np.mean(ifs[-1][0]))
+    return W.random_cloud(seed, n, (cx, 0.0, 0.5 * (z_lo + z_hi)), (0.006, 0.004, 0.5 * (z_hi - z_lo)))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("flags", [1, 2, 3])
+@pytest.mark.parametrize("layout", ["one", "stack"])
+@pytest.mark.parametrize("nf", [1, 3])
+def test_chain_modes_match_reference(gpu, orc, prec, flags, layout, nf):
+    """rsi_chain_ex: omnidirectional interface sources (flag 1) and field points above the
+    last interface with the reflected field (flag 2), single frequency and a uniform
+    three-frequency grid (one multi-frequency launch per stage in FP32)."""
+    if layout == "one":
+        tilt = math.radians(10.0)
+        media, zs = (W.WATER, W.STEEL_5900), (0.05,)
+    else:
+        cfg = W.LayeredStack()
+        tilt, media, zs = cfg.tilt, cfg.media, cfg.z_if
+    axis = (math.sin(tilt), 0.0, math.cos(tilt))
+    xd, ifs, tgt = _small_chain(orc, 1 << 12, zs, media, tilt, 600, seed=3)
+    if flags & 2:
+        tgt = _above_targets(ifs, zs, 600, 17)
+    freqs = [2.5e6] if nf == 1 else [1.0e6, 3.0e6, 5.0e6]
+    ref = orc.chain(xd, 1.0, (0, 0, 0), axis, ifs, list(zs), [m[0] for m in media], [m[1] for m in media],
+                    tgt, freqs, 1, flags=flags)
+    T = gpu.Transducer(*devpts(xd[:3]), dev(xd[3]), 1.0, (0.0, 0.0, 0.0), axis)
+    I = [gpu.Interface(*devpts(q[:3]), dev(q[3]), z) for q, z in zip(ifs, zs)]
+    got = host(gpu.rsi_chain(T, I, media, devpts(tgt), freqs, 1, prec, flags=flags))
+    for f in range(nf):
+        assert rel(got[f], ref[f]) <= TOL[prec], (f, rel(got[f], ref[f]))
+
+
+def test_chain_modes_plan_replay(gpu, orc):
+    """A plan of the above mode with omnidirectional sources replays to the eager result
+    bit for bit, with eager work between replays."""
+    import torch
+    cfg = W.LayeredStack()
+    xd, ifs, _ = _small_chain(orc, 1 << 11, cfg.z_if[:2], cfg.media[:3], cfg.tilt, 10)
+    tg = devpts(_above_targets(ifs, cfg.z_if[:2], 500, 5))
+    T = gpu.Transducer(*devpts(xd[:3]), dev(xd[3]), 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    I = [gpu.Interface(*devpts(q[:3]), dev(q[3]), z) for q, z in zip(ifs, cfg.z_if[:2])]
+    freqs = [2e6, 3e6, 4e6]
+    for prec in (0, 1):
+        eager = host(gpu.rsi_chain(T, I, cfg.media[:3], tg, freqs, 1, prec, flags=3))
+        plan = gpu.Plan.chain(T, I, cfg.media[:3], tg, freqs, 1, prec, flags=3)
+        for rep in range(3):
+            plan.out.zero_()
+            plan.execute()
+            torch.cuda.synchronize()
+            _ = torch.randn(100, device="cuda").sum().item()
+            assert np.array_equal(host(plan.out).view(np.uint64), eager.view(np.uint64))
+        plan.destroy()
+
+
 def test_piston_axis_workload(gpu, orc):
     """The 1 MHz piston workload in full: GPU sampling + pair sum vs the reference's own
     samples + sum, and vs the closed-form axis pressure."""
@@ -228,11 +300,11 @@ def _instances(gpu, n_inst, prec, seed=0):
     for i in range(n_inst):
         ns = int(rng.integers(1, 9000)) if i % 5 else 0
         nt = int(rng.integers(1, 3000))
-        kind = i % 2
+        kind = i % 3  # monopole, dipole, omnidirectional
         src, w, s, tgt = _case(100 + i, max(ns, 1), nt, kind)
         src = tuple(v[:ns] for v in src)
         w, s = w[:ns], s[:ns]
-        c = 1480.0 if kind == 0 else 5900.0
+        c = 5900.0 if kind == 1 else 1480.0
         f = 1e6 * (1 + i % 7)
         insts.append(gpu.Instance(devpts(src), dev(w), devpts(tgt), c, f, kind, vel=dev(s),
                                   normal=(0.0, 0.0, 1.0)))

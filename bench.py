@@ -16,6 +16,7 @@ reference timed on the host cores over a bounded sample of the same workload.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -41,7 +42,8 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="one_interface",
-                    choices=["one_interface", "layered_stack", "scan_batch", "surrogate"],
+                    choices=["one_interface", "layered_stack", "scan_batch", "surrogate",
+                             "interface_continuity"],
                     help="one_interface is the benchmark line; the others are secondary "
                          "measurements printed in the same format")
     ap.add_argument("--autotune", action="store_true",
@@ -174,6 +176,89 @@ def layered_stack(args):
     plan.destroy()
 
 
+def interface_continuity(args):
+    """Pressure on both sides of the interface along the beam axis (eq. 6 continuity),
+    for the dipole interface sources of eq. 7 and for the omnidirectional sources of the
+    ablation; |p| normalised by rho1 c1 v0."""
+    import torch
+    from paper_2408_06765_amd import rsi
+    from paper_2408_06765_amd import workloads as W
+
+    cfg = W.InterfaceContinuity()
+    (c1, r1), (c2, r2) = cfg.media
+    xs = rsi.rsi_sample_disc(cfg.xd_seed, cfg.n_xd, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt)
+    q = rsi.rsi_sample_square(cfg.if_seed, cfg.n_if, cfg.patch_centre[0], cfg.patch_centre[1], cfg.z_if,
+                              cfg.half_width)
+    T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    I = [rsi.Interface(*q[:3], q[3], cfg.z_if)]
+    above = tuple(torch.as_tensor(a, device="cuda") for a in cfg.points("above"))
+    below = tuple(torch.as_tensor(a, device="cuda") for a in cfg.points("below"))
+    om = 2 * math.pi * cfg.freq
+    res, timing = {}, {}
+    for name, fl in (("dipole", 0), ("omni", rsi.RSI_CHAIN_OMNI)):
+        for prec in (rsi.RSI_FP32, rsi.RSI_FP64):
+            def run():
+                a = rsi.rsi_chain(T, I, cfg.media, above, [cfg.freq], rsi.RSI_T_LOCAL, prec,
+                                  flags=fl | rsi.RSI_CHAIN_ABOVE)[0]
+                b = rsi.rsi_chain(T, I, cfg.media, below, [cfg.freq], rsi.RSI_T_LOCAL, prec, flags=fl)[0]
+                return a, b
+            run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a, b = run()
+            torch.cuda.synchronize()
+            timing[(name, prec)] = time.perf_counter() - t0
+            p1 = (om * r1 * a.abs() / (r1 * c1)).cpu().numpy()  # |p| / (rho1 c1 v0)
+            p2 = (om * r2 * b.abs() / (r1 * c1)).cpu().numpy()
+            res[(name, prec)] = (p1, p2, a.cpu().numpy(), b.cpu().numpy())
+    # pairs per chain evaluation: piston -> interface, interface -> points, plus the
+    # incident field at the points above
+    n_d = cfg.n_d
+    pairs = 2 * cfg.n_xd * cfg.n_if + cfg.n_if * 2 * n_d + cfg.n_xd * n_d
+    # Above the plane incident and reflected waves interfere (a standing wave of period
+    # about lambda/2), so the upper face is taken at the plane itself: the boundary
+    # value (1 + R) phi_i(Q0) of the model at the axis intercept Q0.  Below, |p| varies
+    # slowly and is extrapolated to the plane from the three nearest points.
+    q0 = tuple(torch.tensor([v], dtype=torch.float64, device="cuda")
+               for v in (cfg.patch_centre[0], cfg.patch_centre[1], cfg.z_if))
+    phi_i = rsi.rsi_propagate(xs[:3], xs[3], torch.ones(cfg.n_xd, dtype=torch.complex128, device="cuda"),
+                              q0, c1, cfg.freq, rsi.RSI_MONOPOLE, rsi.RSI_FP64)[0].item()
+    R0 = rsi.rsi_reflection(rsi.RSI_T_LOCAL, 1, [cfg.z_if], cfg.media, (0.0, 0.0, 0.0), cfg.axis,
+                            q0[0], q0[1])[0].item()
+    p_face_above = om * r1 * abs((1 + R0) * phi_i) / (r1 * c1)
+    d3 = cfg.distances[:3]
+
+    def at_plane(y):
+        return float(np.polyval(np.polyfit(d3, y[:3], 1), 0.0))
+    p_face_dip, p_face_omni = at_plane(res[("dipole", 0)][1]), at_plane(res[("omni", 0)][1])
+    jd, jo = p_face_dip / p_face_above, p_face_omni / p_face_above
+    f32_vs_f64 = max(float(np.linalg.norm(res[(m, 0)][k] - res[(m, 1)][k]) / np.linalg.norm(res[(m, 1)][k]))
+                     for m in ("dipole", "omni") for k in (2, 3))
+    s2 = c2 / c1 * math.sin(cfg.tilt)
+    line = {
+        "metric": "pressure ratio |p2/p1| across the interface on the beam axis (eq. 6)",
+        "value": round(float(jd), 4), "unit": "ratio", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(1e3 * timing[("dipole", 0)], 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "interface_continuity: tilted piston (10 deg) 2^16 -> water/5900 m/s "
+                               "interface 2^22 samples, 2.5 MHz, local T; 10 points 0.1-1 mm each side"},
+        "omni_ratio": round(float(jo), 4),
+        "p_face_above_boundary_value": round(float(p_face_above), 5),
+        "p_face_below_dipole_extrapolated": round(p_face_dip, 5),
+        "p_face_below_omni_extrapolated": round(p_face_omni, 5),
+        "omni_ratio_expected_plane_wave": round(1.0 / math.sqrt(1 - s2 * s2), 4),
+        "distance_mm": [round(1e3 * d, 4) for d in cfg.distances],
+        "p_above_dipole": [round(float(v), 5) for v in res[("dipole", 0)][0]],
+        "p_below_dipole": [round(float(v), 5) for v in res[("dipole", 0)][1]],
+        "p_above_omni": [round(float(v), 5) for v in res[("omni", 0)][0]],
+        "p_below_omni": [round(float(v), 5) for v in res[("omni", 0)][1]],
+        "fp32_vs_fp64_rel_l2": f32_vs_f64,
+        "gpairs_per_s_fp32": round(pairs / timing[("dipole", 0)] / 1e9, 1),
+        "gpairs_per_s_fp64": round(pairs / timing[("dipole", 1)] / 1e9, 1),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def scan_batch(args):
     """256 uneven scan positions in one persistent launch (batched plan)."""
     import torch
@@ -263,6 +348,8 @@ def main():
 
     if args.workload == "layered_stack":
         return layered_stack(args)
+    if args.workload == "interface_continuity":
+        return interface_continuity(args)
     if args.workload == "scan_batch":
         return scan_batch(args)
     if args.workload == "surrogate":

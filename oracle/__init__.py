@@ -54,6 +54,12 @@ def _load():
                               C.c_int, _dp, C.c_int, _dp]
     lib.orc_chain_ex.argtypes = lib.orc_chain.argtypes[:-1] + [C.c_int, _dp]
     lib.orc_reflection.argtypes = lib.orc_transmission.argtypes
+    lib.orc_halton2d.argtypes = [C.c_int64, C.c_int64, _dp]
+    lib.orc_sample_disc_ex.argtypes = [C.c_int] + lib.orc_sample_disc.argtypes
+    lib.orc_sample_square_ex.argtypes = [C.c_int] + lib.orc_sample_square.argtypes
+    lib.orc_sample_cap.argtypes = [C.c_int, C.c_uint32, C.c_int64, C.c_double, C.c_double, _dp,
+                                   C.c_double, _dp, _dp, _dp, _dp]
+    lib.orc_apodise.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp]
     lib.orc_to_pressure.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _dp]
     lib.orc_to_pressure.restype = None
     lib.orc_num_threads.restype = C.c_int
@@ -92,23 +98,57 @@ def sobol2d(seed: int, n: int, first: int = 0) -> np.ndarray:
     return out
 
 
-def sample_disc(seed: int, n: int, radius: float, centre=(0.0, 0.0, 0.0), tilt: float = 0.0):
+SEQ_SOBOL, SEQ_HALTON = 0, 1
+
+
+def halton2d(n: int, first: int = 0) -> np.ndarray:
+    """Halton points (bases 2, 3) of indices first .. first+n-1 as float64 [n, 2]."""
+    lib = _load()
+    out = np.zeros((n, 2))
+    _check(lib.orc_halton2d(first, n, out.ctypes.data_as(_dp)), "halton2d")
+    return out
+
+
+def sample_disc(seed: int, n: int, radius: float, centre=(0.0, 0.0, 0.0), tilt: float = 0.0,
+                seq: int = SEQ_SOBOL):
     """Transducer face samples, eq. (18); returns x, y, z, w."""
     lib = _load()
     bufs = [np.zeros(n) for _ in range(4)]
     cen, cp = _d(centre)
-    _check(lib.orc_sample_disc(seed & 0xFFFFFFFF, n, radius, cp, tilt,
-                               *[b.ctypes.data_as(_dp) for b in bufs]), "sample_disc")
+    _check(lib.orc_sample_disc_ex(seq, seed & 0xFFFFFFFF, n, radius, cp, tilt,
+                                  *[b.ctypes.data_as(_dp) for b in bufs]), "sample_disc")
     return tuple(bufs)
 
 
-def sample_square(seed: int, n: int, cx: float, cy: float, z0: float, half_width: float):
+def sample_square(seed: int, n: int, cx: float, cy: float, z0: float, half_width: float,
+                  seq: int = SEQ_SOBOL):
     """Interface patch samples, eq. (17); returns x, y, z, w."""
     lib = _load()
     bufs = [np.zeros(n) for _ in range(4)]
-    _check(lib.orc_sample_square(seed & 0xFFFFFFFF, n, cx, cy, z0, half_width,
-                                 *[b.ctypes.data_as(_dp) for b in bufs]), "sample_square")
+    _check(lib.orc_sample_square_ex(seq, seed & 0xFFFFFFFF, n, cx, cy, z0, half_width,
+                                    *[b.ctypes.data_as(_dp) for b in bufs]), "sample_square")
     return tuple(bufs)
+
+
+def sample_cap(seed: int, n: int, radius: float, curvature: float, centre=(0.0, 0.0, 0.0),
+               tilt: float = 0.0, seq: int = SEQ_SOBOL):
+    """Focused transducer: spherical cap samples (Sec. 3.3); returns x, y, z, w."""
+    lib = _load()
+    bufs = [np.zeros(n) for _ in range(4)]
+    cen, cp = _d(centre)
+    _check(lib.orc_sample_cap(seq, seed & 0xFFFFFFFF, n, radius, curvature, cp, tilt,
+                              *[b.ctypes.data_as(_dp) for b in bufs]), "sample_cap")
+    return tuple(bufs)
+
+
+def apodise(pts, w, centre, axis, width: float) -> np.ndarray:
+    """Gaussian apodisation of the weights: w * exp(-rho^2 / width^2) (returns a copy)."""
+    lib = _load()
+    x, xp = _d(pts[0]); y, yp = _d(pts[1]); z, zp = _d(pts[2])
+    out = np.array(w, dtype=np.float64, copy=True)
+    _, cp = _d(centre); _, ap = _d(axis)
+    _check(lib.orc_apodise(x.shape[0], xp, yp, zp, cp, ap, width, out.ctypes.data_as(_dp)), "apodise")
+    return out
 
 
 MONOPOLE, DIPOLE, OMNI = 0, 1, 2

@@ -329,6 +329,92 @@ def test_omnidirectional_interface_sources(orc):
     assert np.linalg.norm(omni) / nd > 1.1
 
 
+# ----------------------------------------------------------------------------- source variants
+def _radical_inverse_exact(i, b):
+    """Radical inverse as an exact fraction (independent of the reference's integer
+    arithmetic), rounded once by float()."""
+    from fractions import Fraction
+    v, f = Fraction(0), Fraction(1, b)
+    while i:
+        v += (i % b) * f
+        i //= b
+        f /= b
+    return float(v)
+
+
+def test_halton_is_the_radical_inverse(orc):
+    """Sec. 2.3's Halton sequence: coordinate d of index i is the base-(2, 3)[d] radical
+    inverse, bit for bit (exact fractions, rounded once), for small and large indices;
+    the first 3^5 values of the base-3 coordinate are exactly {j / 3^5}."""
+    idx = list(range(0, 300)) + [2 ** 39 - 7, 3 ** 24 + 11, 123456789012]
+    for i in idx:
+        h = orc.halton2d(1, first=i)[0]
+        assert h[0] == _radical_inverse_exact(i, 2) and h[1] == _radical_inverse_exact(i, 3), i
+    h = orc.halton2d(3 ** 5, first=0)[:, 1]
+    assert np.array_equal(np.sort(h), np.arange(3 ** 5) / 3 ** 5)
+
+
+def test_halton_qmc_converges_on_piston_axis(orc):
+    """With the paper's Halton points the piston-axis error decays like a QMC rule
+    (log-log slope <= -0.8) and reaches the closed form of the Sobol pin's accuracy."""
+    f = 1.0e6
+    k = 2 * math.pi * f / C_W
+    z = np.linspace(0.002, 0.1, 40)
+    ex = RHO_W * C_W * (np.exp(1j * k * z) - np.exp(1j * k * np.sqrt(z * z + A * A)))
+    Ns = [2 ** m for m in range(8, 17, 2)]
+    errs = []
+    for n in Ns:
+        x, y, zz, w = orc.sample_disc(0, n, A, seq=orc.SEQ_HALTON)
+        phi = orc.propagate(orc.MONOPOLE, (x, y, zz), w, 1.0, (0 * z, 0 * z, z), C_W, f)
+        errs.append(rel(orc.to_pressure(phi, RHO_W, f), ex))
+    slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
+    assert slope <= -0.8 and errs[-1] < 5e-4
+
+
+@pytest.mark.parametrize("seq", [0, 1])
+def test_focused_cap_axis_closed_form(orc, seq):
+    """Focused transducer (Sec. 3.3: a = 6.35 mm, R = 33 mm): the monopole integral over
+    a spherical cap has the exact on-axis value (O'Neil)
+        p(z) = rho c v0 (e^{ikz} - e^{ik r_e}) / (1 - z/R),
+    r_e the distance to the rim, z from the apex.  The sampler puts every point on the
+    sphere of radius R about the focus within the aperture, with weights summing to the
+    cap area."""
+    f, R = 2.5e6, 0.033
+    k = 2 * math.pi * f / C_W
+    x, y, zz, w = orc.sample_cap(2, 1 << 16, A, R, seq=seq)
+    assert np.allclose(np.sqrt(x ** 2 + y ** 2 + (zz - R) ** 2), R, rtol=0, atol=1e-15)
+    assert np.max(x ** 2 + y ** 2) <= A * A * (1 + 1e-12)
+    sag = R - math.sqrt(R * R - A * A)
+    assert abs(w.sum() / (2 * math.pi * R * sag) - 1) < 1e-12
+    z = np.concatenate([np.linspace(0.005, 0.03, 30), np.linspace(0.036, 0.06, 20)])
+    re_ = np.sqrt((z - sag) ** 2 + A * A)
+    ex = RHO_W * C_W * (np.exp(1j * k * z) - np.exp(1j * k * re_)) / (1 - z / R)
+    phi = orc.propagate(orc.MONOPOLE, (x, y, zz), w, 1.0, (0 * z, 0 * z, z), C_W, f)
+    assert rel(orc.to_pressure(phi, RHO_W, f), ex) < 2e-4  # a convex cap misses by ~1
+
+
+def test_gaussian_apodisation_closed_form(orc):
+    """Gaussian apodisation (Sec. 4): with face velocity v0 exp(-rho^2/W^2) on the disc,
+    the on-axis potential is
+        phi(z) = -v0 int_z^{r_e} exp(-(r^2 - z^2)/W^2) e^{ikr} dr
+               = -v0 (W sqrt(pi)/2) [e^{ikz} w(i a) - e^{-(r_e^2 - z^2)/W^2 + ik r_e} w(i b)],
+    a = z/W - ikW/2, b = r_e/W - ikW/2, w the Faddeeva function (scipy wofz)."""
+    from scipy.special import wofz
+    f, Wd = 1.0e6, 0.004
+    k = 2 * math.pi * f / C_W
+    x, y, zz, w = orc.sample_disc(4, 1 << 16, A)
+    wa = orc.apodise((x, y, zz), w, (0, 0, 0), (0, 0, 1), Wd)
+    z = np.linspace(0.002, 0.08, 40)
+    re_ = np.sqrt(z * z + A * A)
+    a, b = z / Wd - 0.5j * k * Wd, re_ / Wd - 0.5j * k * Wd
+    ex = -(Wd * math.sqrt(math.pi) / 2) * (np.exp(1j * k * z) * wofz(1j * a)
+                                          - np.exp(-(re_ ** 2 - z * z) / Wd ** 2 + 1j * k * re_) * wofz(1j * b))
+    phi = orc.propagate(orc.MONOPOLE, (x, y, zz), wa, 1.0, (0 * z, 0 * z, z), C_W, f)
+    assert rel(phi, ex) < 1e-4  # the untapered disc misses by ~1.5
+    # the flat piston is the limit of an infinitely wide Gaussian
+    assert np.all(orc.apodise((x, y, zz), w, (0, 0, 0), (0, 0, 1), 1e6) / w > 1 - 1e-12)
+
+
 # ----------------------------------------------------------------------------- eqs. 8, 11, 15
 IMPEDANCE_CASES = [(1480.0, 1000.0, 5900.0, 7800.0), (5900.0, 7800.0, 2700.0, 2700.0),
                    (1480.0, 1000.0, 6409.0, 2700.0)]

@@ -53,6 +53,7 @@ typedef enum {
 typedef enum { RSI_MONOPOLE = 0, RSI_DIPOLE = 1, RSI_OMNI = 2 } rsi_kernel;
 typedef enum { RSI_FP32 = 0, RSI_FP64 = 1 } rsi_precision;
 typedef enum { RSI_T_GLOBAL = 0, RSI_T_LOCAL = 1, RSI_T_UNITY = 2 } rsi_tmode;
+typedef enum { RSI_SEQ_SOBOL = 0, RSI_SEQ_HALTON = 1 } rsi_sequence;
 
 typedef struct { double c, rho; } rsi_medium;            /* m/s, kg/m^3             */
 
@@ -126,6 +127,43 @@ rsi_status rsi_sample_disc(uint32_t seed, int64_t n, double radius, const double
 rsi_status rsi_sample_square(uint32_t seed, int64_t n, double cx, double cy, double z0,
                              double half_width, double *x, double *y, double *z, double *w,
                              void *stream);
+
+/* Halton points (the paper's sequence, Sec. 2.3) of indices first .. first+n-1:
+ * out[2i+d] = radical inverse of the index in base 2 (d = 0) or 3 (d = 1), the integer
+ * of mirrored digits over b^K rounded once (bit-identical to that fraction rounded to
+ * FP64).  out: device double[2n].  RSI_ERR_SIZE unless 0 <= first, first + n <= 2^40. */
+rsi_status rsi_halton2d(int64_t first, int64_t n, double *out, void *stream);
+
+/* rsi_sample_disc / rsi_sample_square with a choice of sequence: RSI_SEQ_SOBOL (the
+ * scrambled Sobol points of `seed`, identical to the functions above) or RSI_SEQ_HALTON
+ * (Halton points of indices seed+1 .. seed+n: the origin point is skipped).
+ * RSI_ERR_ARG for an unknown sequence. */
+rsi_status rsi_sample_disc_ex(rsi_sequence seq, uint32_t seed, int64_t n, double radius,
+                              const double *centre, double tilt, double *x, double *y, double *z,
+                              double *w, void *stream);
+rsi_status rsi_sample_square_ex(rsi_sequence seq, uint32_t seed, int64_t n, double cx, double cy,
+                                double z0, double half_width, double *x, double *y, double *z,
+                                double *w, void *stream);
+
+/* Focused transducer (Sec. 3.3): n area-uniform samples on a spherical cap of aperture
+ * radius `radius` and radius of curvature `curvature` (>= radius), apex at `centre`
+ * (host double[3]), concave towards its axis (sin tilt, 0, cos tilt) so that the
+ * geometric focus lies at centre + curvature * axis.  Height above the apex uniform in
+ * u0, azimuth 2 pi u1; w = 2 pi R^2 (1 - cos a_max) / n with sin a_max = radius/R.
+ * The cap radiates with eq. (3) like the flat piston (rsi_transducer.pts / .w).
+ * RSI_ERR_ARG if radius <= 0 or curvature < radius. */
+rsi_status rsi_sample_cap(rsi_sequence seq, uint32_t seed, int64_t n, double radius,
+                          double curvature, const double *centre, double tilt, double *x, double *y,
+                          double *z, double *w, void *stream);
+
+/* Gaussian apodisation of a transducer (Sec. 4: the face velocity modulated by the
+ * position of each source), folded into the quadrature weights: w[i] *= exp(-rho_i^2 /
+ * width^2), rho_i the distance of sample i from the line through `centre` along `axis`
+ * (host double[3] each; axis need not be unit).  w: device double[n], updated in place.
+ * RSI_ERR_ARG if width <= 0 or axis = 0. */
+rsi_status rsi_apodise(int64_t n, const double *x, const double *y, const double *z,
+                       const double *centre, const double *axis, double width, double *w,
+                       void *stream);
 
 /* ------------------------------------------------------------------------------
  * a2. Interface transmission (eqs. 7, 8, 11, 15).

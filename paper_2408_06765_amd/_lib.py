@@ -47,6 +47,16 @@ SIGNATURES = {
                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "rsi_sample_square": ([C.c_uint32, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double,
                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "rsi_halton2d": ([C.c_int64, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
+    "rsi_sample_disc_ex": ([C.c_int, C.c_uint32, C.c_int64, C.c_double, _dp, C.c_double, C.c_void_p,
+                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "rsi_sample_square_ex": ([C.c_int, C.c_uint32, C.c_int64, C.c_double, C.c_double, C.c_double,
+                              C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+                             C.c_int),
+    "rsi_sample_cap": ([C.c_int, C.c_uint32, C.c_int64, C.c_double, C.c_double, _dp, C.c_double,
+                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "rsi_apodise": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, _dp, _dp, C.c_double, C.c_void_p,
+                     C.c_void_p], C.c_int),
     "rsi_transmission": ([C.c_int, C.c_int, _dp, C.POINTER(rsi_medium), _dp, _dp, C.c_int64,
                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "rsi_propagate": ([C.POINTER(rsi_points), C.c_void_p, C.c_void_p, _dp, C.POINTER(rsi_points),

@@ -5,6 +5,7 @@
 // two-dimensional Sobol sequence with a hash-based nested uniform (Owen) scramble,
 // which keeps the (0, m, 2)-net property of every power-of-two prefix.  Each point is
 // computed from its index alone, so any range of points is one independent launch.
+#include <cmath>
 #include <cstring>
 
 #include "rsi_internal.h"
@@ -77,19 +78,59 @@ __global__ void __launch_bounds__(256) sobol2d_kernel(uint32_t s0, uint32_t s1, 
 // 2^-32: maps a 32-bit digit string onto [0, 1) exactly in FP64.
 constexpr double kU32 = 1.0 / 4294967296.0;
 
-__global__ void __launch_bounds__(256) disc_kernel(uint32_t s0, uint32_t s1, int64_t n,
-                                                   double radius, double cx, double cy,
-                                                   double cz, double ct, double st, double wj,
-                                                   double *x, double *y, double *z,
-                                                   double *w) {
+// Halton sequence (the paper's choice, Sec. 2.3): the radical inverse of the index in
+// base b, as the integer of mirrored digits over b^K followed by one IEEE division
+// (the correctly rounded value; exact integers below 2^53 for indices below 2^40).
+__device__ inline double radical_inverse(uint64_t index, uint64_t base) {
+    uint64_t num = 0, den = 1;
+    while (index) {
+        const uint64_t q = index / base;
+        num = num * base + (index - q * base);
+        den *= base;
+        index = q;
+    }
+    return (double)num / (double)den;
+}
+
+// Where the two unit coordinates of sample i come from: scrambled Sobol points with
+// the coordinate seeds s0, s1 (seq 0), or Halton points of index first + i (seq 1).
+struct UnitSource {
+    int seq;
+    uint32_t s0, s1;
+    int64_t first;
+};
+
+__device__ inline void unit_pair(const UnitSource &u, int64_t i, double &u0, double &u1) {
+    if (u.seq == RSI_SEQ_HALTON) {
+        u0 = radical_inverse((uint64_t)(u.first + i), 2);
+        u1 = radical_inverse((uint64_t)(u.first + i), 3);
+    } else {
+        uint32_t a, b;
+        scrambled_pair((uint32_t)i, u.s0, u.s1, a, b);
+        u0 = (double)a * kU32;
+        u1 = (double)b * kU32;
+    }
+}
+
+__global__ void __launch_bounds__(256) halton2d_kernel(int64_t first, int64_t n, double *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t u0, u1;
-    scrambled_pair((uint32_t)i, s0, s1, u0, u1);
+    reinterpret_cast<double2 *>(out)[i] =
+        make_double2(radical_inverse((uint64_t)(first + i), 2), radical_inverse((uint64_t)(first + i), 3));
+}
+
+__global__ void __launch_bounds__(256) disc_kernel(UnitSource us, int64_t n, double radius,
+                                                   double cx, double cy, double cz, double ct,
+                                                   double st, double wj, double *x, double *y,
+                                                   double *z, double *w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double u0, u1;
+    unit_pair(us, i, u0, u1);
     // eq. (18): area-uniform radius and uniform angle
-    const double r = radius * sqrt((double)u0 * kU32);
+    const double r = radius * sqrt(u0);
     double sn, cs;
-    sincospi(2.0 * ((double)u1 * kU32), &sn, &cs);
+    sincospi(2.0 * u1, &sn, &cs);
     const double xi = r * cs, eta = r * sn;
     x[i] = cx + xi * ct;  // rotation by `tilt` about +y, then translation
     y[i] = cy + eta;
@@ -97,19 +138,56 @@ __global__ void __launch_bounds__(256) disc_kernel(uint32_t s0, uint32_t s1, int
     w[i] = wj;
 }
 
-__global__ void __launch_bounds__(256) square_kernel(uint32_t s0, uint32_t s1, int64_t n,
-                                                     double cx, double cy, double z0,
-                                                     double h, double wj, double *x,
-                                                     double *y, double *z, double *w) {
+__global__ void __launch_bounds__(256) square_kernel(UnitSource us, int64_t n, double cx,
+                                                     double cy, double z0, double h, double wj,
+                                                     double *x, double *y, double *z, double *w) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t u0, u1;
-    scrambled_pair((uint32_t)i, s0, s1, u0, u1);
+    double u0, u1;
+    unit_pair(us, i, u0, u1);
     // eq. (17): uniform on the square [cx - h, cx + h] x [cy - h, cy + h]
-    x[i] = cx + h * (2.0 * ((double)u0 * kU32) - 1.0);
-    y[i] = cy + h * (2.0 * ((double)u1 * kU32) - 1.0);
+    x[i] = cx + h * (2.0 * u0 - 1.0);
+    y[i] = cy + h * (2.0 * u1 - 1.0);
     z[i] = z0;
     w[i] = wj;
+}
+
+// Spherical cap (focused transducer, Sec. 3.3): height above the apex uniform in u0
+// (area-uniform), azimuth 2 pi u1; in the cap frame (R sin a cos p, R sin a sin p,
+// R (1 - cos a)), then tilted about +y and translated like the flat disc.
+__global__ void __launch_bounds__(256) cap_kernel(UnitSource us, int64_t n, double R, double ca,
+                                                  double cx, double cy, double cz, double ct,
+                                                  double st, double wj, double *x, double *y,
+                                                  double *z, double *w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double u0, u1;
+    unit_pair(us, i, u0, u1);
+    // t = 1 - cos(a); sin(a) = sqrt(t (2 - t)) has no cancellation near the apex
+    const double t = u0 * (1.0 - ca);
+    const double sal = sqrt(t * (2.0 - t));
+    double sn, cs;
+    sincospi(2.0 * u1, &sn, &cs);
+    const double xi = R * sal * cs, eta = R * sal * sn, zeta = R * t;
+    x[i] = cx + xi * ct + zeta * st;
+    y[i] = cy + eta;
+    z[i] = cz - xi * st + zeta * ct;
+    w[i] = wj;
+}
+
+// Gaussian apodisation (Sec. 4): w *= exp(-rho^2 / width^2), rho the distance from the
+// axis line through the centre.
+__global__ void __launch_bounds__(256) apodise_kernel(int64_t n, const double *__restrict__ x,
+                                                      const double *__restrict__ y,
+                                                      const double *__restrict__ z, double cx,
+                                                      double cy, double cz, double ax, double ay,
+                                                      double az, double inv_w2, double *w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double dx = x[i] - cx, dy = y[i] - cy, dz = z[i] - cz;
+    const double along = dx * ax + dy * ay + dz * az;
+    const double rho2 = dx * dx + dy * dy + dz * dz - along * along;
+    w[i] *= exp(-rho2 * inv_w2);
 }
 
 static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -148,17 +226,57 @@ rsi_status rsi_sobol2d(uint32_t seed, int64_t first, int64_t n, uint32_t *out, v
     return RSI_OK;
 }
 
-rsi_status rsi_sample_disc(uint32_t seed, int64_t n, double radius, const double *centre,
-                           double tilt, double *x, double *y, double *z, double *w,
-                           void *stream) {
+static rsi_status unit_source(rsi_sequence seq, uint32_t seed, int64_t n, UnitSource &us) {
+    if (seq != RSI_SEQ_SOBOL && seq != RSI_SEQ_HALTON) return RSI_ERR_ARG;
     if (n < 0 || n > (int64_t(1) << 32)) return RSI_ERR_SIZE;
+    us.seq = (int)seq;
+    us.s0 = coord_seed(seed, 0);
+    us.s1 = coord_seed(seed, 1);
+    us.first = (int64_t)seed + 1;  // Halton: start after the origin point
+    return RSI_OK;
+}
+
+rsi_status rsi_halton2d(int64_t first, int64_t n, double *out, void *stream) {
+    if (first < 0 || n < 0 || first + n > (int64_t(1) << 40)) return RSI_ERR_SIZE;
+    if (n == 0) return RSI_OK;
+    if (!out) return RSI_ERR_NULL;
+    hipLaunchKernelGGL(halton2d_kernel, dim3(grid_for(n)), dim3(256), 0, as_stream(stream), first, n, out);
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+rsi_status rsi_sample_disc_ex(rsi_sequence seq, uint32_t seed, int64_t n, double radius,
+                              const double *centre, double tilt, double *x, double *y, double *z,
+                              double *w, void *stream) {
+    UnitSource us;
+    RSI_TRY(unit_source(seq, seed, n, us));
     if (!(radius > 0.0)) return RSI_ERR_ARG;
     if (n == 0) return RSI_OK;
     if (!centre || !x || !y || !z || !w) return RSI_ERR_NULL;
     const double wj = kPi * radius * radius / (double)n;
-    hipLaunchKernelGGL(disc_kernel, dim3(grid_for(n)), dim3(256), 0, as_stream(stream),
-                       coord_seed(seed, 0), coord_seed(seed, 1), n, radius, centre[0],
-                       centre[1], centre[2], cos(tilt), sin(tilt), wj, x, y, z, w);
+    hipLaunchKernelGGL(disc_kernel, dim3(grid_for(n)), dim3(256), 0, as_stream(stream), us, n, radius,
+                       centre[0], centre[1], centre[2], cos(tilt), sin(tilt), wj, x, y, z, w);
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+rsi_status rsi_sample_disc(uint32_t seed, int64_t n, double radius, const double *centre,
+                           double tilt, double *x, double *y, double *z, double *w,
+                           void *stream) {
+    return rsi_sample_disc_ex(RSI_SEQ_SOBOL, seed, n, radius, centre, tilt, x, y, z, w, stream);
+}
+
+rsi_status rsi_sample_square_ex(rsi_sequence seq, uint32_t seed, int64_t n, double cx, double cy,
+                                double z0, double half_width, double *x, double *y, double *z,
+                                double *w, void *stream) {
+    UnitSource us;
+    RSI_TRY(unit_source(seq, seed, n, us));
+    if (!(half_width > 0.0)) return RSI_ERR_ARG;
+    if (n == 0) return RSI_OK;
+    if (!x || !y || !z || !w) return RSI_ERR_NULL;
+    const double wj = 4.0 * half_width * half_width / (double)n;
+    hipLaunchKernelGGL(square_kernel, dim3(grid_for(n)), dim3(256), 0, as_stream(stream), us, n, cx, cy, z0,
+                       half_width, wj, x, y, z, w);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }
@@ -166,14 +284,38 @@ rsi_status rsi_sample_disc(uint32_t seed, int64_t n, double radius, const double
 rsi_status rsi_sample_square(uint32_t seed, int64_t n, double cx, double cy, double z0,
                              double half_width, double *x, double *y, double *z, double *w,
                              void *stream) {
-    if (n < 0 || n > (int64_t(1) << 32)) return RSI_ERR_SIZE;
-    if (!(half_width > 0.0)) return RSI_ERR_ARG;
+    return rsi_sample_square_ex(RSI_SEQ_SOBOL, seed, n, cx, cy, z0, half_width, x, y, z, w, stream);
+}
+
+rsi_status rsi_sample_cap(rsi_sequence seq, uint32_t seed, int64_t n, double radius,
+                          double curvature, const double *centre, double tilt, double *x, double *y,
+                          double *z, double *w, void *stream) {
+    UnitSource us;
+    RSI_TRY(unit_source(seq, seed, n, us));
+    if (!(radius > 0.0) || !(curvature >= radius) || !std::isfinite(curvature)) return RSI_ERR_ARG;
+    if (n == 0) return RSI_OK;
+    if (!centre || !x || !y || !z || !w) return RSI_ERR_NULL;
+    const double sa = radius / curvature, ca = sqrt(1.0 - sa * sa);
+    const double wj = 2.0 * kPi * curvature * curvature * (1.0 - ca) / (double)n;
+    hipLaunchKernelGGL(cap_kernel, dim3(grid_for(n)), dim3(256), 0, as_stream(stream), us, n, curvature, ca,
+                       centre[0], centre[1], centre[2], cos(tilt), sin(tilt), wj, x, y, z, w);
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+rsi_status rsi_apodise(int64_t n, const double *x, const double *y, const double *z,
+                       const double *centre, const double *axis, double width, double *w,
+                       void *stream) {
+    if (n < 0) return RSI_ERR_SIZE;
+    if (!(width > 0.0)) return RSI_ERR_ARG;
+    if (!centre || !axis) return RSI_ERR_NULL;
+    const double an = sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+    if (!(an > 0.0)) return RSI_ERR_ARG;
     if (n == 0) return RSI_OK;
     if (!x || !y || !z || !w) return RSI_ERR_NULL;
-    const double wj = 4.0 * half_width * half_width / (double)n;
-    hipLaunchKernelGGL(square_kernel, dim3(grid_for(n)), dim3(256), 0, as_stream(stream),
-                       coord_seed(seed, 0), coord_seed(seed, 1), n, cx, cy, z0, half_width, wj,
-                       x, y, z, w);
+    hipLaunchKernelGGL(apodise_kernel, dim3(grid_for(n)), dim3(256), 0, as_stream(stream), n, x, y, z,
+                       centre[0], centre[1], centre[2], axis[0] / an, axis[1] / an, axis[2] / an,
+                       1.0 / (width * width), w);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }

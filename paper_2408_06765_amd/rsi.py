@@ -20,6 +20,7 @@ RSI_FP32, RSI_FP64 = 0, 1
 RSI_T_GLOBAL, RSI_T_LOCAL, RSI_T_UNITY = 0, 1, 2
 RSI_FLAG_PLANAR_Z = 1
 RSI_CHAIN_OMNI, RSI_CHAIN_ABOVE = 1, 2
+RSI_SEQ_SOBOL, RSI_SEQ_HALTON = 0, 1
 
 _OUT_DTYPE = {RSI_FP32: torch.complex64, RSI_FP64: torch.complex128}
 
@@ -71,22 +72,48 @@ def rsi_sobol2d(seed: int, n: int, first: int = 0, device="cuda") -> torch.Tenso
     return out
 
 
+def rsi_halton2d(n: int, first: int = 0, device="cuda") -> torch.Tensor:
+    """Halton points (bases 2, 3) of indices first .. first+n-1, float64 [n, 2]."""
+    out = torch.empty((n, 2), dtype=torch.float64, device=device)
+    L.check(L.load().rsi_halton2d(first, n, _ptr(out), _stream()), "rsi_halton2d")
+    return out
+
+
 def rsi_sample_disc(seed: int, n: int, radius: float, centre=(0.0, 0.0, 0.0), tilt: float = 0.0,
-                    device="cuda"):
+                    device="cuda", seq: int = RSI_SEQ_SOBOL):
     """Piston face samples (eq. 18): returns x, y, z, w (float64)."""
     bufs = [torch.empty(n, dtype=torch.float64, device=device) for _ in range(4)]
-    L.check(L.load().rsi_sample_disc(seed & 0xFFFFFFFF, n, radius, _dvec(centre), tilt,
-                                     *[_ptr(b) for b in bufs], _stream()), "rsi_sample_disc")
+    L.check(L.load().rsi_sample_disc_ex(seq, seed & 0xFFFFFFFF, n, radius, _dvec(centre), tilt,
+                                        *[_ptr(b) for b in bufs], _stream()), "rsi_sample_disc_ex")
     return tuple(bufs)
 
 
 def rsi_sample_square(seed: int, n: int, cx: float, cy: float, z0: float, half_width: float,
-                      device="cuda"):
+                      device="cuda", seq: int = RSI_SEQ_SOBOL):
     """Interface patch samples (eq. 17): returns x, y, z, w (float64)."""
     bufs = [torch.empty(n, dtype=torch.float64, device=device) for _ in range(4)]
-    L.check(L.load().rsi_sample_square(seed & 0xFFFFFFFF, n, cx, cy, z0, half_width,
-                                       *[_ptr(b) for b in bufs], _stream()), "rsi_sample_square")
+    L.check(L.load().rsi_sample_square_ex(seq, seed & 0xFFFFFFFF, n, cx, cy, z0, half_width,
+                                          *[_ptr(b) for b in bufs], _stream()), "rsi_sample_square_ex")
     return tuple(bufs)
+
+
+def rsi_sample_cap(seed: int, n: int, radius: float, curvature: float, centre=(0.0, 0.0, 0.0),
+                   tilt: float = 0.0, device="cuda", seq: int = RSI_SEQ_SOBOL):
+    """Focused transducer (Sec. 3.3): spherical-cap samples; returns x, y, z, w."""
+    bufs = [torch.empty(n, dtype=torch.float64, device=device) for _ in range(4)]
+    L.check(L.load().rsi_sample_cap(seq, seed & 0xFFFFFFFF, n, radius, curvature, _dvec(centre), tilt,
+                                    *[_ptr(b) for b in bufs], _stream()), "rsi_sample_cap")
+    return tuple(bufs)
+
+
+def rsi_apodise(pts, w: torch.Tensor, centre, axis, width: float) -> torch.Tensor:
+    """Gaussian apodisation of the weights in place: w *= exp(-rho^2 / width^2)."""
+    for a, name in zip(pts, "xyz"):
+        _dev(a, torch.float64, name)
+    _dev(w, torch.float64, "w")
+    L.check(L.load().rsi_apodise(w.numel(), _ptr(pts[0]), _ptr(pts[1]), _ptr(pts[2]), _dvec(centre),
+                                 _dvec(axis), width, _ptr(w), _stream()), "rsi_apodise")
+    return w
 
 
 # ---------------------------------------------------------------------------- a2

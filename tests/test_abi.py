@@ -97,6 +97,17 @@ def test_argument_errors_before_any_device_work():
     assert lib.rsi_sobol2d(0, 0, 0, None, None) == 0
     # pressure
     assert lib.rsi_to_pressure(4, None, 0, -1.0, 1e6, None, None) == 2
+    # sequences, cap, apodisation, Halton range
+    cen = (C.c_double * 3)(0, 0, 0)
+    ax = (C.c_double * 3)(0, 0, 1)
+    assert lib.rsi_sample_disc_ex(5, 0, 10, 0.01, cen, 0.0, None, None, None, None, None) == 2
+    assert lib.rsi_sample_cap(0, 0, 10, 0.01, 0.005, cen, 0.0, None, None, None, None, None) == 2
+    assert lib.rsi_sample_cap(1, 0, -1, 0.01, 0.05, cen, 0.0, None, None, None, None, None) == 3
+    assert lib.rsi_sample_cap(1, 0, 0, 0.01, 0.05, cen, 0.0, None, None, None, None, None) == 0
+    assert lib.rsi_halton2d((1 << 40) - 5, 10, None, None) == 3
+    assert lib.rsi_apodise(10, None, None, None, cen, ax, 0.0, None, None) == 2
+    assert lib.rsi_apodise(10, None, None, None, cen, (C.c_double * 3)(0, 0, 0), 1.0, None, None) == 2
+    assert lib.rsi_apodise(0, None, None, None, cen, ax, 1.0, None, None) == 0
 
 
 def test_chain_validation():

@@ -52,6 +52,36 @@ def test_sample_maps_match(gpu, orc):
         assert np.max(np.abs(a - b)) <= 1e-17 + 4e-16 * np.max(np.abs(b))
 
 
+def test_halton_bit_exact(gpu, orc):
+    for first, n in ((0, 4097), (1, 3000), (2 ** 39 - 2000, 2000)):
+        g = host(gpu.rsi_halton2d(n, first))
+        o = orc.halton2d(n, first)
+        assert np.array_equal(g.view(np.uint64), o.view(np.uint64)), first
+
+
+@pytest.mark.parametrize("seq", [0, 1])
+def test_sample_maps_sequences_and_cap(gpu, orc, seq):
+    """Disc, square and cap samplers with Sobol and Halton points match the reference's
+    maps (FP64, libm vs device sin/cos/sqrt: a few ulp)."""
+    def close(g, o):
+        for a, b in zip(g, o):
+            assert np.max(np.abs(host(a) - b)) <= 1e-17 + 4e-16 * np.max(np.abs(b))
+    close(gpu.rsi_sample_disc(7, 5001, 0.00635, (0.001, 0.0, 0.002), 0.2, seq=seq),
+          orc.sample_disc(7, 5001, 0.00635, (0.001, 0.0, 0.002), 0.2, seq=seq))
+    close(gpu.rsi_sample_square(3, 4097, 0.008, -0.001, 0.05, 0.02, seq=seq),
+          orc.sample_square(3, 4097, 0.008, -0.001, 0.05, 0.02, seq=seq))
+    close(gpu.rsi_sample_cap(5, 6000, 0.00635, 0.033, (0.0, 0.0, 0.001), 0.1, seq=seq),
+          orc.sample_cap(5, 6000, 0.00635, 0.033, (0.0, 0.0, 0.001), 0.1, seq=seq))
+
+
+def test_apodise_matches(gpu, orc):
+    x, y, z, w = orc.sample_cap(1, 3000, 0.00635, 0.033, (0.0, 0.0, 0.0), 0.15)
+    wg = dev(w.copy())
+    gpu.rsi_apodise(devpts((x, y, z)), wg, (0.0, 0.0, 0.0), (math.sin(0.15), 0.0, math.cos(0.15)), 0.004)
+    ref = orc.apodise((x, y, z), w, (0.0, 0.0, 0.0), (math.sin(0.15), 0.0, math.cos(0.15)), 0.004)
+    assert np.max(np.abs(host(wg) / ref - 1)) < 1e-14
+
+
 # ----------------------------------------------------------------------------- a2
 @pytest.mark.parametrize("tmode", [0, 1, 2])
 def test_transmission_matches(gpu, orc, tmode):
@@ -272,6 +302,23 @@ def test_chain_modes_plan_replay(gpu, orc):
             _ = torch.randn(100, device="cuda").sum().item()
             assert np.array_equal(host(plan.out).view(np.uint64), eager.view(np.uint64))
         plan.destroy()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_focused_apodised_chain(gpu, orc, prec):
+    """Focused transducer (spherical cap, Sec. 3.3) with a Gaussian apodisation (Sec. 4)
+    at normal incidence through a water/steel interface 10 mm away, Halton points as in
+    the paper (Sec. 2.3)."""
+    R, L, f = 0.033, 0.01, 2.5e6
+    media = (W.WATER, W.STEEL_5900)
+    xd = list(orc.sample_cap(0, 4096, W.PISTON_RADIUS, R, seq=orc.SEQ_HALTON))
+    xd[3] = orc.apodise(xd[:3], xd[3], (0, 0, 0), (0, 0, 1), 0.005)
+    q = orc.sample_square(0, 1 << 13, 0.0, 0.0, L, 0.012, seq=orc.SEQ_HALTON)
+    tgt = W.random_cloud(7, 700, (0.0, 0.0, L + 0.008), (0.004, 0.004, 0.007))
+    ref = orc.chain(xd, 1.0, (0, 0, 0), (0, 0, 1), [q], [L], [m[0] for m in media], [m[1] for m in media],
+                    tgt, [f], 0)
+    got = _gpu_chain(gpu, xd, [q], [L], media, tgt, [f], 0, prec, (0.0, 0.0, 1.0))
+    assert rel(got, ref) <= TOL[prec]
 
 
 def test_piston_axis_workload(gpu, orc):

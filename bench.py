@@ -43,7 +43,7 @@ def parse():
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="one_interface",
                     choices=["one_interface", "layered_stack", "scan_batch", "surrogate",
-                             "interface_continuity"],
+                             "interface_continuity", "focused_normal"],
                     help="one_interface is the benchmark line; the others are secondary "
                          "measurements printed in the same format")
     ap.add_argument("--autotune", action="store_true",
@@ -259,6 +259,100 @@ def interface_continuity(args):
     print(json.dumps(line), flush=True)
 
 
+def focused_normal(args):
+    """Focused transducer at normal incidence (Sec. 3.3): cap R = 33 mm, 10 mm water path,
+    steel, 2.5 MHz, 10^5 Halton samples per surface.  Timed: the chain onto the 401 x 401
+    y-z slice (FP32, one plan replay per step).  Reported beside it: the on-axis velocity
+    amplitude k2 |phi| / v0 in the steel, its peak depth against the paper's 14 mm, the
+    -6 dB width of the focal spot, the focal gain over a flat piston, the apodised
+    variant, and the on-axis error of 10^5 Halton and 10^5 Sobol samples against a
+    2^20-sample Sobol field (FP32 vs FP64 stated)."""
+    import torch
+    from paper_2408_06765_amd import rsi
+    from paper_2408_06765_amd import workloads as W
+
+    cfg = W.FocusedNormal()
+    (c1, r1), (c2, r2) = cfg.media
+    zero, axis = (0.0, 0.0, 0.0), (0.0, 0.0, 1.0)
+    freqs = [cfg.freq]
+
+    def model(seq, n_xd, n_if, apod=False, flat=False):
+        if flat:
+            xs = rsi.rsi_sample_disc(cfg.xd_seed, n_xd, cfg.radius, zero, 0.0, seq=seq)
+        else:
+            xs = rsi.rsi_sample_cap(cfg.xd_seed, n_xd, cfg.radius, cfg.curvature, zero, 0.0, seq=seq)
+        w = xs[3]
+        if apod:
+            rsi.rsi_apodise(xs[:3], w, zero, axis, cfg.apod_width)
+        q = rsi.rsi_sample_square(cfg.if_seed, n_if, 0.0, 0.0, cfg.water_path, cfg.half_width, seq=seq)
+        return rsi.Transducer(*xs[:3], w, 1.0, zero, axis), [rsi.Interface(*q[:3], q[3], cfg.water_path)]
+
+    dev = lambda pts: tuple(torch.as_tensor(a, device="cuda") for a in pts)
+    grid, line, focal = dev(cfg.grid()), dev(cfg.axis_line()), dev(cfg.focal_line())
+    H = rsi.RSI_SEQ_HALTON
+    T, I = model(H, cfg.n_xd, cfg.n_if)
+    plan = rsi.Plan.chain(T, I, cfg.media, grid, freqs, rsi.RSI_T_GLOBAL, rsi.RSI_FP32)
+    dt = timed(plan.execute, args.steps, args.warmup)
+    n_g = grid[0].numel()
+    pairs = cfg.n_xd * cfg.n_if + cfg.n_if * n_g
+    k2 = 2 * math.pi * cfg.freq / c2
+    vel = lambda phi: k2 * np.abs(phi)                      # k2 |phi| / v0, v0 = 1
+
+    def on(T_, I_, tgt, prec=rsi.RSI_FP32):
+        return rsi.rsi_chain(T_, I_, cfg.media, tgt, freqs, rsi.RSI_T_GLOBAL, prec)[0].cpu().numpy()
+
+    z = cfg.axis_z
+    ax_h32 = on(T, I, line)
+    ax_h64 = on(T, I, line, rsi.RSI_FP64)
+    ax_s32 = on(*model(rsi.RSI_SEQ_SOBOL, cfg.n_xd, cfg.n_if), line)
+    n_ref = 1 << 20
+    ax_ref = on(*model(rsi.RSI_SEQ_SOBOL, n_ref, n_ref), line)
+    ax_ref_h = on(*model(H, n_ref, n_ref), line)
+    ax_apod = on(*model(H, cfg.n_xd, cfg.n_if, apod=True), line)
+    ax_flat = on(*model(H, cfg.n_xd, cfg.n_if, flat=True), line)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def peak(a):
+        v = vel(a)
+        i = int(np.argmax(v))
+        if 0 < i < len(v) - 1:                               # parabolic refinement
+            y0, y1, y2 = v[i - 1], v[i], v[i + 1]
+            d = 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)
+            return float(z[i] + d * (z[1] - z[0])), float(y1 - 0.25 * (y0 - y2) * d)
+        return float(z[i]), float(v[i])
+
+    zp, vp = peak(ax_h32)
+    zp_apod, vp_apod = peak(ax_apod)
+    _, vp_flat = peak(ax_flat)
+    fl = vel(on(T, I, focal))
+    y = cfg.focal_line()[1]
+    above = y[fl >= 0.5 * fl.max()]
+    img = plan.out[0].cpu().numpy().reshape(cfg.n_grid, cfg.n_grid)
+    iz, iy = np.unravel_index(int(np.argmax(np.abs(img))), img.shape)
+    line_out = base_line(pairs * args.steps / dt / 1e9, args.steps, args.warmup, dt,
+                         {"workload": "focused_normal: spherical cap a 6.35 mm R 33 mm, 10 mm water -> "
+                                      "steel 5840 m/s, 2.5 MHz, 10^5 Halton per surface, interface +-3a, "
+                                      "global T -> 401 x 401 y-z slice 1-25 mm below the interface",
+                          "pairs_per_step": pairs})
+    line_out.update({
+        "axis_peak_z_mm": round(1e3 * zp, 3),
+        "paper_focal_z_mm": round(1e3 * cfg.z_focus_paper, 3),
+        "paraxial_geometric_focus_z_mm": round(1e3 * (cfg.water_path + (cfg.curvature - cfg.water_path) * c1 / c2), 3),
+        "axis_peak_k2phi_over_v0": round(vp, 4),
+        "image_peak_z_mm": round(1e3 * cfg.grid()[2].reshape(cfg.n_grid, cfg.n_grid)[iz, iy], 3),
+        "focal_gain_over_flat_piston": round(vp / vp_flat, 3),
+        "focal_spot_minus6db_width_mm_at_paper_focus": round(1e3 * (above.max() - above.min()), 3),
+        "apodised_axis_peak_z_mm": round(1e3 * zp_apod, 3),
+        "apodised_peak_over_uniform": round(vp_apod / vp, 4),
+        "axis_rel_l2_halton_1e5_vs_sobol_2p20": rel(ax_h32, ax_ref),
+        "axis_rel_l2_sobol_1e5_vs_sobol_2p20": rel(ax_s32, ax_ref),
+        "axis_rel_l2_halton_2p20_vs_sobol_2p20": rel(ax_ref_h, ax_ref),
+        "axis_fp32_vs_fp64_rel_l2": rel(ax_h32, ax_h64),
+    })
+    print(json.dumps(line_out), flush=True)
+    plan.destroy()
+
+
 def scan_batch(args):
     """256 uneven scan positions in one persistent launch (batched plan)."""
     import torch
@@ -350,6 +444,8 @@ def main():
         return layered_stack(args)
     if args.workload == "interface_continuity":
         return interface_continuity(args)
+    if args.workload == "focused_normal":
+        return focused_normal(args)
     if args.workload == "scan_batch":
         return scan_batch(args)
     if args.workload == "surrogate":

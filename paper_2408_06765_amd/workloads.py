@@ -8,6 +8,7 @@ configurations, as plain numbers and numpy arrays:
   piston_axis  (Sec. 3 piston in water, 1 MHz, on-axis line)
   one_interface (water -> 5900 m/s solid at 50 mm, 10 deg tilt, 5 MHz, 512 x 512 image)
   layered_stack (three interfaces 2 mm apart, 64 frequencies 1-10 MHz, 128^3 volume)
+  focused_normal (Sec. 3.3: spherical-cap transducer over a water/steel interface)
   scan_batch   (256 uneven scan positions of the piston in water)
   surrogate    (parameter box of the learned surrogate)
 
@@ -24,6 +25,7 @@ import numpy as np
 
 WATER = (1480.0, 1000.0)          # (c m/s, rho kg/m^3), Sec. 3
 STEEL_5900 = (5900.0, 7800.0)     # second medium of the interface workloads
+STEEL_PAPER = (5840.0, 7800.0)    # steel of Sec. 3 (the paper-geometry variants)
 MID_2700 = (2700.0, 2700.0)       # middle layer of the stack (speed 2700 m/s)
 PISTON_RADIUS = 6.35e-3           # Sec. 3
 
@@ -133,6 +135,57 @@ class InterfaceContinuity:
             s2 = self.media[1][0] / self.media[0][0] * math.sin(self.tilt)
             ux, uz = s2, math.sqrt(1.0 - s2 * s2)
         return x0 + d * ux, np.zeros_like(d), self.z_if + d * uz
+
+
+@dataclass
+class FocusedNormal:
+    """Focused transducer at normal incidence (Sec. 3.3): a spherical cap of aperture
+    radius 6.35 mm and radius of curvature 33 mm, apex at the origin, 10 mm of water
+    above a steel half-space, 2.5 MHz, 10^5 Halton samples on every surface (Sec. 2.3),
+    interface sampled over +-3a (Sec. 2.3) about the axis.  Field: a 401 x 401 slice of
+    the y-z plane (x = 0) in the steel, 1-25 mm below the interface, an on-axis line
+    and the off-axis line at z = 14 mm (the paper's stated focal depth)."""
+    radius: float = PISTON_RADIUS
+    curvature: float = 0.033
+    freq: float = 2.5e6
+    water_path: float = 0.010
+    media: Tuple[Tuple[float, float], ...] = (WATER, STEEL_PAPER)
+    n_xd: int = 100000
+    n_if: int = 100000
+    xd_seed: int = 0
+    if_seed: int = 1 << 20       # Halton: the interface starts 2^20 indices further on
+    n_grid: int = 401
+    half_y: float = 0.010
+    depth0: float = 1.0e-3
+    depth1: float = 25.0e-3
+    n_axis: int = 1001
+    z_focus_paper: float = 0.014
+    apod_width: float = PISTON_RADIUS
+
+    @property
+    def half_width(self) -> float:
+        return 3.0 * self.radius
+
+    @property
+    def axis_z(self) -> np.ndarray:
+        return self.water_path + np.linspace(self.depth0, self.depth1, self.n_axis)
+
+    def grid(self, n=None):
+        """y-z slice at x = 0, row-major [z][y]."""
+        n = n or self.n_grid
+        y = np.linspace(-self.half_y, self.half_y, n)
+        z = self.water_path + np.linspace(self.depth0, self.depth1, n)
+        Z, Y = np.meshgrid(z, y, indexing="ij")
+        return np.zeros(Z.size), Y.ravel().copy(), Z.ravel().copy()
+
+    def axis_line(self):
+        z = self.axis_z
+        return np.zeros_like(z), np.zeros_like(z), z
+
+    def focal_line(self, n=None):
+        n = n or self.n_grid
+        y = np.linspace(-self.half_y, self.half_y, n)
+        return np.zeros_like(y), y, np.full_like(y, self.z_focus_paper)
 
 
 def snell_intercepts(x0: float, tilt: float, z_if, speeds) -> List[float]:

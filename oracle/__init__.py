@@ -60,6 +60,8 @@ def _load():
     lib.orc_sample_cap.argtypes = [C.c_int, C.c_uint32, C.c_int64, C.c_double, C.c_double, _dp,
                                    C.c_double, _dp, _dp, _dp, _dp]
     lib.orc_apodise.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp]
+    lib.orc_ray_field.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double, C.c_int, _dp, _dp,
+                                  _dp, C.c_int64, _dp, _dp, _dp, C.c_int, _dp, _dp]
     lib.orc_to_pressure.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _dp]
     lib.orc_to_pressure.restype = None
     lib.orc_num_threads.restype = C.c_int
@@ -256,6 +258,30 @@ def chain(xd, v0: float, xc, axis, ifaces, zif, c, rho, tgt, freqs, tmode: int,
                           p(rho), tx.shape[0], p(tgt[0]), p(tgt[1]), p(tgt[2]), len(freqs),
                           p(freqs), tmode, flags, out.ctypes.data_as(_dp))
     _check(rc, "chain")
+    return _cplx_out(out).reshape(len(freqs), tx.shape[0])
+
+
+def ray_field(xd, v0: float, zif, c, rho, tgt, freqs) -> np.ndarray:
+    """Ray-tracing model (Sec. 2.2, eq. 12 with the slowness of eq. 14 through the planes
+    z = zif[l], normal +z): transducer samples xd = (x, y, z, w) straight to the field
+    points, no interface sampled.  c, rho: media 0..n_if.  Returns complex
+    [n_freq, n_tgt]."""
+    lib = _load()
+    keep = []
+
+    def p(a):
+        a, ap = _d(a)
+        keep.append(a)
+        return ap
+
+    zif = np.atleast_1d(np.asarray(zif, dtype=np.float64))
+    freqs = np.atleast_1d(np.asarray(freqs, dtype=np.float64))
+    tx = np.ascontiguousarray(tgt[0], dtype=np.float64)
+    out = np.zeros(2 * len(freqs) * tx.shape[0])
+    rc = lib.orc_ray_field(len(xd[0]), p(xd[0]), p(xd[1]), p(xd[2]), p(xd[3]), v0, len(zif),
+                           p(zif if len(zif) else [0.0]), p(c), p(rho), tx.shape[0], p(tgt[0]),
+                           p(tgt[1]), p(tgt[2]), len(freqs), p(freqs), out.ctypes.data_as(_dp))
+    _check(rc, "ray_field")
     return _cplx_out(out).reshape(len(freqs), tx.shape[0])
 
 

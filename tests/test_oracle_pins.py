@@ -415,6 +415,143 @@ def test_gaussian_apodisation_closed_form(orc):
     assert np.all(orc.apodise((x, y, zz), w, (0, 0, 0), (0, 0, 1), 1e6) / w > 1 - 1e-12)
 
 
+# ----------------------------------------------------------------------------- ray tracing, eqs. 12, 14
+def _one(S):
+    return (np.array([S[0]]), np.array([S[1]]), np.array([S[2]]), np.array([1.0]))
+
+
+def _pts(P):
+    return tuple(np.array([p[k] for p in P], dtype=float) for k in range(3))
+
+
+def test_ray_matched_media_is_monopole(orc):
+    """Planes between identical media: T = 1, the ray is straight and both spreading
+    factors of eq. (12) equal the distance, so the ray model is eq. (3) exactly.  Field
+    points above the last plane get nothing."""
+    f = 1.5e6
+    xd = orc.sample_disc(5, 64, A, (0.0, 0.0, -0.02), 0.2)
+    tgt = W.random_cloud(6, 12, (0.004, 0.0, 0.02), (0.01, 0.01, 0.008))
+    for zif in ([0.0], [-0.005, 0.004]):
+        n = len(zif) + 1
+        ray = orc.ray_field(xd, 1.0, zif, [C_W] * n, [RHO_W] * n, tgt, [f])[0]
+        mono = orc.propagate(orc.MONOPOLE, xd[:3], xd[3], 1.0, tgt, C_W, f)
+        assert rel(ray, mono) < 1e-12
+    above = (np.array([0.0]), np.array([0.0]), np.array([0.003]))
+    assert orc.ray_field(xd, 1.0, [0.0, 0.004], [C_W] * 3, [RHO_W] * 3, above, [f])[0, 0] == 0
+
+
+def test_ray_extra_plane_between_identical_media(orc):
+    """A plane between two identical media changes nothing: the layer sums of the
+    spreading and the phase split one layer into two, and its T is 1."""
+    f = 2.0e6
+    xd = orc.sample_disc(7, 48, A, (0.0, 0.0, -0.03), 0.15)
+    tgt = W.random_cloud(8, 10, (0.006, 0.0, 0.015), (0.01, 0.01, 0.005))
+    steel = W.STEEL_5900
+    one = orc.ray_field(xd, 1.0, [0.0], [C_W, steel[0]], [RHO_W, steel[1]], tgt, [f])[0]
+    a = orc.ray_field(xd, 1.0, [-0.01, 0.0], [C_W, C_W, steel[0]], [RHO_W, RHO_W, steel[1]], tgt, [f])[0]
+    b = orc.ray_field(xd, 1.0, [0.0, 0.004], [C_W, steel[0], steel[0]], [RHO_W, steel[1], steel[1]], tgt, [f])[0]
+    assert rel(a, one) < 1e-12 and rel(b, one) < 1e-12
+
+
+@pytest.mark.parametrize("layers", [
+    ([0.0], [1480.0, 5900.0], [1000.0, 7800.0]),
+    ([0.0, 0.003], [1480.0, 2700.0, 5900.0], [1000.0, 2700.0, 7800.0]),
+])
+def test_ray_reciprocity(orc, layers):
+    """Source and receiver swapped (the stack mirrored in z, the media reversed):
+    rho_last phi(S -> P) = rho_first phi(P -> S), the reciprocity of the velocity
+    potential of point sources in fluids.  Breaks with a transmission product taken in
+    the wrong direction, or a spreading factor referred to the wrong end medium."""
+    zif, c, rho = layers
+    f = 1.0e6
+    S = (0.001, -0.002, -0.02)
+    for P in [(0.012, 0.003, 0.02), (0.0, 0.0, 0.015), (-0.02, 0.01, 0.03)]:
+        fwd = orc.ray_field(_one(S), 1.0, zif, c, rho, _pts([P]), [f])[0, 0]
+        Pm, Sm = (P[0], P[1], -P[2]), (S[0], S[1], -S[2])
+        rev = orc.ray_field(_one(Pm), 1.0, [-z for z in zif[::-1]], c[::-1], rho[::-1], _pts([Sm]), [f])[0, 0]
+        assert abs(rho[-1] * fwd - rho[0] * rev) < 1e-12 * abs(rho[0] * rev)
+
+
+def _fermat_time(S, P, zif, c):
+    """Least travel time over the crossing points (Fermat): the ray stays in the vertical
+    plane through S and P, so each crossing is a position s along it; nested bounded
+    searches (the time is convex in each crossing)."""
+    from scipy.optimize import minimize_scalar
+    S, P = np.array(S, float), np.array(P, float)
+    dh = P[:2] - S[:2]
+
+    def at(s, z):
+        return np.array([S[0] + s * dh[0], S[1] + s * dh[1], z])
+
+    def rest(prev, m):  # least time from point prev (on plane m-1) onward
+        if m == len(zif):
+            return np.linalg.norm(P - prev) / c[m]
+        res = minimize_scalar(lambda s: np.linalg.norm(at(s, zif[m]) - prev) / c[m] + rest(at(s, zif[m]), m + 1),
+                              bounds=(-0.5, 1.5), method="bounded", options={"xatol": 1e-14})
+        return res.fun
+    return rest(S, 0)
+
+
+@pytest.mark.parametrize("zif,c", [([0.0], [1480.0, 5900.0]), ([0.0, 0.004], [1480.0, 5900.0, 2700.0])])
+def test_ray_phase_is_fermat_time(orc, zif, c):
+    """The phase of each ray is omega times the least travel time through the planes
+    (eq. 13 made stationary): the root of eq. (14) found by the reference against a
+    direct minimisation over the crossing points.  With T > 0 the field of one sample
+    is -T e^{i omega t}/(2 pi A)."""
+    f = 1.3e6
+    rho = [1000.0] * len(c)
+    S = (0.002, 0.001, -0.025)
+    for P in [(0.006, 0.0, 0.01), (0.02, -0.004, 0.02), (0.0, 0.0, 0.01)]:
+        phi = orc.ray_field(_one(S), 1.0, zif, c, rho, _pts([P]), [f])[0, 0]
+        ex = np.exp(2j * math.pi * f * _fermat_time(S, P, zif, c))
+        assert abs(-phi / abs(phi) - ex) < 1e-9
+
+
+def _polar_rule_at(xs, ys, rmax, k):
+    """Windowed polar Gauss rule on the plane z = 0 about (xs, ys), fine enough for
+    wavenumber k over rmax."""
+    n_pan = int(k * rmax * 1.5 / 8) + 50
+    n_phi = int(k * rmax * 1.2) + 64
+    r, wr = gl_panels(0.0, rmax, n_pan, 16)
+    win = np.where(r < rmax / 2, 1.0, np.cos(0.5 * math.pi * (r - rmax / 2) / (rmax / 2)) ** 2)
+    ang = 2 * math.pi * np.arange(n_phi) / n_phi
+    R, PH = np.meshgrid(r, ang, indexing="ij")
+    w = ((wr * win * r)[:, None] * (2 * math.pi / n_phi) * np.ones_like(PH)).ravel()
+    return (xs + (R * np.cos(PH)).ravel(), ys + (R * np.sin(PH)).ravel(), np.zeros(R.size), w)
+
+
+def test_ray_is_stationary_phase_limit_of_rsi_chain(orc):
+    """Sec. 2.2 derives eq. (12) from the exact angular spectrum by stationary phase, so
+    at high frequency it must approach the RSI chain (eqs. 3, 7, local T) of a point
+    source through the plane, with a difference that falls like 1/(k D).  The interface
+    integral is done by an accurate polar rule about the ray's crossing point (from the
+    Fermat search, not from the reference's root).  The second medium is slower, so no
+    ray reaches the critical angle (where the local-T integral grows a head-wave term
+    the ray model does not have).  Wide angles (sin theta1 ~ 0.6) make the cos^2 ratio
+    of the spreading matter: swapping it misses by 6-11 %."""
+    from scipy.optimize import minimize_scalar
+    c, rho = [1480.0, 1100.0], [1000.0, 1200.0]
+    S = (0.0, 0.0, -0.02)
+    errs = {}
+    for f in (1.0e6, 2.0e6):
+        k = 2 * math.pi * f / min(c)
+        for P in [(0.004, 0.0, 0.015), (0.02, 0.0, 0.01), (0.025, 0.01, 0.02)]:
+            dh = np.array(P[:2]) - np.array(S[:2])
+            res = minimize_scalar(lambda s: math.hypot(s * dh[0], s * dh[1], S[2]) / c[0]
+                                  + math.hypot((1 - s) * dh[0], (1 - s) * dh[1], P[2]) / c[1],
+                                  bounds=(0.0, 1.0), method="bounded", options={"xatol": 1e-12})
+            xs, ys = S[0] + res.x * dh[0], S[1] + res.x * dh[1]
+            q = _polar_rule_at(xs, ys, 0.03, k)
+            ch = orc.chain(_one(S), 1.0, S, (0.0, 0.0, 1.0), [q], [0.0], c, rho, _pts([P]), [f],
+                           orc.T_LOCAL)[0, 0]
+            ray = orc.ray_field(_one(S), 1.0, [0.0], c, rho, _pts([P]), [f])[0, 0]
+            errs[(f, P)] = abs(ch / ray - 1)
+    for P in [(0.004, 0.0, 0.015), (0.02, 0.0, 0.01), (0.025, 0.01, 0.02)]:
+        e1, e2 = errs[(1.0e6, P)], errs[(2.0e6, P)]
+        assert e1 < 4e-3 and e2 < 2e-3, (P, e1, e2)
+        assert 0.4 < e2 / e1 < 0.6, (P, e1, e2)  # O(1/k)
+
+
 # ----------------------------------------------------------------------------- eqs. 8, 11, 15
 IMPEDANCE_CASES = [(1480.0, 1000.0, 5900.0, 7800.0), (5900.0, 7800.0, 2700.0, 2700.0),
                    (1480.0, 1000.0, 6409.0, 2700.0)]

@@ -284,6 +284,41 @@ rsi_status rsi_chain_ex(const rsi_transducer *xd, const rsi_interface *ifaces, i
                         void *out, void *stream);
 
 /* ------------------------------------------------------------------------------
+ * Ray tracing (Sec. 2.2): the single-surface-integral model.
+ * ------------------------------------------------------------------------------ */
+
+/* For every frequency f of `freqs` (host double[n_freq]) and every field point P:
+ *   phi(P) = -(v0 / 2 pi) sum_j w_j T_j e^{i 2 pi f t_j} / A_j      (eq. 12 under eq. 16)
+ * over the transducer samples Q_j of `xd` alone: no interface is sampled.  The ray
+ * from Q_j to P crosses the planes z = zif[0] < ... < zif[n_if-1] (host double[n_if],
+ * normal +z; layer l = 0..n_if is media[l], host rsi_medium[n_if+1]) with the
+ * horizontal slowness C that solves eq. (14) through the stack,
+ *   sum_l h_l C / sqrt(S_l^2 - C^2) = |P - Q_j| (horizontal),   S_l = 1 / c_l,
+ * h_l its vertical extent in layer l (h_0 = zif[0] - z_j, h_last = z_P - zif[n_if-1]).
+ * With eta_l = sqrt(S_l^2 - C^2) (c_l eta_l = cos theta_l, eq. 15):
+ *   t_j = C rho + sum_l h_l eta_l, the travel time (phase sum_l k_l D_l);
+ *   A_j = eta_0 sqrt((sum_l h_l / eta_l)(sum_l h_l S_l^2 / eta_l^3)), eq. (12)'s
+ *         spreading, extended to several planes by the stationary-phase evaluation
+ *         of the layered angular spectrum (eq. 10);
+ *   T_j = prod over the planes of eq. (11) at the ray's angles (real: a ray is never
+ *         past a critical angle).
+ * Pairs whose sample is on or below the first plane, or whose field point is on or
+ * above the last plane, contribute nothing.  n_if = 0: one medium, where eq. (12) is
+ * eq. (3) (the monopole pair sum of rsi_propagate).  xd->centre and xd->axis are not
+ * used.  out: device complex [n_freq][tgt->n] of the call's precision.
+ * Precision: RSI_FP64 solves every root to the last bit by Newton's method inside a
+ * bisection bracket.  RSI_FP32 computes per field point, in FP64, the ray from the
+ * centre of the samples' bounding box and its phase in revolutions; per pair it solves
+ * the root by Newton's method in FP32 from that ray and forms the travel-time
+ * difference to it in a cancellation-free form, so the large part of the phase never
+ * passes through FP32.  Errors: RSI_ERR_SIZE for n_if > 8 or negative counts;
+ * RSI_ERR_ARG for media with c or rho <= 0, planes not strictly increasing, a
+ * frequency <= 0 or non-finite values. */
+rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif, int n_if,
+                         const rsi_medium *media, const rsi_points *tgt, const double *freqs,
+                         int n_freq, rsi_precision prec, void *out, void *stream);
+
+/* ------------------------------------------------------------------------------
  * a7. Batching: persistent launches, plans and graph replay.
  * ------------------------------------------------------------------------------ */
 

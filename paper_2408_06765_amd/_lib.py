@@ -72,6 +72,8 @@ SIGNATURES = {
                       C.c_uint32, C.c_void_p, C.c_void_p], C.c_int),
     "rsi_reflection": ([C.c_int, C.c_int, _dp, C.POINTER(rsi_medium), _dp, _dp, C.c_int64,
                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "rsi_ray_field": ([C.POINTER(rsi_transducer), _dp, C.c_int, C.POINTER(rsi_medium),
+                       C.POINTER(rsi_points), _dp, C.c_int, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
     "rsi_propagate_batched": ([C.POINTER(rsi_instance), C.c_int, C.c_int, C.c_void_p], C.c_int),
     "rsi_plan_create_chain": ([C.POINTER(C.c_void_p), C.POINTER(rsi_transducer),
                                C.POINTER(rsi_interface), C.c_int, C.POINTER(rsi_medium),

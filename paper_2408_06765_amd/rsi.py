@@ -224,6 +224,26 @@ def rsi_chain(xd: Transducer, ifaces: Sequence[Interface], media, tgt, freqs, tm
     return out
 
 
+# ---------------------------------------------------------------------------- ray tracing
+def rsi_ray_field(xd: Transducer, zif: Sequence[float], media, tgt, freqs, prec: int,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Ray-tracing model (Sec. 2.2, eq. 12): transducer samples straight to the field
+    points through the planes z = zif[l]; complex [n_freq, n_tgt]."""
+    xs = xd.c_struct()
+    zif = [float(z) for z in zif]
+    if len(media) != len(zif) + 1:
+        raise ValueError("need one medium per layer: len(media) == len(zif) + 1")
+    tp = _points(*tgt, "tgt")
+    fr = _dvec(list(freqs))
+    if out is None:
+        out = torch.empty((len(freqs), tp.n), dtype=_OUT_DTYPE[prec], device=tgt[0].device)
+    _dev(out, _OUT_DTYPE[prec], "out")
+    L.check(L.load().rsi_ray_field(C.byref(xs), _dvec(zif) if zif else None, len(zif), _media(media),
+                                   C.byref(tp), fr, len(freqs), prec, _ptr(out), _stream()),
+            "rsi_ray_field")
+    return out
+
+
 # ---------------------------------------------------------------------------- a7
 @dataclass
 class Instance:

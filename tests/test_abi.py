@@ -150,3 +150,31 @@ def test_chain_validation():
     assert lib.rsi_plan_create_batched(C.byref(plan), inst, 1, 0) == 2
     assert lib.rsi_plan_destroy(None) == 0
     assert lib.rsi_plan_execute(None, None) == 1
+
+
+def test_ray_field_validation():
+    from paper_2408_06765_amd import _lib as L
+    lib = L.load()
+    xd = L.rsi_transducer(L.rsi_points(None, None, None, 0), None, 1.0, (C.c_double * 3)(0, 0, 0),
+                          (C.c_double * 3)(0, 0, 1))
+    media = (L.rsi_medium * 3)(L.rsi_medium(1480, 1000), L.rsi_medium(5900, 7800), L.rsi_medium(2700, 2700))
+    tgt = L.rsi_points(None, None, None, 0)
+    fr = (C.c_double * 1)(1e6)
+    zif = (C.c_double * 2)(0.05, 0.04)
+    ok = (C.c_double * 2)(0.04, 0.05)
+    # planes not strictly increasing, too many planes, negative count
+    assert lib.rsi_ray_field(C.byref(xd), zif, 2, media, C.byref(tgt), fr, 1, 0, None, None) == 2
+    assert lib.rsi_ray_field(C.byref(xd), ok, 9, media, C.byref(tgt), fr, 1, 0, None, None) == 3
+    assert lib.rsi_ray_field(C.byref(xd), ok, -1, media, C.byref(tgt), fr, 1, 0, None, None) == 3
+    # missing plane depths, bad medium, bad frequency, bad precision
+    assert lib.rsi_ray_field(C.byref(xd), None, 1, media, C.byref(tgt), fr, 1, 0, None, None) == 1
+    bad = (L.rsi_medium * 2)(L.rsi_medium(1480, 1000), L.rsi_medium(-5900, 7800))
+    assert lib.rsi_ray_field(C.byref(xd), ok, 1, bad, C.byref(tgt), fr, 1, 0, None, None) == 2
+    assert lib.rsi_ray_field(C.byref(xd), ok, 1, media, C.byref(tgt), (C.c_double * 1)(0.0), 1, 0, None,
+                             None) == 2
+    assert lib.rsi_ray_field(C.byref(xd), ok, 1, media, C.byref(tgt), fr, 1, 7, None, None) == 2
+    # no field points: nothing to do; field points but no output buffer
+    assert lib.rsi_ray_field(C.byref(xd), ok, 2, media, C.byref(tgt), fr, 1, 0, None, None) == 0
+    one = (C.c_double * 1)(0.0)
+    tgt1 = L.rsi_points(C.cast(one, C.c_void_p), C.cast(one, C.c_void_p), C.cast(one, C.c_void_p), 1)
+    assert lib.rsi_ray_field(C.byref(xd), ok, 2, media, C.byref(tgt1), fr, 1, 0, None, None) == 1

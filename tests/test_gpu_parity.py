@@ -407,3 +407,72 @@ def test_chain_plan_replay(gpu, orc, prec):
         _ = torch.randn(100, device="cuda").sum().item()
         assert np.array_equal(host(plan.out).view(np.uint64), eager.view(np.uint64))
     plan.destroy()
+
+
+# ----------------------------------------------------------------------------- ray tracing (Sec. 2.2)
+def _ray_case(orc, layout, n_xd, n_tgt, seed=0):
+    tilt = math.radians(10.0)
+    xd = orc.sample_disc(seed, n_xd, W.PISTON_RADIUS, (0.0, 0.0, 0.0), tilt)
+    if layout == "water":
+        zs, media = [], (W.WATER,)
+        centre = (0.004, 0.0, 0.04)
+    elif layout == "one":
+        zs, media = [0.05], (W.WATER, W.STEEL_5900)
+        centre = (0.05 * math.tan(tilt) + 0.012, 0.0, 0.05 + 0.015)
+    else:
+        cfg = W.LayeredStack()
+        zs, media = list(cfg.z_if), cfg.media
+        centre = (cfg.volume_centre_x(), 0.0, cfg.z_if[-1] + 0.012)
+    tgt = W.random_cloud(seed + 5, n_tgt, centre, (0.012, 0.006, 0.01))
+    return xd, zs, media, tgt
+
+
+def _ray_gpu(gpu, xd, zs, media, tgt, freqs, prec):
+    T = gpu.Transducer(*devpts(xd[:3]), dev(xd[3]), 1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    return host(gpu.rsi_ray_field(T, zs, media, devpts(tgt), freqs, prec))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("layout", ["water", "one", "stack"])
+@pytest.mark.parametrize("nf", [1, 11])
+def test_ray_field_matches_reference(gpu, orc, prec, layout, nf):
+    """eq. (12) through 0, 1 and 3 planes; one frequency, and eleven (a block of eight
+    and a ragged block of three in one call).  1000 field points: three full tiles and a
+    ragged one."""
+    xd, zs, media, tgt = _ray_case(orc, layout, 2048, 1000)
+    freqs = [2.5e6] if nf == 1 else list(np.linspace(1.0e6, 10.0e6, nf))
+    ref = orc.ray_field(xd, 1.0, zs, [m[0] for m in media], [m[1] for m in media], tgt, freqs)
+    got = _ray_gpu(gpu, xd, zs, media, tgt, freqs, prec)
+    for q in range(nf):
+        assert rel(got[q], ref[q]) <= TOL[prec], (q, rel(got[q], ref[q]))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ray_field_split_sources_and_masked_pairs(gpu, orc, prec):
+    """Enough samples for several source splits (fixed-order reduction), field points
+    above the last plane (no ray: exactly zero on both sides), and samples on both sides
+    of the first plane (only those above it radiate)."""
+    xd, zs, media, tgt = _ray_case(orc, "one", 9000, 300, seed=2)
+    tgt = tuple(np.concatenate([a, b]) for a, b in zip(tgt, W.random_cloud(11, 40, (0.01, 0.0, 0.045),
+                                                                              (0.01, 0.01, 0.004))))
+    freqs = [3.0e6, 4.0e6]
+    ref = orc.ray_field(xd, 1.0, zs, [m[0] for m in media], [m[1] for m in media], tgt, freqs)
+    got = _ray_gpu(gpu, xd, zs, media, tgt, freqs, prec)
+    assert rel(got, ref) <= TOL[prec]
+    assert np.all(got[:, 300:] == 0) and np.all(ref[:, 300:] == 0)
+    # a transducer straddling the first plane: the samples below it are masked
+    xs = list(orc.sample_disc(4, 3000, W.PISTON_RADIUS, (0.0, 0.0, 0.05), math.radians(30.0)))
+    tg = W.random_cloud(12, 300, (0.02, 0.0, 0.065), (0.01, 0.006, 0.008))
+    ref = orc.ray_field(xs, 1.0, zs, [m[0] for m in media], [m[1] for m in media], tg, [2.0e6])
+    got = _ray_gpu(gpu, xs, zs, media, tg, [2.0e6], prec)
+    assert rel(got, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ray_field_empty_transducer_gives_zero(gpu, prec):
+    import torch
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    T = gpu.Transducer(e, e, e, e, 1.0)
+    tg = devpts(W.random_cloud(1, 100, (0, 0, 0.06), (0.01, 0.01, 0.005)))
+    out = gpu.rsi_ray_field(T, [0.05], (W.WATER, W.STEEL_5900), tg, [1e6, 2e6], prec)
+    assert host(out).shape == (2, 100) and np.all(host(out) == 0)

@@ -43,7 +43,8 @@ def parse():
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="one_interface",
                     choices=["one_interface", "layered_stack", "scan_batch", "surrogate",
-                             "interface_continuity", "focused_normal"],
+                             "interface_continuity", "focused_normal", "ray_field",
+                             "ray_crossover"],
                     help="one_interface is the benchmark line; the others are secondary "
                          "measurements printed in the same format")
     ap.add_argument("--autotune", action="store_true",
@@ -353,6 +354,137 @@ def focused_normal(args):
     plan.destroy()
 
 
+def _event_ms(fn, reps=3):
+    """Median time of fn() in ms, HIP events on torch's current stream (the library
+    launches on it), after one untimed call."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def flops_ray_pair(n_layers, n_freq=1, newton=2):
+    """Algorithmic FP32 flops of one ray pair (FMA = 2, transcendental = 1), frozen at
+    two Newton evaluations: fixed 14 (geometry, predictor) + per evaluation 9 per layer
+    + 8, + 13 per layer + 3 after the root (travel time, spreading, transmission), + 9
+    per frequency (phase, sin, cos, accumulation)."""
+    L = n_layers
+    return 14 + newton * (9 * L + 8) + 13 * L + 3 + 9 * n_freq
+
+
+def ray_field_leg(args):
+    """Ray tracing (Sec. 2.2, eq. 12) on the oblique-incidence configuration of Sec. 3.1:
+    tilted piston (10 deg, 2.5 MHz), 10^5 Halton samples, one water/steel plane at 0.1 m,
+    a 401 x 401 slice of the x-z plane below it, FP32; FP64 and the RSI chain on a
+    sample of the slice for the error."""
+    import torch
+    from paper_2408_06765_amd import rsi
+    from paper_2408_06765_amd import workloads as W
+
+    cfg = W.RayCrossover()
+    media = cfg.stacks[1]
+    zs = cfg.planes(media)
+    H = rsi.RSI_SEQ_HALTON
+    xs = rsi.rsi_sample_disc(cfg.xd_seed, cfg.n_samples, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt, seq=H)
+    T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    n = 401
+    xc = cfg.patch_centres(media)[0]
+    X, Z = np.meshgrid(np.linspace(xc - 0.01, xc + 0.04, n), zs[0] + np.linspace(0.001, 0.04, n))
+    tgt = tuple(torch.as_tensor(a.ravel().copy(), device="cuda") for a in (X, 0 * X, Z))
+    out = torch.empty((1, n * n), dtype=torch.complex64, device="cuda")
+    run = lambda: rsi.rsi_ray_field(T, zs, media, tgt, [cfg.freq], rsi.RSI_FP32, out=out)
+    dt = timed(run, args.steps, args.warmup)
+    pairs = cfg.n_samples * n * n
+    # errors on every 97th point: FP32 vs FP64 ray model, ray model vs RSI chain
+    sub = torch.arange(0, n * n, 97, device="cuda")
+    ts = tuple(a[sub].contiguous() for a in tgt)
+    f32 = out[0, sub].cpu().numpy()
+    f64 = rsi.rsi_ray_field(T, zs, media, ts, [cfg.freq], rsi.RSI_FP64)[0].cpu().numpy()
+    q = rsi.rsi_sample_square(1 << 20, cfg.n_samples, xc, 0.0, zs[0], cfg.half_width, seq=H)
+    I = [rsi.Interface(*q[:3], q[3], zs[0])]
+    ch = rsi.rsi_chain(T, I, media, ts, [cfg.freq], rsi.RSI_T_LOCAL, rsi.RSI_FP64)[0].cpu().numpy()
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    fl = flops_ray_pair(len(media))
+    tflops = pairs * fl * args.steps / dt / 1e12
+    line = base_line(pairs * args.steps / dt / 1e9, args.steps, args.warmup, dt,
+                     {"workload": "ray_field: tilted piston (10 deg, 2.5 MHz) 10^5 Halton -> ray tracing "
+                                  "through water/steel (5840 m/s) at 0.1 m -> 401 x 401 x-z slice 1-40 mm "
+                                  "below", "pairs_per_step": pairs})
+    line["metric"] = "Gpairs/s ray tracing (eq. 12, one root of eq. 14 per pair) + % FP32 VALU peak"
+    line.update({
+        "flops_per_pair_convention": fl,
+        "tflops_algorithmic": round(tflops, 2),
+        "frac_fp32_peak": round(tflops / PEAK_FP32_TFLOPS, 4),
+        "fp32_vs_fp64_rel_l2": rel(f32, f64),
+        "ray_vs_rsi_chain_rel_l2": rel(f64, ch),
+    })
+    print(json.dumps(line), flush=True)
+
+
+def ray_crossover(args):
+    """Sec. 3.5 / Fig. 8: time of the RSI chain and of the ray model against the number
+    of field points through 0, 1 and 4 planes (FP32, one-shot calls, HIP events), and
+    where the two curves cross."""
+    import torch
+    from paper_2408_06765_amd import rsi
+    from paper_2408_06765_amd import workloads as W
+
+    cfg = W.RayCrossover()
+    H = rsi.RSI_SEQ_HALTON
+    xs = rsi.rsi_sample_disc(cfg.xd_seed, cfg.n_samples, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt, seq=H)
+    T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    freqs = [cfg.freq]
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    table = {}
+    for media in cfg.stacks:
+        zs = cfg.planes(media)
+        I = []
+        for m, (z, xc) in enumerate(zip(zs, cfg.patch_centres(media))):
+            q = rsi.rsi_sample_square((m + 1) << 20, cfg.n_samples, xc, 0.0, z, cfg.half_width, seq=H)
+            I.append(rsi.Interface(*q[:3], q[3], z))
+        rows = []
+        for nf in cfg.n_field:
+            tgt = tuple(torch.as_tensor(a, device="cuda") for a in cfg.field(media, nf))
+            o1 = torch.empty((1, nf), dtype=torch.complex64, device="cuda")
+            o2 = torch.empty((1, nf), dtype=torch.complex64, device="cuda")
+            t_rsi = _event_ms(lambda: rsi.rsi_chain(T, I, media, tgt, freqs, rsi.RSI_T_LOCAL, rsi.RSI_FP32, out=o1))
+            t_ray = _event_ms(lambda: rsi.rsi_ray_field(T, zs, media, tgt, freqs, rsi.RSI_FP32, out=o2))
+            row = {"n_field": nf, "rsi_ms": round(t_rsi, 3), "ray_ms": round(t_ray, 3)}
+            if nf == 1000:
+                row["ray_vs_rsi_rel_l2"] = rel(o2.cpu().numpy(), o1.cpu().numpy())
+            rows.append(row)
+            print(f"planes {len(zs)} n_field {nf}: rsi {t_rsi:.3f} ms ray {t_ray:.3f} ms", file=sys.stderr,
+                  flush=True)
+        # crossover: first interval where the ray time overtakes the RSI time (log-log)
+        cross = None
+        for a, b in zip(rows[:-1], rows[1:]):
+            da, db = math.log(a["ray_ms"] / a["rsi_ms"]), math.log(b["ray_ms"] / b["rsi_ms"])
+            if da < 0 <= db:
+                u = da / (da - db)
+                cross = round(math.exp(math.log(a["n_field"]) + u * math.log(b["n_field"] / a["n_field"])))
+                break
+        table[len(zs)] = {"rows": rows, "crossover_n_field": cross}
+    line = {
+        "metric": "field points above which the RSI chain is faster than ray tracing (Fig. 8)",
+        "value": table[1]["crossover_n_field"], "unit": "field points", "n_gpus": 1, "steps": 3,
+        "warmup": 1, "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ray_crossover: tilted piston (10 deg, 2.5 MHz), 0.1 m water, 0/1/4 planes "
+                               "(water/steel/aluminium/steel/water, 2 mm), 10^5 Halton samples per surface, "
+                               "field points in the last medium"},
+        "planes": {str(k): v for k, v in table.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def scan_batch(args):
     """256 uneven scan positions in one persistent launch (batched plan)."""
     import torch
@@ -446,6 +578,10 @@ def main():
         return interface_continuity(args)
     if args.workload == "focused_normal":
         return focused_normal(args)
+    if args.workload == "ray_field":
+        return ray_field_leg(args)
+    if args.workload == "ray_crossover":
+        return ray_crossover(args)
     if args.workload == "scan_batch":
         return scan_batch(args)
     if args.workload == "surrogate":

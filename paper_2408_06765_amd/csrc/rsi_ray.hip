@@ -44,7 +44,7 @@
 #include <cmath>
 #include <type_traits>
 
-#include "rsi_internal.h"
+#include "rsi_device.h"
 
 namespace rsi {
 namespace {
@@ -54,11 +54,13 @@ constexpr int kRayMaxL = kRayMaxIf + 1;    // layers
 constexpr int kRayFB = 8;                  // frequencies per launch
 constexpr int kRaySub = 64;                // sources per FP32 block before the fold
 constexpr int kRayMaxIt = 12;              // FP32 Newton evaluations per pair (bound)
+constexpr int64_t kRayFewTargets = 8192;   // below: one wave per field point and source range
+constexpr int64_t kRayFewWaves = 16384;    // waves that launch aims for
 
 // One transducer sample of the FP32 path (read with wave-uniform scalar loads).
 struct alignas(32) RayRecF {
     float ex, ey, ez, eh2;   // offset from the anchor; |horizontal offset|^2
-    float a, pad0, pad1, pad2;  // -(1/2pi) w_j v0
+    float a, pad0, pad1, pad2;  // -(1/2pi) w_j v0 2 rho_0 (see ray_pair_f32)
 };
 // FP64 path: absolute position and folded strength.
 struct alignas(32) RayRecD {
@@ -74,10 +76,9 @@ struct RayStack {
     double rhod[kRayMaxL];   // densities
     double zif0, zlast;      // first and last plane
     double Smind;            // min_l S_l
-    float S2[kRayMaxL], h[kRayMaxL], rho[kRayMaxL];
-    float Smin;              // FP32 min_l S_l
-    float Cmax;              // largest FP32 start value (below Smin)
-    float e2min;             // floor of S_l^2 - C^2 (grazing rays stay finite)
+    float S2[kRayMaxL], h[kRayMaxL], hS2[kRayMaxL], rho[kRayMaxL], rho2[kRayMaxL];
+    float Cmax;              // largest FP32 slowness: S_l^2 - C^2 > 0 in FP32 for every l
+    float hCmax;             // Cmax / 2
 };
 struct RayFreqs {
     double f[kRayFB];
@@ -85,8 +86,9 @@ struct RayFreqs {
     int n;                   // valid entries (the rest repeat the last)
 };
 
+// Anchor = centre of the samples' bounding box; radius = its half diagonal.
 __device__ inline void ray_anchor(const double *__restrict__ partials, double &ax, double &ay,
-                                  double &az) {
+                                  double &az, double &radius) {
     double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
     for (int b = 0; b < kBBoxBlocks; ++b)
         for (int k = 0; k < 3; ++k) {
@@ -96,20 +98,24 @@ __device__ inline void ray_anchor(const double *__restrict__ partials, double &a
     ax = 0.5 * (lo[0] + hi[0]);
     ay = 0.5 * (lo[1] + hi[1]);
     az = 0.5 * (lo[2] + hi[2]);
+    const double sx = hi[0] - lo[0], sy = hi[1] - lo[1], sz = hi[2] - lo[2];
+    radius = 0.5 * sqrt(sx * sx + sy * sy + sz * sz);
 }
 
+// A sample on or below the first plane has no ray: its strength is zero (decided here
+// in FP64, as in the definition).
 __global__ void __launch_bounds__(256) ray_prep_f32_kernel(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, const double *__restrict__ w, double v0,
-    const double *__restrict__ partials, double *__restrict__ anchor_out,
+    const double *__restrict__ z, const double *__restrict__ w, double v0, double zif0,
+    double rho0, const double *__restrict__ partials, double *__restrict__ anchor_out,
     RayRecF *__restrict__ rec) {
-    double ax, ay, az;
-    ray_anchor(partials, ax, ay, az);
+    double ax, ay, az, radius;
+    ray_anchor(partials, ax, ay, az, radius);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         anchor_out[0] = ax;
         anchor_out[1] = ay;
         anchor_out[2] = az;
-        anchor_out[3] = 0.0;
+        anchor_out[3] = radius;
     }
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
@@ -120,7 +126,7 @@ __global__ void __launch_bounds__(256) ray_prep_f32_kernel(
     r.ey = ey;
     r.ez = ez;
     r.eh2 = (float)(dex * dex + dey * dey);
-    r.a = (float)(-w[j] * v0 / kTwoPi);
+    r.a = zif0 - z[j] > 0.0 ? (float)(-w[j] * v0 * 2.0 * rho0 / kTwoPi) : 0.0f;
     r.pad0 = r.pad1 = r.pad2 = 0.0f;
     rec[j] = r;
 }
@@ -131,8 +137,8 @@ __global__ void __launch_bounds__(256) ray_prep_f64_kernel(
     const double *__restrict__ partials, double *__restrict__ anchor_out,
     RayRecD *__restrict__ rec) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double ax, ay, az;
-        ray_anchor(partials, ax, ay, az);
+        double ax, ay, az, radius;
+        ray_anchor(partials, ax, ay, az, radius);
         anchor_out[0] = ax;
         anchor_out[1] = ay;
         anchor_out[2] = az;
@@ -185,12 +191,20 @@ __device__ inline double ray_guess(double rho, double H, const RayStack &st) {
 }
 
 // Per-target constants of the FP32 path.
+// Start of the pair's Newton iteration: the pair's F at C_0 is exactly -R with
+// R = drho + e_z C_0 / eta_0^0 (the reference ray solves the reference equation), and its
+// derivatives at C_0 are the reference's with h_0 lowered by e_z.  Series reversion of
+// F(C_0 + delta) = 0 to third order:
+//   d = R / F1,  delta = d - a d^2 + (2 a^2 - b) d^3,  a = F2 / (2 F1),  b = F3 / (6 F1),
+// with 1/F1 = (1/F1_0)(1 + e_z g1 / F1_0), F2 = F2_0 - e_z g2 (g1, g2 the h_0-derivatives).
 template <int L, int NF>
 struct RayTgtF {
     float dmx, dmy;         // -2 (P - C_A) horizontal
     float rho0, rho02;      // reference horizontal distance, squared
-    float C0, c0e0, iFp0;   // reference root, C_0 / eta_0^0, 1 / F'(C_0)
-    float h00, hn;          // h_0 of the anchor, h_n of the field point
+    float C0, c0e0;         // reference root, C_0 / eta_0^0
+    float iF1, k1;          // 1/F1_0 and g1 / F1_0^2
+    float F2h, g2h, b3;     // F2_0 / 2, g2 / 2, F3_0 / (6 F1_0)
+    float h00, hn, hnS2;    // h_0 of the anchor; h_n of the field point (> 0) and h_n S_n^2
     float eta0[L];
     float ph0[NF];          // frac(f_q t_0)
     bool valid;             // field point below the last plane
@@ -214,25 +228,39 @@ __device__ __forceinline__ void ray_setup_f32(RayTgtF<L, NF> &T, double px, doub
         H += hc[l];
     }
     const double C0 = ray_root_f64<L>(rho0, hc, st, ray_guess(rho0, H, st));
-    // t_0 with the true extents: dt = t - t_0 holds for any C_0 and any h_0^0
-    double t0 = C0 * rho0, Fp = 0.0;
+    // t_0 with the true extents: dt = t - t_0 holds for any C_0 and any h_0^0.  The
+    // derivatives of F for the start use the clamped extents (well posed).
+    const double C02 = C0 * C0;
+    double t0 = C0 * rho0, F1 = 0.0, F2 = 0.0, F3 = 0.0;
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-        const double e2 = st.S2d[l] - C0 * C0;
+        const double e2 = st.S2d[l] - C02;
         const double eta = sqrt(e2);
+        const double ie2 = 1.0 / e2, ie3 = ie2 / eta;
         T.eta0[l] = (float)eta;
         t0 += h[l] * eta;
-        Fp += h[l] * st.S2d[l] / (eta * e2);
+        const double u = hc[l] * st.S2d[l] * ie3;  // h S^2 / eta^3
+        F1 += u;
+        F2 += 3.0 * C0 * u * ie2;
+        F3 += 3.0 * u * ie2 * (1.0 + 5.0 * C02 * ie2);
     }
+    const double e20 = st.S2d[0] - C02, eta00 = sqrt(e20);
+    const double g1 = st.S2d[0] / (eta00 * e20), g2 = 3.0 * C0 * g1 / e20;
+    const double iF1 = 1.0 / F1;
     T.dmx = (float)(-2.0 * dx);
     T.dmy = (float)(-2.0 * dy);
     T.rho0 = (float)rho0;
     T.rho02 = (float)(rho0 * rho0);
     T.C0 = (float)C0;
-    T.c0e0 = (float)(C0 / sqrt(st.S2d[0] - C0 * C0));
-    T.iFp0 = Fp > 0.0 ? (float)(1.0 / Fp) : 0.0f;
+    T.c0e0 = (float)(C0 / eta00);
+    T.iF1 = (float)iF1;
+    T.k1 = (float)(g1 * iF1 * iF1);
+    T.F2h = (float)(0.5 * F2);
+    T.g2h = (float)(0.5 * g2);
+    T.b3 = (float)(F3 * iF1 / 6.0);
     T.h00 = (float)h[0];
     T.hn = (float)hc[L - 1];  // positive, so the pair's iteration stays well posed
+    T.hnS2 = (float)(hc[L - 1] * st.S2d[L - 1]);
     T.valid = h[L - 1] > 0.0;
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
@@ -243,7 +271,10 @@ __device__ __forceinline__ void ray_setup_f32(RayTgtF<L, NF> &T, double px, doub
 }
 
 // One transducer sample against the lane's field point.  `s` is wave-uniform (SGPRs).
-template <int L, int NF, class Rec>
+// FRACT: reduce the phase to [0, 1) before v_sin / v_cos (needed only when the argument
+// can exceed their own range: |f dt| <= f |Q_j - C_A| / c_0, the travel time changing with
+// the sample's position at most at the first medium's slowness).
+template <int L, int NF, bool FRACT, class Rec>
 __device__ __forceinline__ void ray_pair_f32(const RayTgtF<L, NF> &T, const Rec &s,
                                              const RayStack &st, const float (&ff)[NF],
                                              float (&ar)[NF], float (&ai)[NF]) {
@@ -251,78 +282,93 @@ __device__ __forceinline__ void ray_pair_f32(const RayTgtF<L, NF> &T, const Rec 
     const float r2 = fmaxf(T.rho02 + q, 0.0f);
     const float rho = __builtin_amdgcn_sqrtf(r2);
     const float drho = q * __builtin_amdgcn_rcpf(fmaxf(rho + T.rho0, FLT_MIN));
-    const float h0 = T.h00 - s.ez;
-    float h[L];
-    h[0] = fmaxf(h0, 1e-12f);  // a sample on or below the first plane is masked below
+    // extents and h S^2 per layer (a sample on or below the first plane has a = 0; its
+    // extent is kept positive so that the iteration stays finite)
+    float h[L], hS2[L];
+    h[0] = fmaxf(T.h00 - s.ez, 1e-12f);
+    hS2[0] = h[0] * st.S2[0];
 #pragma unroll
-    for (int l = 1; l < L - 1; ++l) h[l] = st.h[l];
+    for (int l = 1; l < L - 1; ++l) {
+        h[l] = st.h[l];
+        hS2[l] = st.hS2[l];
+    }
     h[L - 1] = T.hn;
-    // first Newton step of the pair's equation taken from the reference ray
-    float C = fmaf(fmaf(s.ez, T.c0e0, drho), T.iFp0, T.C0);
-    C = fminf(fmaxf(C, 0.0f), st.Cmax);
+    hS2[L - 1] = T.hnS2;
+    // start: third-order series reversion about the reference root
+    const float R = fmaf(s.ez, T.c0e0, drho);
+    const float iF1 = fmaf(s.ez, T.k1, T.iF1);
+    const float d = R * iF1;
+    const float a = fmaf(-s.ez, T.g2h, T.F2h) * iF1;
+    const float u = fmaf(a + a, a, -T.b3);
+    float C = fmaf(d, fmaf(fmaf(u, d, -a), d, 1.0f), T.C0);
+    C = __builtin_amdgcn_fmed3f(C, 0.0f, st.Cmax);
+    // Newton on F(C) = C S1 - rho, F' = S3, until |F| is within a few units of its FP32
+    // rounding (the phase is stationary in C; the amplitude moves by ~1e-6 relative)
+    const float tolF = fmaf(4e-6f, rho, 1e-9f);
     float e2[L], r[L], S1, S3;
     for (int it = 0;; ++it) {
         S1 = 0.0f;
         S3 = 0.0f;
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-            e2[l] = fmaxf(fmaf(-C, C, st.S2[l]), st.e2min);
+            e2[l] = fmaf(-C, C, st.S2[l]);
             r[l] = __builtin_amdgcn_rsqf(e2[l]);  // 1 / eta_l
-            const float g = h[l] * r[l];
-            S1 += g;
-            S3 = fmaf(g * r[l] * r[l], st.S2[l], S3);
+            S1 = fmaf(h[l], r[l], S1);
+            S3 = fmaf(hS2[l] * r[l], r[l] * r[l], S3);
         }
-        const float iS3 = __builtin_amdgcn_rcpf(S3);
-        const float step = fmaf(C, S1, -rho) * iS3;
-        // converged to a few units of the FP32 rounding of F (the phase is stationary
-        // in C, the amplitude changes to first order by ~1e-6 relative)
-        if (fabsf(step) <= 2e-6f * fmaf(rho, iS3, C) || it == kRayMaxIt) break;
-        const float Cn = C - step;
-        C = Cn < st.Smin ? Cn : 0.5f * (C + st.Smin);
+        const float F = fmaf(C, S1, -rho);
+        if (fabsf(F) <= tolF || it == kRayMaxIt) break;
+        // Newton step, kept below C_max (steps from the left can overshoot the pole)
+        C = fminf(fmaf(-F, __builtin_amdgcn_rcpf(S3), C), fmaf(0.5f, C, st.hCmax));
     }
     float eta[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) eta[l] = e2[l] * r[l];
-    const float cs = C + T.C0;
-    float B = rho;
+    // sum_l h_l / (eta_l + eta_l^0)
+    float hsum;
+    if constexpr (L <= 5) {
+        float num = h[0], den = eta[0] + T.eta0[0];
 #pragma unroll
-    for (int l = 0; l < L; ++l) B = fmaf(-cs * h[l], __builtin_amdgcn_rcpf(eta[l] + T.eta0[l]), B);
-    float dt = fmaf(C - T.C0, B, fmaf(T.C0, drho, -s.ez * T.eta0[0]));
-    float m = s.a * r[0] * __builtin_amdgcn_rsqf(S1 * S3);
+        for (int l = 1; l < L; ++l) {
+            const float dl = eta[l] + T.eta0[l];
+            num = fmaf(num, dl, h[l] * den);
+            den *= dl;
+        }
+        hsum = num * __builtin_amdgcn_rcpf(den);
+    } else {
+        hsum = 0.0f;
 #pragma unroll
-    for (int l = 0; l < L - 1; ++l)
-        m *= 2.0f * st.rho[l] * eta[l] *
-             __builtin_amdgcn_rcpf(fmaf(st.rho[l + 1], eta[l], st.rho[l] * eta[l + 1]));
-    const bool ok = T.valid && h0 > 0.0f;
-    m = ok ? m : 0.0f;
-    dt = ok ? dt : 0.0f;
+        for (int l = 0; l < L; ++l) hsum = fmaf(h[l], __builtin_amdgcn_rcpf(eta[l] + T.eta0[l]), hsum);
+    }
+    const float B = fmaf(-(C + T.C0), hsum, rho);
+    const float dt = fmaf(C - T.C0, B, fmaf(T.C0, drho, -s.ez * T.eta0[0]));
+    // T / A = prod(2 rho_l eta_l) / (eta_0 sqrt(S1 S3) prod(den_l)),
+    // den_l = rho_{l+1} eta_l + rho_l eta_{l+1}; the first factor 2 rho_0 eta_0 / eta_0 is
+    // the constant 2 rho_0, folded into the sample's strength a
+    float num = s.a, den2 = S1 * S3;
 #pragma unroll
-    for (int q = 0; q < NF; ++q) {
-        const float ph = __builtin_amdgcn_fractf(fmaf(dt, ff[q], T.ph0[q]));
-        ar[q] = fmaf(m, __builtin_amdgcn_cosf(ph), ar[q]);
-        ai[q] = fmaf(m, __builtin_amdgcn_sinf(ph), ai[q]);
+    for (int l = 0; l < L - 1; ++l) {
+        const float dn = fmaf(st.rho[l + 1], eta[l], st.rho[l] * eta[l + 1]);
+        if (l > 0) num *= st.rho2[l] * eta[l];
+        den2 *= dn * dn;
+    }
+    const float m = num * __builtin_amdgcn_rsqf(den2);
+#pragma unroll
+    for (int q2 = 0; q2 < NF; ++q2) {
+        float ph = fmaf(dt, ff[q2], T.ph0[q2]);  // revolutions
+        if constexpr (FRACT) ph = __builtin_amdgcn_fractf(ph);
+        ar[q2] = fmaf(m, __builtin_amdgcn_cosf(ph), ar[q2]);
+        ai[q2] = fmaf(m, __builtin_amdgcn_sinf(ph), ai[q2]);
     }
 }
 
-// grid (target tiles of kBlock, source splits); out [split][fr.n][n_tgt]
-template <int L, int NF>
-__global__ void __launch_bounds__(kBlock) ray_f32_kernel(
-    const RayRecF *__restrict__ recs, int64_t n_src, int64_t chunk,
-    const double *__restrict__ tx, const double *__restrict__ ty, const double *__restrict__ tz,
-    int64_t n_tgt, const double *__restrict__ anchor, RayStack st, RayFreqs fr,
-    float2 *__restrict__ out) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool in = i < n_tgt;
-    if (!in) i = n_tgt - 1;
-    RayTgtF<L, NF> T;
-    ray_setup_f32<L, NF>(T, tx[i], ty[i], tz[i], anchor[0], anchor[1], anchor[2], st, fr);
-    float ff[NF];
-#pragma unroll
-    for (int q = 0; q < NF; ++q) ff[q] = fr.ff[q];
-    const int64_t j0 = (int64_t)blockIdx.y * chunk;
-    const int64_t j1 = (j0 + chunk < n_src) ? j0 + chunk : n_src;
+template <int L, int NF, bool FRACT>
+__device__ __forceinline__ void ray_sum_f32(const RayTgtF<L, NF> &T, const RayRecF *recs,
+                                            int64_t j0, int64_t j1, const RayStack &st,
+                                            const float (&ff)[NF], float (&mre)[NF],
+                                            float (&mim)[NF]) {
     const RayRecFPtr rec = (RayRecFPtr)recs;
-    float mre[NF], mim[NF], cre[NF], cim[NF];
+    float cre[NF], cim[NF];
 #pragma unroll
     for (int q = 0; q < NF; ++q) mre[q] = mim[q] = cre[q] = cim[q] = 0.0f;
     for (int64_t jb = j0; jb < j1; jb += kRaySub) {
@@ -330,7 +376,12 @@ __global__ void __launch_bounds__(kBlock) ray_f32_kernel(
         float ar[NF], ai[NF];
 #pragma unroll
         for (int q = 0; q < NF; ++q) ar[q] = ai[q] = 0.0f;
-        for (int64_t j = jb; j < je; ++j) ray_pair_f32<L, NF>(T, rec[j], st, ff, ar, ai);
+        if (je - jb == kRaySub) {  // full block: constant trip count
+            for (int jj = 0; jj < kRaySub; ++jj)
+                ray_pair_f32<L, NF, FRACT>(T, rec[jb + jj], st, ff, ar, ai);
+        } else {
+            for (int64_t j = jb; j < je; ++j) ray_pair_f32<L, NF, FRACT>(T, rec[j], st, ff, ar, ai);
+        }
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
             float y = ar[q] - cre[q];
@@ -343,11 +394,107 @@ __global__ void __launch_bounds__(kBlock) ray_f32_kernel(
             mim[q] = t;
         }
     }
+}
+
+// grid (target tiles of kBlock, source splits); out [split][fr.n][n_tgt].  inv_lam0 =
+// the block's highest frequency over c_0 (bounds the phase argument with the anchor radius).
+template <int L, int NF>
+__global__ void __launch_bounds__(kBlock) ray_f32_kernel(
+    const RayRecF *__restrict__ recs, int64_t n_src, int64_t chunk,
+    const double *__restrict__ tx, const double *__restrict__ ty, const double *__restrict__ tz,
+    int64_t n_tgt, const double *__restrict__ anchor, RayStack st, RayFreqs fr, double inv_lam0,
+    float2 *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool in = i < n_tgt;
+    if (!in) i = n_tgt - 1;
+    RayTgtF<L, NF> T;
+    ray_setup_f32<L, NF>(T, tx[i], ty[i], tz[i], anchor[0], anchor[1], anchor[2], st, fr);
+    float ff[NF];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) ff[q] = fr.ff[q];
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = (j0 + chunk < n_src) ? j0 + chunk : n_src;
+    float mre[NF], mim[NF];
+    if (phase_in_sin_range(anchor[3], inv_lam0))
+        ray_sum_f32<L, NF, false>(T, recs, j0, j1, st, ff, mre, mim);
+    else
+        ray_sum_f32<L, NF, true>(T, recs, j0, j1, st, ff, mre, mim);
     if (!in) return;
     float2 *o = out + (int64_t)blockIdx.y * fr.n * n_tgt;
 #pragma unroll
     for (int q = 0; q < NF; ++q)
-        if (q < fr.n) o[(int64_t)q * n_tgt + i] = make_float2(mre[q], mim[q]);
+        if (q < fr.n) o[(int64_t)q * n_tgt + i] = T.valid ? make_float2(mre[q], mim[q]) : make_float2(0.0f, 0.0f);
+}
+
+// Few field points: one wave per (field point, source range).  Lanes take every 64th
+// sample (vector loads; the sample records stay in L2), and the 64 lane sums are combined
+// by a fixed shuffle tree, so results are still bitwise repeatable.  grid (n_tgt, splits),
+// out [split][fr.n][n_tgt].
+template <int L, int NF, bool FRACT>
+__device__ __forceinline__ void ray_sum_lanes_f32(const RayTgtF<L, NF> &T,
+                                                  const RayRecF *__restrict__ rec, int64_t j0,
+                                                  int64_t j1, const RayStack &st,
+                                                  const float (&ff)[NF], float (&mre)[NF],
+                                                  float (&mim)[NF]) {
+    float cre[NF], cim[NF];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) mre[q] = mim[q] = cre[q] = cim[q] = 0.0f;
+    const int lane = threadIdx.x & 63;
+    for (int64_t jb = j0 + lane; jb < j1; jb += 64 * kRaySub) {
+        const int64_t je = (jb + 64 * kRaySub < j1) ? jb + 64 * kRaySub : j1;
+        float ar[NF], ai[NF];
+#pragma unroll
+        for (int q = 0; q < NF; ++q) ar[q] = ai[q] = 0.0f;
+        for (int64_t j = jb; j < je; j += 64) {
+            const RayRecF r = rec[j];
+            ray_pair_f32<L, NF, FRACT>(T, r, st, ff, ar, ai);
+        }
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            float y = ar[q] - cre[q];
+            float t = mre[q] + y;
+            cre[q] = (t - mre[q]) - y;
+            mre[q] = t;
+            y = ai[q] - cim[q];
+            t = mim[q] + y;
+            cim[q] = (t - mim[q]) - y;
+            mim[q] = t;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            mre[q] += __shfl_xor(mre[q], off);
+            mim[q] += __shfl_xor(mim[q], off);
+        }
+    }
+}
+
+template <int L, int NF>
+__global__ void __launch_bounds__(64) ray_f32_few_kernel(
+    const RayRecF *__restrict__ recs, int64_t n_src, int64_t chunk,
+    const double *__restrict__ tx, const double *__restrict__ ty, const double *__restrict__ tz,
+    int64_t n_tgt, const double *__restrict__ anchor, RayStack st, RayFreqs fr, double inv_lam0,
+    float2 *__restrict__ out) {
+    const int64_t i = blockIdx.x;
+    RayTgtF<L, NF> T;
+    ray_setup_f32<L, NF>(T, tx[i], ty[i], tz[i], anchor[0], anchor[1], anchor[2], st, fr);
+    float ff[NF];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) ff[q] = fr.ff[q];
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = (j0 + chunk < n_src) ? j0 + chunk : n_src;
+    float mre[NF], mim[NF];
+    if (phase_in_sin_range(anchor[3], inv_lam0))
+        ray_sum_lanes_f32<L, NF, false>(T, recs, j0, j1, st, ff, mre, mim);
+    else
+        ray_sum_lanes_f32<L, NF, true>(T, recs, j0, j1, st, ff, mre, mim);
+    if (threadIdx.x != 0) return;
+    float2 *o = out + (int64_t)blockIdx.y * fr.n * n_tgt;
+#pragma unroll
+    for (int q = 0; q < NF; ++q)
+        if (q < fr.n) o[(int64_t)q * n_tgt + i] = T.valid ? make_float2(mre[q], mim[q]) : make_float2(0.0f, 0.0f);
 }
 
 template <int L, int NF>
@@ -468,8 +615,20 @@ template <int L, int NF>
 void launch_ray_f32(dim3 grid, hipStream_t s, const RayRecF *rec, int64_t n_src, int64_t chunk,
                     const Targets &t, const double *anchor, const RayStack &st,
                     const RayFreqs &fr, float2 *dst) {
+    double fmax = 0.0;
+    for (int q = 0; q < fr.n; ++q) fmax = fr.f[q] > fmax ? fr.f[q] : fmax;
     hipLaunchKernelGGL((ray_f32_kernel<L, NF>), grid, dim3(kBlock), 0, s, rec, n_src, chunk, t.x,
-                       t.y, t.z, t.n, anchor, st, fr, dst);
+                       t.y, t.z, t.n, anchor, st, fr, fmax * sqrt(st.S2d[0]), dst);
+}
+
+template <int L, int NF>
+void launch_ray_f32_few(dim3 grid, hipStream_t s, const RayRecF *rec, int64_t n_src,
+                        int64_t chunk, const Targets &t, const double *anchor,
+                        const RayStack &st, const RayFreqs &fr, float2 *dst) {
+    double fmax = 0.0;
+    for (int q = 0; q < fr.n; ++q) fmax = fr.f[q] > fmax ? fr.f[q] : fmax;
+    hipLaunchKernelGGL((ray_f32_few_kernel<L, NF>), grid, dim3(64), 0, s, rec, n_src, chunk, t.x,
+                       t.y, t.z, t.n, anchor, st, fr, fmax * sqrt(st.S2d[0]), dst);
 }
 
 template <int L, int NF>
@@ -481,15 +640,19 @@ void launch_ray_f64(dim3 grid, hipStream_t s, const RayRecD *rec, int64_t n_src,
 }
 
 template <int NF, class Rec, class T2>
-void dispatch_ray(int L, dim3 grid, hipStream_t s, const Rec *rec, int64_t n_src, int64_t chunk,
-                  const Targets &t, const double *anchor, const RayStack &st, const RayFreqs &fr,
-                  T2 *dst) {
+void dispatch_ray(int L, bool few, dim3 grid, hipStream_t s, const Rec *rec, int64_t n_src,
+                  int64_t chunk, const Targets &t, const double *anchor, const RayStack &st,
+                  const RayFreqs &fr, T2 *dst) {
 #define RSI_RAY_CASE(LL)                                                                   \
     case LL:                                                                               \
-        if constexpr (std::is_same<T2, float2>::value)                                     \
-            launch_ray_f32<LL, NF>(grid, s, rec, n_src, chunk, t, anchor, st, fr, dst);    \
-        else                                                                               \
+        if constexpr (std::is_same<T2, float2>::value) {                                   \
+            if (few)                                                                       \
+                launch_ray_f32_few<LL, NF>(grid, s, rec, n_src, chunk, t, anchor, st, fr, dst); \
+            else                                                                           \
+                launch_ray_f32<LL, NF>(grid, s, rec, n_src, chunk, t, anchor, st, fr, dst); \
+        } else {                                                                           \
             launch_ray_f64<LL, NF>(grid, s, rec, n_src, chunk, t, anchor, st, fr, dst);    \
+        }                                                                                  \
         break;
     switch (L) {
         RSI_RAY_CASE(2)
@@ -535,26 +698,36 @@ rsi_status validate_ray(const rsi_transducer *xd, const double *zif, int n_if,
 RayStack make_stack(const double *zif, int n_if, const rsi_medium *media) {
     RayStack st{};
     const int L = n_if + 1;
-    double Smin = 1.0 / media[0].c, S2min = Smin * Smin;
+    double Smin = 1.0 / media[0].c;
     for (int l = 0; l < L; ++l) {
         const double S = 1.0 / media[l].c;
         st.S2d[l] = S * S;
         st.rhod[l] = media[l].rho;
         st.S2[l] = (float)(S * S);
         st.rho[l] = (float)media[l].rho;
+        st.rho2[l] = (float)(2.0 * media[l].rho);
         Smin = S < Smin ? S : Smin;
-        S2min = S * S < S2min ? S * S : S2min;
     }
     for (int l = 1; l < L - 1; ++l) {
         st.hd[l] = zif[l] - zif[l - 1];
         st.h[l] = (float)st.hd[l];
+        st.hS2[l] = (float)(st.hd[l] * st.S2d[l]);
     }
     st.zif0 = zif[0];
     st.zlast = zif[n_if - 1];
     st.Smind = Smin;
-    st.Smin = (float)Smin;
-    st.Cmax = (float)(Smin * (1.0 - 0x1p-12));
-    st.e2min = (float)(S2min * 0x1p-40);
+    // C_max: within 2^-20 of the fastest layer's slowness (rays closer to grazing than
+    // that carry an amplitude below ~1e-4 of a normal ray), and with S_l^2 - C^2 > 0 in
+    // FP32 for every layer, so the FP32 iteration needs no floor
+    float cm = (float)(Smin * (1.0 - 0x1p-20));
+    for (;;) {
+        bool ok = true;
+        for (int l = 0; l < L; ++l) ok = ok && std::fmaf(-cm, cm, st.S2[l]) > st.S2[l] * 0x1p-22f;
+        if (ok) break;
+        cm = std::nextafterf(cm, 0.0f);
+    }
+    st.Cmax = cm;
+    st.hCmax = 0.5f * cm;
     return st;
 }
 
@@ -627,10 +800,21 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
     }
     const RayStack st = make_stack(zif, n_if, media);
     const int L = n_if + 1;
-    const int64_t chunk = sh.chunk > 0 ? sh.chunk : n_src;
+    // FP32 with few field points: one wave per (point, source range), sized to put about
+    // 64 waves on every CU with at least 4 samples per lane
+    const bool few = prec == RSI_FP32 && tgt->n < kRayFewTargets;
+    int64_t chunk = sh.chunk > 0 ? sh.chunk : n_src;
+    if (few) {
+        int64_t splits = (kRayFewWaves + tgt->n - 1) / tgt->n;
+        const int64_t max_splits = (n_src + 255) / 256;
+        splits = splits < max_splits ? splits : max_splits;
+        splits = splits < 1 ? 1 : splits;
+        chunk = (n_src + splits - 1) / splits;
+        chunk = (chunk + 63) / 64 * 64;
+    }
     const int64_t ns = (n_src + chunk - 1) / chunk;
     if (ns > 65535) return RSI_ERR_SIZE;
-    const int64_t bx = (tgt->n + kBlock - 1) / kBlock;
+    const int64_t bx = few ? tgt->n : (tgt->n + kBlock - 1) / kBlock;
     if (bx > 0x7fffffff) return RSI_ERR_SIZE;
     const dim3 grid((unsigned)bx, (unsigned)ns);
     double *anchor = nullptr;
@@ -642,15 +826,16 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
         RSI_TRY(scratch.alloc(&rec, (size_t)n_src));
         if (ns > 1) RSI_TRY(scratch.alloc(&partial, (size_t)(ns * nfb_max * tgt->n)));
         hipLaunchKernelGGL(ray_prep_f32_kernel, dim3(blocks_of(n_src)), dim3(256), 0, s, n_src,
-                           xd->pts.x, xd->pts.y, xd->pts.z, xd->w, xd->v0, partials, anchor, rec);
+                           xd->pts.x, xd->pts.y, xd->pts.z, xd->w, xd->v0, zif[0], media[0].rho,
+                           partials, anchor, rec);
         RSI_HIP(hipGetLastError());
         for (int q0 = 0; q0 < n_freq; q0 += kRayFB) {
             const int nb = n_freq - q0 < kRayFB ? n_freq - q0 : kRayFB;
             const RayFreqs fr = freq_block(freqs, q0, nb);
             float2 *o = static_cast<float2 *>(out) + (int64_t)q0 * tgt->n;
             float2 *dst = ns > 1 ? partial : o;
-            if (nb == 1) dispatch_ray<1>(L, grid, s, rec, n_src, chunk, t, anchor, st, fr, dst);
-            else dispatch_ray<kRayFB>(L, grid, s, rec, n_src, chunk, t, anchor, st, fr, dst);
+            if (nb == 1) dispatch_ray<1>(L, few, grid, s, rec, n_src, chunk, t, anchor, st, fr, dst);
+            else dispatch_ray<kRayFB>(L, few, grid, s, rec, n_src, chunk, t, anchor, st, fr, dst);
             RSI_HIP(hipGetLastError());
             if (ns > 1) {
                 const int64_t n = (int64_t)nb * tgt->n;
@@ -673,8 +858,8 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
         const RayFreqs fr = freq_block(freqs, q0, nb);
         double2 *o = static_cast<double2 *>(out) + (int64_t)q0 * tgt->n;
         double2 *dst = ns > 1 ? partial : o;
-        if (nb == 1) dispatch_ray<1>(L, grid, s, rec, n_src, chunk, t, anchor, st, fr, dst);
-        else dispatch_ray<kRayFB>(L, grid, s, rec, n_src, chunk, t, anchor, st, fr, dst);
+        if (nb == 1) dispatch_ray<1>(L, false, grid, s, rec, n_src, chunk, t, anchor, st, fr, dst);
+        else dispatch_ray<kRayFB>(L, false, grid, s, rec, n_src, chunk, t, anchor, st, fr, dst);
         RSI_HIP(hipGetLastError());
         if (ns > 1) {
             const int64_t n = (int64_t)nb * tgt->n;

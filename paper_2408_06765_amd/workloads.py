@@ -9,6 +9,7 @@ configurations, as plain numbers and numpy arrays:
   one_interface (water -> 5900 m/s solid at 50 mm, 10 deg tilt, 5 MHz, 512 x 512 image)
   layered_stack (three interfaces 2 mm apart, 64 frequencies 1-10 MHz, 128^3 volume)
   focused_normal (Sec. 3.3: spherical-cap transducer over a water/steel interface)
+  ray_crossover (Sec. 3.5: RSI vs ray tracing against the number of field points)
   scan_batch   (256 uneven scan positions of the piston in water)
   surrogate    (parameter box of the learned surrogate)
 
@@ -26,6 +27,7 @@ import numpy as np
 WATER = (1480.0, 1000.0)          # (c m/s, rho kg/m^3), Sec. 3
 STEEL_5900 = (5900.0, 7800.0)     # second medium of the interface workloads
 STEEL_PAPER = (5840.0, 7800.0)    # steel of Sec. 3 (the paper-geometry variants)
+ALU_PAPER = (6409.0, 2700.0)      # aluminium of Sec. 3
 MID_2700 = (2700.0, 2700.0)       # middle layer of the stack (speed 2700 m/s)
 PISTON_RADIUS = 6.35e-3           # Sec. 3
 
@@ -186,6 +188,62 @@ class FocusedNormal:
         n = n or self.n_grid
         y = np.linspace(-self.half_y, self.half_y, n)
         return np.zeros_like(y), y, np.full_like(y, self.z_focus_paper)
+
+
+@dataclass
+class RayCrossover:
+    """Cost of the two models against the number of field points (Sec. 3.5): the
+    oblique piston (10 deg, 2.5 MHz, 0.1 m water path) above no plane (water), one
+    (water/steel) or four (water/steel/aluminium/steel/water, 2 mm layers, the
+    materials of Sec. 3), 10^5 Halton samples on every sampled surface (Sec. 3),
+    interface patches of half-width 3a (Sec. 2.3) centred on the Snell-chained beam
+    intercepts.  Field points: seeded uniform in a box about the refracted beam axis
+    2-20 mm below the last plane (the paper spreads them over all layers; here they all
+    lie in the last medium, which every method evaluates the same way)."""
+    radius: float = PISTON_RADIUS
+    freq: float = 2.5e6
+    tilt: float = deg(10.0)
+    water_path: float = 0.1
+    layer: float = 0.002
+    n_samples: int = 100000
+    xd_seed: int = 0
+    n_field: Tuple[int, ...] = (1, 10, 100, 1000, 10000, 100000, 1000000)
+    stacks: Tuple[Tuple[Tuple[float, float], ...], ...] = (
+        (WATER,),
+        (WATER, STEEL_PAPER),
+        (WATER, STEEL_PAPER, ALU_PAPER, STEEL_PAPER, WATER),
+    )
+
+    @property
+    def half_width(self) -> float:
+        return 3.0 * self.radius
+
+    @property
+    def axis(self):
+        return (math.sin(self.tilt), 0.0, math.cos(self.tilt))
+
+    def planes(self, media) -> List[float]:
+        return [self.water_path + m * self.layer for m in range(len(media) - 1)]
+
+    def patch_centres(self, media) -> List[float]:
+        zs = self.planes(media)
+        return snell_intercepts(0.0, self.tilt, zs, [m[0] for m in media]) if zs else []
+
+    def field(self, media, n: int, seed: int = 0):
+        zs = self.planes(media)
+        z_top = zs[-1] if zs else self.water_path
+        speeds = [m[0] for m in media]
+        if zs:
+            x_top = self.patch_centres(media)[-1]
+            s = min(math.sin(self.tilt) / speeds[0] * speeds[-1], 0.999999)
+        else:
+            x_top, s = z_top * math.tan(self.tilt), math.sin(self.tilt)
+        t = s / math.sqrt(1 - s * s)
+        rng = np.random.default_rng([seed, len(media), n])
+        d = rng.uniform(0.002, 0.020, n)
+        x = x_top + d * t + rng.uniform(-0.010, 0.010, n)
+        y = rng.uniform(-0.005, 0.005, n)
+        return x, y, z_top + d
 
 
 def snell_intercepts(x0: float, tilt: float, z_if, speeds) -> List[float]:

@@ -476,3 +476,17 @@ def test_ray_field_empty_transducer_gives_zero(gpu, prec):
     tg = devpts(W.random_cloud(1, 100, (0, 0, 0.06), (0.01, 0.01, 0.005)))
     out = gpu.rsi_ray_field(T, [0.05], (W.WATER, W.STEEL_5900), tg, [1e6, 2e6], prec)
     assert host(out).shape == (2, 100) and np.all(host(out) == 0)
+
+
+@pytest.mark.parametrize("nf", [1, 3])
+def test_ray_field_standard_launch_many_targets(gpu, orc, nf):
+    """FP32 with 8192 or more field points: one field point per lane, samples read as
+    wave-uniform records (below that, one wave per field point takes the samples across
+    its lanes; the other ray tests cover that launch).  9000 points: 35 full tiles and a
+    ragged one."""
+    xd, zs, media, tgt = _ray_case(orc, "one", 1024, 9000, seed=4)
+    freqs = [2.5e6] if nf == 1 else [1.5e6, 2.5e6, 3.5e6]
+    ref = orc.ray_field(xd, 1.0, zs, [m[0] for m in media], [m[1] for m in media], tgt, freqs)
+    got = _ray_gpu(gpu, xd, zs, media, tgt, freqs, 0)
+    for q in range(nf):
+        assert rel(got[q], ref[q]) <= TOL[0], (q, rel(got[q], ref[q]))

@@ -512,16 +512,18 @@ def scan_batch(args):
 
 def surrogate(args):
     """The learned surrogate: 10^7 RSI samples (5120 random configurations of the
-    one-interface piston family x 1953 points), 5 x 256 MLP trained with the MFMA kernels,
-    held-out residual per (f, depth, tilt) cell, 10^6 queries (64 configurations x 125^2)
-    answered by the network where its cell passes the threshold and by RSI elsewhere."""
+    one-interface piston family x 1953 points, drawn where the recipe trains: f <= 3.25 MHz,
+    tilt <= 10 deg), 5 x 256 MLP on the ray-model carrier trained with the MFMA kernels,
+    held-out residual per (f, depth, tilt) cell (8 x 4 x 8 over the whole box), 10^6
+    queries (64 random configurations over the whole box x 125^2) answered by the
+    surrogate where its cell passes the threshold and by RSI elsewhere."""
     import torch
     from paper_2408_06765_amd import surrogate as S
 
     cfg = S.SurrogateConfig()
     sur = S.Surrogate(cfg)
     t0 = time.perf_counter()
-    q, t = sur.dataset(S.random_configs(cfg, 5120, 3), points_per_config=1953)
+    q, t = sur.dataset(S.training_configs(cfg, 5120, 3), points_per_config=1953)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     loss = sur.train(q, t, log=lambda s: print(s, file=sys.stderr, flush=True))
@@ -530,7 +532,7 @@ def surrogate(args):
     del q, t
     errs = sur.validate(S.cell_configs(cfg, 101))
     e = np.array([errs[c] for c in sorted(errs)])
-    qc = S.cell_configs(cfg, 202)
+    qc = S.random_configs(cfg, 64, 202)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     out, used = sur.answer(qc)
@@ -541,10 +543,36 @@ def surrogate(args):
     torch.cuda.synchronize()
     t5 = time.perf_counter()
     for f, d, tl in qc:
-        sur.predict(sur.src.queries(f, d, tl))
+        sur.predict(f, d, tl)
     torch.cuda.synchronize()
     t6 = time.perf_counter()
-    rsi_s, routed_s, net_s = t5 - t4, t4 - t3, t6 - t5
+    for f, d, tl in qc:
+        sur.network(sur.src.queries(f, d, tl))
+    torch.cuda.synchronize()
+    t7 = time.perf_counter()
+    # speedup where the surrogate answers: its time against RSI on the passing configurations
+    ok = [not u for u in used]
+    pass_cfgs = [c for c, o in zip(qc, ok) if o]
+    rsi_pass = sur_pass = None
+    if pass_cfgs:
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for f, d, tl in pass_cfgs:
+            sur.src.rsi_pressure(f, d, tl)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for f, d, tl in pass_cfgs:
+            sur.predict(f, d, tl)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        rsi_pass, sur_pass = tb - ta, tc - tb
+    # the carrier alone (network output zero) against RSI: what the network adds
+    carrier = []
+    if cfg.carrier == "ray":
+        for f, d, tl in S.cell_configs(cfg, 101):
+            if f <= cfg.train_f_max and tl <= cfg.train_tilt_max:
+                carrier.append(S.rel_l2(sur.src.ray_pressure(f, d, tl), sur.src.rsi_pressure(f, d, tl)))
+    rsi_s, routed_s, sur_s, net_s = t5 - t4, t4 - t3, t6 - t5, t7 - t6
     n_q = len(qc) * cfg.nx * cfg.nz
     thresholds = [1e-3, 1e-2, 1e-1, 0.3, 1.0]
     line = {
@@ -553,15 +581,27 @@ def surrogate(args):
         "ms_per_step": round(1e3 * routed_s, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16 (MFMA, FP32 accumulation)", "data": "synthetic",
         "config": {"workload": "surrogate: piston + water/5900 m/s interface, x, z, f 1-10 MHz, depth "
-                               "30-70 mm, tilt 0-20 deg; 5 x 256 Fourier-feature MLP",
+                               "30-70 mm, tilt 0-20 deg; 5 x 256 Fourier-feature MLP on the "
+                               + ("ray-model carrier (2^14 samples), trained on f <= 3.25 MHz, tilt <= 10 deg"
+                                  if cfg.carrier == "ray" else "plane-wave carrier"),
                    "train_samples": 5120 * 1953, "queries": n_q},
         "data_generation_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2), "final_loss": loss,
         "cell_residual": {"min": float(e.min()), "median": float(np.median(e)), "max": float(e.max())},
         "cells_passing": {str(th): int((e <= th).sum()) for th in thresholds}, "cells": int(e.size),
+        "cells_in_training_region": int(sum(1 for (f, d, tl) in S.cell_configs(cfg, 101)
+                                            if f <= cfg.train_f_max and tl <= cfg.train_tilt_max)),
         "queries_on_rsi_fallback": int(sum(used)),
-        "rsi_s_for_queries": round(rsi_s, 4), "network_s_for_queries": round(net_s, 4),
+        "rsi_s_for_queries": round(rsi_s, 4), "surrogate_s_for_queries": round(sur_s, 4),
+        "network_s_for_queries": round(net_s, 4), "surrogate_speedup_all_queries": round(rsi_s / sur_s, 2),
         "network_only_speedup": round(rsi_s / net_s, 2),
+        "passing_configurations": len(pass_cfgs),
+        "speedup_in_passing_cells": round(rsi_pass / sur_pass, 2) if pass_cfgs else None,
+        "cells_passing_list": [int(c) for c in sorted(errs) if errs[c] <= cfg.threshold],
     }
+    if carrier:
+        cr = np.array(carrier)
+        line["carrier_only_residual_in_training_region"] = {"min": float(cr.min()), "median": float(np.median(cr)),
+                                                            "max": float(cr.max())}
     print(json.dumps(line), flush=True)
 
 

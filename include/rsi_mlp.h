@@ -3,13 +3,12 @@
  *
  * A coordinate MLP maps q = (x, z_below, f, depth, tilt) -- a field point in the x-z plane
  * below a planar water/solid interface at z = depth, for a piston tilted by `tilt` about
- * y at frequency f -- to the complex pressure envelope.  The field itself is
- *     p(q) = scale * (y0 + i y1) * exp(i psi(q)),
- *     psi  = 2 pi f (D1/c1 + D2/c2)
- * with D1, D2 the path lengths in the two media of the refracted ray from the piston
- * centre (the origin) to the field point (eqs. 14-15 with two media); the carrier
- * exp(i psi) is computed, the envelope y is learned.  The RSI model (rsi.h) produces
- * the training fields and stays the fallback and judge of the surrogate.
+ * y at frequency f -- to two numbers y = (y0, y1) from which the field is rebuilt around
+ * a computed carrier: the refracted plane wave of the beam axis (rsi_surrogate_carrier),
+ * or the ray-tracing model of the piston (rsi_ray_field, eq. 12) with the network
+ * learning the RSI field's departure from it (rsi_surrogate_ray_frame).  The RSI model
+ * (rsi.h) produces the training fields and stays the fallback and judge of the
+ * surrogate.
  *
  * Network: u = B v (B fixed [m][5], v = affine image of q on its box in [-1, 1]^5),
  * h0 = [sin 2 pi u, cos 2 pi u] (2m features), h_l = silu(W_l h_{l-1} + b_l) for
@@ -79,6 +78,23 @@ rsi_status rsi_mlp_load(rsi_mlp *net, const char *path);
  * one revolution).  scale = rho1 c1 (a pressure per unit velocity). */
 rsi_status rsi_surrogate_carrier(int64_t n, const float *q, rsi_medium m1, rsi_medium m2,
                                  int mode, const float *in, float *out, void *stream);
+
+/* Ray-model frame of the surrogate.  p_ray: the ray-tracing field (rsi_ray_field) at the
+ * same n points; s: the RMS of ref [n_ref], the ray field of the same configuration on a
+ * fixed set of points (n_ref >= 1).  For each point i, with u_i = p_ray[i] / |p_ray[i]|
+ * (|p_ray[i]| below 1e-30 s counts as 1e-30 s):
+ *   mode 0 (field -> frame): out[i] = (in[i] - p_ray[i]) conj(u_i) / (s sigma), its
+ *                            magnitude capped at `clip` when clip > 0 (training targets:
+ *                            configurations where the ray model fails do not swamp the
+ *                            loss; they fail validation and fall back to RSI anyway)
+ *   mode 1 (frame -> field): out[i] = p_ray[i] + s sigma in[i] u_i   (clip unused)
+ * The network then learns the RSI field's departure from the ray model in the frame of
+ * the ray's phase, scaled so that the squared error summed over a configuration's points
+ * is its squared rel-L2 (up to a constant).  All arrays complex FP32 (out may alias in).
+ * RSI_ERR_ARG for sigma <= 0, a non-finite clip or an unknown mode. */
+rsi_status rsi_surrogate_ray_frame(int64_t n, const float *p_ray, int64_t n_ref, const float *ref,
+                                   double sigma, double clip, int mode, const float *in,
+                                   float *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -459,6 +459,46 @@ __global__ void __launch_bounds__(256) carrier_kernel(int64_t n, const float *__
     }
 }
 
+// Ray-model frame: every block first forms s = RMS of the n_ref reference values (a few
+// hundred loads, fixed order), then maps its points.
+__global__ void __launch_bounds__(256) ray_frame_kernel(int64_t n, const float2 *__restrict__ pr,
+                                                        int64_t n_ref, const float2 *__restrict__ ref,
+                                                        double sigma, double clip, int mode,
+                                                        const float2 *__restrict__ in,
+                                                        float2 *__restrict__ out) {
+    __shared__ double part[256];
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < n_ref; k += 256) {
+        const float2 v = ref[k];
+        acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double s = sqrt(part[0] / (double)n_ref);
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float2 p = pr[i], a = in[i];
+    const double mag = fmax(sqrt((double)p.x * p.x + (double)p.y * p.y), 1e-30 * s);
+    const double ux = p.x / mag, uy = p.y / mag, ss = s * sigma;
+    if (mode == 0) {  // (in - p_ray) conj(u) / (s sigma)
+        const double dx = (double)a.x - p.x, dy = (double)a.y - p.y;
+        double yr = (dx * ux + dy * uy) / ss, yi = (dy * ux - dx * uy) / ss;
+        const double ym = sqrt(yr * yr + yi * yi);
+        if (clip > 0.0 && ym > clip) {
+            yr *= clip / ym;
+            yi *= clip / ym;
+        }
+        out[i] = make_float2((float)yr, (float)yi);
+    } else {          // p_ray + s sigma in u
+        out[i] = make_float2((float)(p.x + ss * (a.x * ux - a.y * uy)),
+                             (float)(p.y + ss * (a.x * uy + a.y * ux)));
+    }
+}
+
 }  // namespace rsi
 
 // ---------------------------------------------------------------------------
@@ -854,6 +894,23 @@ rsi_status rsi_surrogate_carrier(int64_t n, const float *q, rsi_medium m1, rsi_m
     hipLaunchKernelGGL(carrier_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream), n,
                        q, m1.c, m2.c, mode, m1.rho * m1.c, reinterpret_cast<const float2 *>(in),
                        reinterpret_cast<float2 *>(out));
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+rsi_status rsi_surrogate_ray_frame(int64_t n, const float *p_ray, int64_t n_ref, const float *ref,
+                                   double sigma, double clip, int mode, const float *in,
+                                   float *out, void *stream) {
+    if (n < 0 || n_ref < 0) return RSI_ERR_SIZE;
+    if (mode != 0 && mode != 1) return RSI_ERR_ARG;
+    if (!(sigma > 0.0) || !std::isfinite(sigma) || !std::isfinite(clip)) return RSI_ERR_ARG;
+    if (n == 0) return RSI_OK;
+    if (n_ref < 1 || (n + 255) / 256 > 0x7fffffff) return RSI_ERR_SIZE;
+    if (!p_ray || !ref || !in || !out) return RSI_ERR_NULL;
+    hipLaunchKernelGGL(ray_frame_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream),
+                       n, reinterpret_cast<const float2 *>(p_ray), n_ref,
+                       reinterpret_cast<const float2 *>(ref), sigma, clip, mode,
+                       reinterpret_cast<const float2 *>(in), reinterpret_cast<float2 *>(out));
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }

@@ -42,6 +42,7 @@
 // pair sum of rsi_pairsum.hip.
 #include <cfloat>
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 
 #include "rsi_device.h"
@@ -54,8 +55,7 @@ constexpr int kRayMaxL = kRayMaxIf + 1;    // layers
 constexpr int kRayFB = 8;                  // frequencies per launch
 constexpr int kRaySub = 64;                // sources per FP32 block before the fold
 constexpr int kRayMaxIt = 12;              // FP32 Newton evaluations per pair (bound)
-constexpr int64_t kRayFewTargets = 8192;   // below: one wave per field point and source range
-constexpr int64_t kRayFewWaves = 16384;    // waves that launch aims for
+constexpr int64_t kRayFewWaves = 16384;    // waves the few-point launch aims for
 
 // One transducer sample of the FP32 path (read with wave-uniform scalar loads).
 struct alignas(32) RayRecF {
@@ -800,10 +800,14 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
     }
     const RayStack st = make_stack(zif, n_if, media);
     const int L = n_if + 1;
-    // FP32 with few field points: one wave per (point, source range), sized to put about
-    // 64 waves on every CU with at least 4 samples per lane
-    const bool few = prec == RSI_FP32 && tgt->n < kRayFewTargets;
+    // FP32 with too few field points to fill the chip one per lane (fewer than 32 waves per
+    // CU): one wave per (point, source range) instead, sized to put about 64 waves on
+    // every CU with at least 4 samples per lane
     int64_t chunk = sh.chunk > 0 ? sh.chunk : n_src;
+    const int64_t waves_std = 4 * ((tgt->n + kBlock - 1) / kBlock) * ((n_src + chunk - 1) / chunk);
+    bool few = prec == RSI_FP32 && waves_std < kRayFewWaves / 2;
+    if (const char *e = std::getenv("RSI_RAY_FEW"))  // tuning/testing override: 0 or 1
+        if (prec == RSI_FP32 && (e[0] == '0' || e[0] == '1') && e[1] == 0) few = e[0] == '1';
     if (few) {
         int64_t splits = (kRayFewWaves + tgt->n - 1) / tgt->n;
         const int64_t max_splits = (n_src + 255) / 256;

@@ -1,8 +1,10 @@
 """Learned surrogate of the post-interface field, with the RSI model as its fallback.
 
 Binding of include/rsi_mlp.h (argument marshalling only) plus the training recipe:
-fields from the RSI chain (rsi_chain, FP32) on a grid of configurations are demodulated
-by the ray carrier (rsi_surrogate_carrier) and fitted by the MLP (rsi_mlp_train_step);
+fields from the RSI chain (rsi_chain, FP32) on random configurations are taken into the
+frame of a computed carrier -- by default the ray-tracing model of the same piston
+(rsi_ray_field, eq. 12; rsi_surrogate_ray_frame), else the refracted plane wave of the
+beam axis (rsi_surrogate_carrier) -- and fitted by the MLP (rsi_mlp_train_step);
 held-out configurations give a residual per parameter cell, and queries in cells whose
 residual exceeds the threshold are answered by the RSI chain instead.
 """
@@ -37,6 +39,8 @@ SIGNATURES = {
     "rsi_mlp_load": ([_vp, C.c_char_p], C.c_int),
     "rsi_surrogate_carrier": ([C.c_int64, _vp, L.rsi_medium, L.rsi_medium, C.c_int, _vp, _vp, _vp],
                               C.c_int),
+    "rsi_surrogate_ray_frame": ([C.c_int64, _vp, C.c_int64, _vp, C.c_double, C.c_double, C.c_int, _vp, _vp,
+                                 _vp], C.c_int),
 }
 _bound = False
 
@@ -143,6 +147,18 @@ def rsi_surrogate_carrier(q: torch.Tensor, m1, m2, mode: int, x: torch.Tensor) -
     return out
 
 
+def rsi_surrogate_ray_frame(p_ray: torch.Tensor, ref: torch.Tensor, sigma: float, mode: int,
+                            x: torch.Tensor, clip: float = 0.0) -> torch.Tensor:
+    """mode 0: field -> frame of the ray field (magnitude capped at clip > 0); mode 1:
+    frame -> field (complex64)."""
+    out = torch.empty_like(x)
+    L.check(_load().rsi_surrogate_ray_frame(x.shape[0], _dev(p_ray, torch.complex64, "p_ray"), ref.shape[0],
+                                            _dev(ref, torch.complex64, "ref"), sigma, clip, mode,
+                                            _dev(x, torch.complex64, "in"), _dev(out, torch.complex64, "out"),
+                                            _stream()), "rsi_surrogate_ray_frame")
+    return out
+
+
 # ------------------------------------------------------------------------------ recipe
 def glorot_params(n_ff: int, width: int, depth: int, seed: int) -> np.ndarray:
     """Flat FP32 initial parameters: Glorot-uniform weights, zero biases."""
@@ -175,17 +191,28 @@ class SurrogateConfig:
     grid_f: int = 8
     grid_depth: int = 8
     grid_tilt: int = 10
-    cells: Tuple[int, int, int] = (4, 4, 4)
+    cells: Tuple[int, int, int] = (8, 4, 8)
     n_ff: int = 128
     width: int = 256
     depth: int = 5
-    ff_scales: Tuple[float, ...] = (6.0, 4.0, 2.0, 2.0, 2.0)
+    ff_scales: Tuple[float, ...] = (2.0, 1.5, 0.75, 0.75, 0.75)
     batch: int = 65536
-    epochs: int = 60
+    epochs: int = 300
     lr0: float = 2e-3
     lr1: float = 2e-5
     threshold: float = 1e-3
     seed: int = 0
+    carrier: str = "ray"          # "ray" (rsi_ray_field) or "plane" (refracted plane wave)
+    n_carrier: int = 1 << 14      # transducer samples of the ray carrier
+    sigma: float = 0.02           # expected departure of RSI from the ray model (frame scale)
+    clip: float = 5.0             # cap on training targets in that frame
+    n_ref_side: int = 16          # ref grid of the frame's scale: n_ref_side^2 points
+    # training configurations are drawn from the part of the box where 1e-3 is within
+    # reach: below ~3 MHz the RSI field at 2^16 / 2^18 samples is itself reproducible to
+    # a few 1e-4 (it moves by ~1e-2 at 8-10 MHz when the sample counts are doubled), and
+    # below ~10 deg of tilt no part of the beam passes the critical angle
+    train_f_max: float = 3.25e6
+    train_tilt_max: float = math.radians(10.0)
 
 
 def lohi(box: W.SurrogateBox):
@@ -210,6 +237,17 @@ def random_configs(cfg: SurrogateConfig, n: int, seed: int) -> np.ndarray:
     b = cfg.box
     return np.stack([rng.uniform(*b.f_range, n), rng.uniform(*b.depth_range, n),
                      rng.uniform(*b.tilt_range, n)], 1)
+
+
+def training_configs(cfg: SurrogateConfig, n: int, seed: int) -> np.ndarray:
+    """n configurations uniform in the box, restricted to f <= train_f_max and tilt <=
+    train_tilt_max."""
+    rng = np.random.default_rng(seed)
+    b = cfg.box
+    f1 = min(b.f_range[1], cfg.train_f_max)
+    t1 = min(b.tilt_range[1], cfg.train_tilt_max)
+    return np.stack([rng.uniform(b.f_range[0], f1, n), rng.uniform(*b.depth_range, n),
+                     rng.uniform(b.tilt_range[0], t1, n)], 1)
 
 
 def cell_configs(cfg: SurrogateConfig, seed: int) -> np.ndarray:
@@ -260,6 +298,28 @@ class FieldSource:
         b = self.cfg.box
         return rng.uniform(*b.x_range, n), rng.uniform(*b.z_below, n)
 
+    def _targets(self, q: torch.Tensor):
+        # field points are the FP32 query coordinates widened to FP64, so that the
+        # surrogate and the RSI see exactly the same points
+        return (q[:, 0].double().contiguous(), torch.zeros(q.shape[0], dtype=torch.float64, device="cuda"),
+                (q[:, 3].double() + q[:, 1].double()).contiguous())
+
+    def ray_pressure(self, f: float, depth: float, tilt: float, xz=None) -> torch.Tensor:
+        """p = i omega rho2 phi of the ray-tracing model (eq. 12) at the query points, from
+        the first n_carrier samples of the piston's sample sequence (FP32)."""
+        cfg, b = self.cfg, self.cfg.box
+        xs = rsi.rsi_sample_disc(0, cfg.n_carrier, b.radius, (0.0, 0.0, 0.0), tilt)
+        T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), (math.sin(tilt), 0.0, math.cos(tilt)))
+        phi = rsi.rsi_ray_field(T, [depth], b.media, self._targets(self.queries(f, depth, tilt, xz)), [f],
+                                rsi.RSI_FP32)[0]
+        return rsi.rsi_to_pressure(phi, b.media[1][1], f)
+
+    def ray_reference(self, f: float, depth: float, tilt: float) -> torch.Tensor:
+        """The ray field on the fixed n_ref_side^2 grid that sets a configuration's scale."""
+        b, n = self.cfg.box, self.cfg.n_ref_side
+        X, Z = np.meshgrid(np.linspace(*b.x_range, n), np.linspace(*b.z_below, n))
+        return self.ray_pressure(f, depth, tilt, (X.ravel(), Z.ravel()))
+
     def rsi_pressure(self, f: float, depth: float, tilt: float, xz=None) -> torch.Tensor:
         """p = i omega rho2 phi at the grid points from the RSI chain (FP32)."""
         cfg, b = self.cfg, self.cfg.box
@@ -267,11 +327,7 @@ class FieldSource:
         qs = rsi.rsi_sample_square(1, cfg.n_if, depth * math.tan(tilt), 0.0, depth, cfg.half_width)
         T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), (math.sin(tilt), 0.0, math.cos(tilt)))
         I = [rsi.Interface(*qs[:3], qs[3], depth)]
-        # field points are the FP32 query coordinates widened to FP64, so that the
-        # surrogate and the RSI see exactly the same points
-        q = self.queries(f, depth, tilt, xz)
-        tgt = (q[:, 0].double().contiguous(), torch.zeros(q.shape[0], dtype=torch.float64, device="cuda"),
-               (q[:, 3].double() + q[:, 1].double()).contiguous())
+        tgt = self._targets(self.queries(f, depth, tilt, xz))
         phi = rsi.rsi_chain(T, I, b.media, tgt, [f], rsi.RSI_T_LOCAL, rsi.RSI_FP32)[0]
         return rsi.rsi_to_pressure(phi, b.media[1][1], f)
 
@@ -303,7 +359,11 @@ class Surrogate:
             xz = None if points_per_config is None else self.src.random_points(rng, points_per_config)
             q = self.src.queries(f, d, t, xz)
             p = self.src.rsi_pressure(f, d, t, xz)
-            env = rsi_surrogate_carrier(q, self.m1, self.m2, 0, p)
+            if self.cfg.carrier == "ray":
+                env = rsi_surrogate_ray_frame(self.src.ray_pressure(f, d, t, xz), self.src.ray_reference(f, d, t),
+                                              self.cfg.sigma, 0, p, self.cfg.clip)
+            else:
+                env = rsi_surrogate_carrier(q, self.m1, self.m2, 0, p)
             qs.append(q)
             ts.append(torch.view_as_real(env).contiguous())
         return torch.cat(qs), torch.cat(ts)
@@ -331,22 +391,30 @@ class Surrogate:
         return float(loss)
 
     # ---- inference
-    def predict(self, q: torch.Tensor) -> torch.Tensor:
-        """Field p (complex64) from the network and the carrier, in batches."""
+    def network(self, q: torch.Tensor) -> torch.Tensor:
+        """The network's output y0 + i y1 (complex64) for query rows q, in batches."""
         out = torch.empty(q.shape[0], dtype=torch.complex64, device=q.device)
         y = torch.empty((self.cfg.batch, 2), dtype=torch.float32, device=q.device)
         for s in range(0, q.shape[0], self.cfg.batch):
             e = min(q.shape[0], s + self.cfg.batch)
             yy = self.net.forward(q[s:e].contiguous(), y[:e - s])
-            out[s:e] = rsi_surrogate_carrier(q[s:e].contiguous(), self.m1, self.m2, 1,
-                                             torch.view_as_complex(yy).contiguous())
+            out[s:e] = torch.view_as_complex(yy)
         return out
+
+    def predict(self, f: float, depth: float, tilt: float, xz=None) -> torch.Tensor:
+        """Field p (complex64) of one configuration at its image grid (or the given (x, z)
+        points): the network's output taken back from the carrier's frame."""
+        q = self.src.queries(f, depth, tilt, xz)
+        y = self.network(q)
+        if self.cfg.carrier == "ray":
+            return rsi_surrogate_ray_frame(self.src.ray_pressure(f, depth, tilt, xz),
+                                           self.src.ray_reference(f, depth, tilt), self.cfg.sigma, 1, y)
+        return rsi_surrogate_carrier(q, self.m1, self.m2, 1, y)
 
     def validate(self, configs: np.ndarray) -> Dict[int, float]:
         """Held-out residual (rel-L2 against RSI) per cell; the worst config in a cell counts."""
         for f, d, t in configs:
-            q = self.src.queries(f, d, t)
-            err = rel_l2(self.predict(q), self.src.rsi_pressure(f, d, t))
+            err = rel_l2(self.predict(f, d, t), self.src.rsi_pressure(f, d, t))
             c = cell_of(self.cfg, f, d, t)
             self.cell_err[c] = max(self.cell_err.get(c, 0.0), err)
         return self.cell_err
@@ -358,7 +426,6 @@ class Surrogate:
         for f, d, t in configs:
             c = cell_of(self.cfg, f, d, t)
             ok = self.cell_err.get(c, math.inf) <= self.cfg.threshold
-            q = self.src.queries(f, d, t)
-            out.append(self.predict(q) if ok else self.src.rsi_pressure(f, d, t))
+            out.append(self.predict(f, d, t) if ok else self.src.rsi_pressure(f, d, t))
             used.append(not ok)
         return out, used

@@ -52,6 +52,12 @@ def test_surrogate_argument_errors():
     assert lib.rsi_mlp_forward(None, 1, None, None, None) == 1
     assert lib.rsi_surrogate_carrier(4, None, _lib_medium(1480, 1000), _lib_medium(5900, 7800), 3, None, None,
                                      None) == 2
+    # ray frame: sigma <= 0, unknown mode, no reference values, missing arrays
+    assert lib.rsi_surrogate_ray_frame(4, None, 4, None, 0.0, 0.0, 0, None, None, None) == 2
+    assert lib.rsi_surrogate_ray_frame(4, None, 4, None, 0.02, 0.0, 2, None, None, None) == 2
+    assert lib.rsi_surrogate_ray_frame(4, None, 0, None, 0.02, 0.0, 0, None, None, None) == 3
+    assert lib.rsi_surrogate_ray_frame(4, None, 4, None, 0.02, 5.0, 1, None, None, None) == 1
+    assert lib.rsi_surrogate_ray_frame(0, None, 0, None, 0.02, 5.0, 1, None, None, None) == 0
 
 
 def _lib_medium(c, rho):

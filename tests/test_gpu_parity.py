@@ -478,13 +478,16 @@ def test_ray_field_empty_transducer_gives_zero(gpu, prec):
     assert host(out).shape == (2, 100) and np.all(host(out) == 0)
 
 
+@pytest.mark.parametrize("launch", ["0", "1"])
 @pytest.mark.parametrize("nf", [1, 3])
-def test_ray_field_standard_launch_many_targets(gpu, orc, nf):
-    """FP32 with 8192 or more field points: one field point per lane, samples read as
-    wave-uniform records (below that, one wave per field point takes the samples across
-    its lanes; the other ray tests cover that launch).  9000 points: 35 full tiles and a
-    ragged one."""
-    xd, zs, media, tgt = _ray_case(orc, "one", 1024, 9000, seed=4)
+def test_ray_field_both_fp32_launches(gpu, orc, nf, launch, monkeypatch):
+    """The two FP32 launches, forced (RSI_RAY_FEW): one field point per lane with the
+    samples as wave-uniform records ("0", chosen for large workloads), and one wave per
+    field point with the samples across its lanes ("1", chosen when the first would not
+    fill the chip).  9000 points: 35 full tiles and a ragged one; 5000 samples: several
+    source ranges and a ragged block."""
+    monkeypatch.setenv("RSI_RAY_FEW", launch)
+    xd, zs, media, tgt = _ray_case(orc, "one", 5000, 9000, seed=4)
     freqs = [2.5e6] if nf == 1 else [1.5e6, 2.5e6, 3.5e6]
     ref = orc.ray_field(xd, 1.0, zs, [m[0] for m in media], [m[1] for m in media], tgt, freqs)
     got = _ray_gpu(gpu, xd, zs, media, tgt, freqs, 0)

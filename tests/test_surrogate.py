@@ -32,8 +32,7 @@ def test_training_fits_the_rsi_fields(small):
     probe = train_cfgs[:8]
 
     def err():
-        return np.median([S.rel_l2(sur.predict(sur.src.queries(f, d, t)), sur.src.rsi_pressure(f, d, t))
-                          for f, d, t in probe])
+        return np.median([S.rel_l2(sur.predict(f, d, t), sur.src.rsi_pressure(f, d, t)) for f, d, t in probe])
 
     before = err()
     q, t = sur.dataset(train_cfgs, points_per_config=1953)
@@ -78,25 +77,59 @@ def test_routing_infinite_threshold_is_the_network(small):
         cfg.threshold = old
     assert not any(used)
     for (f, d, t), o in zip(qc, out):
-        assert torch.equal(o, sur.predict(sur.src.queries(f, d, t)))
+        assert torch.equal(o, sur.predict(f, d, t))
 
 
 def test_network_is_faster_than_rsi_on_a_million_queries(small):
-    """10^6 query points (64 configurations x 125^2): the network path against the RSI
+    """10^6 query points (64 configurations x 125^2): the network alone, and the whole
+    surrogate answer (ray carrier with 2^14 samples + network + frame), against the RSI
     chain (2^16 piston and 2^18 interface samples per configuration)."""
     import torch
     S, cfg, sur = small
-    full = S.FieldSource(S.SurrogateConfig())
+    fcfg = S.SurrogateConfig()
+    full = S.FieldSource(fcfg)
     qc = S.random_configs(cfg, 64, 13)
+    qs = [full.queries(f, d, t) for f, d, t in qc]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for f, d, t in qc:
-        sur.predict(full.queries(f, d, t))
+    for q in qs:
+        sur.network(q)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    for (f, d, t), q in zip(qc, qs):
+        S.rsi_surrogate_ray_frame(full.ray_pressure(f, d, t), full.ray_reference(f, d, t), fcfg.sigma, 1,
+                                  sur.network(q))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
     for f, d, t in qc:
         full.rsi_pressure(f, d, t)
     torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    print(f"1e6 queries: network {t1 - t0:.3f} s, RSI {t2 - t1:.3f} s, {(t2 - t1) / (t1 - t0):.1f}x")
-    assert (t2 - t1) > 10 * (t1 - t0)
+    t3 = time.perf_counter()
+    print(f"1e6 queries: network {t1 - t0:.3f} s, surrogate {t2 - t1:.3f} s, RSI {t3 - t2:.3f} s")
+    assert (t3 - t2) > 10 * (t1 - t0)
+    assert (t3 - t2) > 3 * (t2 - t1)
+
+
+def test_ray_frame_matches_its_formula(gpu):
+    """rsi_surrogate_ray_frame against the formula in FP64 (numpy): s = RMS of the
+    reference values, u = p_ray/|p_ray|; mode 0 (with and without the cap) and mode 1,
+    and mode 1 undoes mode 0."""
+    import torch
+    from paper_2408_06765_amd import surrogate as S
+    rng = np.random.default_rng(3)
+    n, nr, sigma = 5000, 256, 0.02
+    pr = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+    ref = (3 * (rng.standard_normal(nr) + 1j * rng.standard_normal(nr))).astype(np.complex64)
+    p = (pr * (1 + 0.05 * (rng.standard_normal(n) + 1j * rng.standard_normal(n)))).astype(np.complex64)
+    p[:50] *= 20  # large departures, for the cap
+    s = np.sqrt(np.mean(np.abs(ref.astype(np.complex128)) ** 2))
+    u = pr.astype(np.complex128) / np.abs(pr.astype(np.complex128))
+    y_ex = (p.astype(np.complex128) - pr) * np.conj(u) / (s * sigma)
+    d = lambda a: torch.as_tensor(a, device="cuda")
+    y = S.rsi_surrogate_ray_frame(d(pr), d(ref), sigma, 0, d(p)).cpu().numpy()
+    assert np.max(np.abs(y - y_ex)) <= 1e-5 * np.max(np.abs(y_ex))
+    yc = S.rsi_surrogate_ray_frame(d(pr), d(ref), sigma, 0, d(p), clip=5.0).cpu().numpy()
+    cap = np.where(np.abs(y_ex) > 5.0, 5.0 / np.abs(y_ex), 1.0)
+    assert np.max(np.abs(yc - y_ex * cap)) <= 1e-5 * 5.0
+    back = S.rsi_surrogate_ray_frame(d(pr), d(ref), sigma, 1, d(y.astype(np.complex64))).cpu().numpy()
+    assert np.max(np.abs(back - p)) <= 1e-5 * np.max(np.abs(p))

@@ -168,6 +168,50 @@ __device__ __forceinline__ void sum_range_f32(const TargetsF<KIND, TPL> &T,
     }
 }
 
+// Few field points: the 64 lanes of a wave take every 64th source of [j0, j1) for the
+// same field point (records by vector loads), each lane folds its blocks as above, and
+// the lane sums are combined by a fixed shuffle tree (bitwise repeatable).
+template <int KIND, bool PLANAR, bool FRACT>
+__device__ __forceinline__ void sum_lanes_f32(const TargetsF<KIND, 1> &T,
+                                              const SrcRecF *__restrict__ rec, int64_t j0,
+                                              int64_t j1, float ilam, float k, float &mre,
+                                              float &mim) {
+    const int lane = threadIdx.x & 63;
+    float cre = 0.0f, cim = 0.0f;
+    mre = mim = 0.0f;
+    for (int64_t jb = j0 + lane; jb < j1; jb += 64 * kSub) {
+        const int64_t je = (jb + 64 * kSub < j1) ? jb + 64 * kSub : j1;
+        AccF A[1];
+        A[0].r1 = A[0].i1 = A[0].r2 = A[0].i2 = 0.0f;
+        for (int64_t j = jb; j < je; j += 64) {
+            const SrcRecF s = rec[j];
+            pair_f32<KIND, 1, PLANAR, FRACT>(T, s, ilam, A);
+        }
+        float br = A[0].r1, bi = A[0].i1;
+        if constexpr (KIND == RSI_DIPOLE) {  // ik A1 - A2
+            br = fmaf(-k, A[0].i1, -A[0].r2);
+            bi = fmaf(k, A[0].r1, -A[0].i2);
+        }
+        float y = br - cre;
+        float t = mre + y;
+        cre = (t - mre) - y;
+        mre = t;
+        y = bi - cim;
+        t = mim + y;
+        cim = (t - mim) - y;
+        mim = t;
+    }
+    if constexpr (KIND == RSI_DIPOLE && PLANAR) {
+        mre *= T.ht[0];
+        mim *= T.ht[0];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mre += __shfl_xor(mre, off);
+        mim += __shfl_xor(mim, off);
+    }
+}
+
 // FP64: sources [j0, j1) against one target, same operations as the definition.
 template <int KIND>
 __device__ __forceinline__ void sum_range_f64(double px, double py, double pz,

@@ -157,6 +157,7 @@ struct Targets {
 struct PairShape {
     int tpl = 2;          // targets per lane (1, 2 or 4)
     int64_t chunk = 0;    // sources per split (0: all)
+    bool few = false;     // FP32: one wave per (field point, split), sources across its lanes
 };
 
 // --- rsi_pairsum.hip ---------------------------------------------------------
@@ -178,7 +179,12 @@ rsi_status prep_sources_f64(const rsi_points &pts, const double *w, const double
                             double v0, Cplx F, SrcSetD &set, hipStream_t s);
 rsi_status set_strength_f64(SrcSetD &set, const double *w, const double *field,
                             const double *tco, Cplx F, hipStream_t s);
-PairShape default_shape(int64_t n_src, int64_t n_tgt);
+// Waves a few-field-point launch aims for (64 per CU).  default_shape switches to it when
+// the launch with one field point per lane would have fewer than `few_below` waves: the
+// RSI pair sum (short pairs, scalar records) from below 8 waves per CU, the ray model
+// (long, divergent pairs) from below 32.
+constexpr int64_t kFewWaves = 16384;
+PairShape default_shape(int64_t n_src, int64_t n_tgt, int64_t few_below = kFewWaves / 8);
 int64_t partial_slots(const PairShape &sh, int64_t n_src, int64_t n_tgt);
 // planar_z: every source lies on the plane z = const through the set's anchor (normal
 // +z); the kernel then drops the z terms (interface samples, by the ABI contract).

@@ -284,6 +284,30 @@ __global__ void __launch_bounds__(kBlock) pairsum_f32_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// FP32 pair-sum kernel for few field points: grid (field points, source splits) of one
+// wave each; the wave's lanes share the field point and split its sources.
+// ---------------------------------------------------------------------------
+template <int KIND, bool PLANAR>
+__global__ void __launch_bounds__(64) pairsum_f32_few_kernel(
+    const SrcRecF *__restrict__ rec, int64_t n_src, int64_t chunk,
+    const double *__restrict__ tx, const double *__restrict__ ty, const double *__restrict__ tz,
+    int64_t n_tgt, const double *__restrict__ anchor, double inv_lam, float k, double nx,
+    double ny, double nz, float2 *__restrict__ out) {
+    TargetsF<KIND, 1> T;
+    const int64_t i = blockIdx.x;
+    setup_targets_f32<KIND, 1>(T, tx, ty, tz, n_tgt, i, anchor[0], anchor[1], anchor[2], inv_lam,
+                               nx, ny, nz);
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = (j0 + chunk < n_src) ? j0 + chunk : n_src;
+    float mre, mim;
+    if (phase_in_sin_range(anchor[3], inv_lam))
+        sum_lanes_f32<KIND, PLANAR, false>(T, rec, j0, j1, (float)inv_lam, k, mre, mim);
+    else
+        sum_lanes_f32<KIND, PLANAR, true>(T, rec, j0, j1, (float)inv_lam, k, mre, mim);
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.y * n_tgt + i] = make_float2(mre, mim);
+}
+
+// ---------------------------------------------------------------------------
 // FP64 pair-sum kernel (one target per lane).
 // ---------------------------------------------------------------------------
 template <int KIND>
@@ -344,7 +368,7 @@ static int env_int(const char *name, int dflt) {
     return (end && *end == 0 && x > 0 && x < (1L << 30)) ? (int)x : dflt;
 }
 
-PairShape default_shape(int64_t n_src, int64_t n_tgt) {
+PairShape default_shape(int64_t n_src, int64_t n_tgt, int64_t few_below) {
     static const int tpl_env = env_int("RSI_PAIRSUM_TPL", 1);
     static const int min_wg = env_int("RSI_PAIRSUM_MIN_WG", 32768);
     PairShape sh;
@@ -359,6 +383,24 @@ PairShape default_shape(int64_t n_src, int64_t n_tgt) {
     int64_t chunk = (n_src + splits - 1) / splits;
     chunk = (chunk + kSub - 1) / kSub * kSub;
     sh.chunk = chunk > 0 ? chunk : kSub;
+    // too few field points to fill the CUs one point per lane: one wave per (point, split)
+    // instead, about 64 waves per CU with >= 4 sources per lane (RSI_PAIRSUM_FEW = 0 or 1
+    // forces either launch, for tuning and tests)
+    bool few = 4 * bx * splits < few_below;
+    if (const char *e = std::getenv("RSI_PAIRSUM_FEW"))
+        if ((e[0] == '0' || e[0] == '1') && e[1] == 0) few = e[0] == '1';
+    if (few && n_tgt > 0) {
+        int64_t fs = (kFewWaves + n_tgt - 1) / n_tgt;
+        const int64_t fmax = (n_src + 255) / 256;
+        if (fs > fmax) fs = fmax;
+        if (fs < 1) fs = 1;
+        if (fs > 65535) fs = 65535;
+        int64_t fc = (n_src + fs - 1) / fs;
+        fc = (fc + kSub - 1) / kSub * kSub;
+        sh.chunk = fc > 0 ? fc : kSub;
+        sh.tpl = 1;
+        sh.few = true;
+    }
     return sh;
 }
 
@@ -371,6 +413,18 @@ static int64_t n_splits(const PairShape &sh, int64_t n_src) {
 int64_t partial_slots(const PairShape &sh, int64_t n_src, int64_t n_tgt) {
     const int64_t ns = n_splits(sh, n_src);
     return ns > 1 ? ns * n_tgt : 0;
+}
+
+template <int KIND>
+static void launch_f32_few(dim3 grid, hipStream_t s, const SrcSetF &set, int64_t chunk,
+                           const Targets &t, double inv_lam, float k, double nx, double ny,
+                           double nz, bool planar, float2 *dst) {
+    if (planar)
+        hipLaunchKernelGGL((pairsum_f32_few_kernel<KIND, true>), grid, dim3(64), 0, s, set.rec, set.n,
+                           chunk, t.x, t.y, t.z, t.n, set.anchor, inv_lam, k, nx, ny, nz, dst);
+    else
+        hipLaunchKernelGGL((pairsum_f32_few_kernel<KIND, false>), grid, dim3(64), 0, s, set.rec, set.n,
+                           chunk, t.x, t.y, t.z, t.n, set.anchor, inv_lam, k, nx, ny, nz, dst);
 }
 
 template <int KIND, int TPL>
@@ -400,14 +454,17 @@ rsi_status pairsum_f32(const SrcSetF &set, const Targets &t, rsi_kernel kind,
     const int64_t chunk = sh.chunk > 0 ? sh.chunk : set.n;
     const int64_t ns = n_splits(sh, set.n);
     if (ns > 65535) return RSI_ERR_SIZE;
-    const int64_t bx = (t.n + (int64_t)kBlock * tpl - 1) / ((int64_t)kBlock * tpl);
+    const int64_t bx = sh.few ? t.n : (t.n + (int64_t)kBlock * tpl - 1) / ((int64_t)kBlock * tpl);
     if (bx > 0x7fffffff) return RSI_ERR_SIZE;
     const dim3 grid((unsigned)bx, (unsigned)ns);
     float2 *dst = ns > 1 ? partial : out;
     if (ns > 1 && !partial) return RSI_ERR_WORKSPACE;
     const double inv_lam = freq / c;
     const float k = (float)(kTwoPi * freq / c);
-    if (kind == RSI_MONOPOLE) {
+    if (sh.few) {
+        if (kind == RSI_MONOPOLE) launch_f32_few<RSI_MONOPOLE>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);
+        else launch_f32_few<RSI_DIPOLE>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);
+    } else if (kind == RSI_MONOPOLE) {
         if (tpl == 1) launch_f32<RSI_MONOPOLE, 1>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);
         else if (tpl == 2) launch_f32<RSI_MONOPOLE, 2>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);
         else launch_f32<RSI_MONOPOLE, 4>(grid, s, set, chunk, t, inv_lam, k, nx, ny, nz, planar_z, dst);

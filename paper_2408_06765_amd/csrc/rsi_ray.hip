@@ -55,7 +55,6 @@ constexpr int kRayMaxL = kRayMaxIf + 1;    // layers
 constexpr int kRayFB = 8;                  // frequencies per launch
 constexpr int kRaySub = 64;                // sources per FP32 block before the fold
 constexpr int kRayMaxIt = 12;              // FP32 Newton evaluations per pair (bound)
-constexpr int64_t kRayFewWaves = 16384;    // waves the few-point launch aims for
 
 // One transducer sample of the FP32 path (read with wave-uniform scalar loads).
 struct alignas(32) RayRecF {
@@ -767,13 +766,13 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
         RSI_HIP(hipGetLastError());
         return RSI_OK;
     }
-    const PairShape sh = default_shape(n_src, tgt->n);
-    const int64_t nslots = partial_slots(sh, n_src, tgt->n);
     double *partials = nullptr;
     RSI_TRY(scratch.alloc(&partials, kBBoxBlocks * 6));
     RSI_TRY(bbox_partials(xd->pts, partials, s));
     if (n_if == 0) {
-        // one medium: eq. (12) is eq. (3), the monopole pair sum
+        // one medium: eq. (12) is eq. (3), the monopole pair sum (with its own shape rule)
+        const PairShape sh = default_shape(n_src, tgt->n);
+        const int64_t nslots = partial_slots(sh, n_src, tgt->n);
         const double c0 = media[0].c;
         if (prec == RSI_FP32) {
             SrcSetF set;
@@ -798,24 +797,15 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
                                 static_cast<double2 *>(out) + (int64_t)q * tgt->n, s));
         return RSI_OK;
     }
+    const PairShape sh = default_shape(n_src, tgt->n, kFewWaves / 2);
     const RayStack st = make_stack(zif, n_if, media);
     const int L = n_if + 1;
-    // FP32 with too few field points to fill the chip one per lane (fewer than 32 waves per
-    // CU): one wave per (point, source range) instead, sized to put about 64 waves on
-    // every CU with at least 4 samples per lane
-    int64_t chunk = sh.chunk > 0 ? sh.chunk : n_src;
-    const int64_t waves_std = 4 * ((tgt->n + kBlock - 1) / kBlock) * ((n_src + chunk - 1) / chunk);
-    bool few = prec == RSI_FP32 && waves_std < kRayFewWaves / 2;
+    // FP32 with too few field points to give every CU 32 waves one per lane: one wave per
+    // (point, source range) instead (PairShape::few)
+    const int64_t chunk = sh.chunk > 0 ? sh.chunk : n_src;
+    bool few = prec == RSI_FP32 && sh.few;
     if (const char *e = std::getenv("RSI_RAY_FEW"))  // tuning/testing override: 0 or 1
         if (prec == RSI_FP32 && (e[0] == '0' || e[0] == '1') && e[1] == 0) few = e[0] == '1';
-    if (few) {
-        int64_t splits = (kRayFewWaves + tgt->n - 1) / tgt->n;
-        const int64_t max_splits = (n_src + 255) / 256;
-        splits = splits < max_splits ? splits : max_splits;
-        splits = splits < 1 ? 1 : splits;
-        chunk = (n_src + splits - 1) / splits;
-        chunk = (chunk + 63) / 64 * 64;
-    }
     const int64_t ns = (n_src + chunk - 1) / chunk;
     if (ns > 65535) return RSI_ERR_SIZE;
     const int64_t bx = few ? tgt->n : (tgt->n + kBlock - 1) / kBlock;

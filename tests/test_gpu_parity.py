@@ -121,10 +121,18 @@ def _case(seed, ns, nt, kind):
     return src, w, s, tgt
 
 
+@pytest.mark.parametrize("launch", ["auto", "0", "1"])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("kind", [0, 1, 2])
 @pytest.mark.parametrize("ns,nt", SIZES)
-def test_propagate_matches_reference(gpu, orc, kind, prec, ns, nt):
+def test_propagate_matches_reference(gpu, orc, kind, prec, ns, nt, launch, monkeypatch):
+    """Pair sums of every kind and precision; launch forces the FP32 launch with one field
+    point per lane ("0") or one wave per field point ("1"), which these sizes would
+    otherwise choose ("auto")."""
+    if launch != "auto":
+        if prec == 1:
+            pytest.skip("the launch choice is an FP32 matter")
+        monkeypatch.setenv("RSI_PAIRSUM_FEW", launch)
     src, w, s, tgt = _case(11 + ns, ns, nt, kind)
     c, f = (5900.0, 5.0e6) if kind == 1 else (1480.0, 5.0e6)
     ref = orc.propagate(kind, src, w, s, tgt, c, f, normal=(0.0, 0.0, 1.0))
@@ -133,10 +141,13 @@ def test_propagate_matches_reference(gpu, orc, kind, prec, ns, nt):
     assert rel(got, ref) <= TOL[prec], (kind, prec, ns, nt, rel(got, ref))
 
 
+@pytest.mark.parametrize("launch", ["0", "1"])
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("ns,nt", [(5, 3), (70001, 613)])
-def test_propagate_planar_flag(gpu, orc, kind, ns, nt):
-    """RSI_FLAG_PLANAR_Z (sources on one z plane): the reduced FP32 kernel keeps parity."""
+def test_propagate_planar_flag(gpu, orc, kind, ns, nt, launch, monkeypatch):
+    """RSI_FLAG_PLANAR_Z (sources on one z plane): the reduced FP32 kernel keeps parity, in
+    both FP32 launches."""
+    monkeypatch.setenv("RSI_PAIRSUM_FEW", launch)
     src, w, s, tgt = _case(31 + ns, ns, nt, 1)
     src = (src[0], src[1], np.full(ns, 0.0123))
     tgt = (tgt[0], tgt[1], tgt[2] + 0.0123)

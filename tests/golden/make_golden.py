@@ -6,6 +6,7 @@ a seeded subset of the image points.
 
     python tests/golden/make_golden.py one_interface      # ~1.7e10 pairs
     python tests/golden/make_golden.py layered_stack      # two frequencies, ~3e11 pairs
+    python tests/golden/make_golden.py focused_normal     # ~1e10 pairs
 """
 import json
 import os
@@ -64,9 +65,31 @@ def layered_stack(n_samples=128, freqs=(1.0e6, 10.0e6)):
     }
 
 
+def focused_normal(n_samples=64):
+    """Focused transducer over water/steel (Sec. 3.3): cap and interface with 10^5 Halton
+    samples each, the 401 x 401 slice sampled, global transmission coefficient."""
+    cfg = W.FocusedNormal()
+    xd = oracle.sample_cap(cfg.xd_seed, cfg.n_xd, cfg.radius, cfg.curvature, (0.0, 0.0, 0.0), 0.0,
+                           seq=oracle.SEQ_HALTON)
+    q = oracle.sample_square(cfg.if_seed, cfg.n_if, 0.0, 0.0, cfg.water_path, cfg.half_width,
+                             seq=oracle.SEQ_HALTON)
+    tx, ty, tz = cfg.grid()
+    rng = np.random.default_rng(2026)
+    idx = np.sort(rng.choice(tx.size, n_samples, replace=False))
+    t0 = time.time()
+    phi = oracle.chain(xd, 1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), [q], [cfg.water_path],
+                       [m[0] for m in cfg.media], [m[1] for m in cfg.media],
+                       (tx[idx], ty[idx], tz[idx]), [cfg.freq], oracle.T_GLOBAL)[0]
+    return {
+        "workload": "focused_normal", "seconds": time.time() - t0,
+        "index": idx.tolist(), "re": phi.real.tolist(), "im": phi.imag.tolist(),
+    }
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "one_interface"
-    res = {"one_interface": one_interface, "layered_stack": layered_stack}[which]()
+    res = {"one_interface": one_interface, "layered_stack": layered_stack,
+           "focused_normal": focused_normal}[which]()
     path = os.path.join(HERE, f"{which}_samples.json")
     with open(path, "w") as f:
         json.dump(res, f)

@@ -127,3 +127,59 @@ def test_scan_batch_full_size_plan(gpu, orc):
     print(f"scan_batch worst instance rel-L2 {worst:.3e}")
     assert worst <= 1e-4
     plan.destroy()
+
+
+def test_focused_normal_full_size_fp32(gpu):
+    """Focused transducer (Sec. 3.3) at the benchmark's size: 10^5 Halton samples on the cap
+    and on the interface, the 401 x 401 slice (chain plan, FP32, global T), against stored
+    reference samples."""
+    import torch
+    g = golden("focused_normal")
+    cfg = W.FocusedNormal()
+    xs = gpu.rsi_sample_cap(cfg.xd_seed, cfg.n_xd, cfg.radius, cfg.curvature, (0.0, 0.0, 0.0), 0.0,
+                            seq=gpu.RSI_SEQ_HALTON)
+    q = gpu.rsi_sample_square(cfg.if_seed, cfg.n_if, 0.0, 0.0, cfg.water_path, cfg.half_width,
+                              seq=gpu.RSI_SEQ_HALTON)
+    T = gpu.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    I = [gpu.Interface(*q[:3], q[3], cfg.water_path)]
+    tgt = tuple(torch.as_tensor(a, device="cuda") for a in cfg.grid())
+    plan = gpu.Plan.chain(T, I, cfg.media, tgt, [cfg.freq], gpu.RSI_T_GLOBAL, gpu.RSI_FP32)
+    plan.execute()
+    torch.cuda.synchronize()
+    out = plan.out[0].cpu().numpy()
+    ref = np.array(g["re"]) + 1j * np.array(g["im"])
+    err = rel(out[np.array(g["index"])], ref)
+    print(f"focused_normal fp32 plan: rel-L2 {err:.3e} on {len(ref)} samples")
+    assert err <= 1e-4
+    plan.destroy()
+
+
+@pytest.mark.parametrize("stack", [1, 2])
+def test_ray_field_full_size_fp32(gpu, orc, stack):
+    """The ray model at the benchmark's sizes: 10^5 Halton samples of the tilted piston
+    through one plane onto the 401 x 401 slice (the ray_field configuration) and through
+    four planes onto 10^5 field points (the largest crossover row but one); 48 sampled
+    points against the reference computed here (one root per pair)."""
+    import torch
+    cfg = W.RayCrossover()
+    media = cfg.stacks[stack]
+    zs = cfg.planes(media)
+    xs = gpu.rsi_sample_disc(cfg.xd_seed, cfg.n_samples, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt,
+                             seq=gpu.RSI_SEQ_HALTON)
+    o = orc.sample_disc(cfg.xd_seed, cfg.n_samples, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt, seq=orc.SEQ_HALTON)
+    if stack == 1:
+        xc = cfg.patch_centres(media)[0]
+        X, Z = np.meshgrid(np.linspace(xc - 0.01, xc + 0.04, 401), zs[0] + np.linspace(0.001, 0.04, 401))
+        pts = (X.ravel(), 0 * X.ravel(), Z.ravel())
+    else:
+        pts = cfg.field(media, 100000)
+    T = gpu.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    tgt = tuple(torch.as_tensor(np.ascontiguousarray(a), device="cuda") for a in pts)
+    out = gpu.rsi_ray_field(T, zs, media, tgt, [cfg.freq], gpu.RSI_FP32)[0].cpu().numpy()
+    sel = np.sort(np.random.default_rng(9).choice(pts[0].size, 48, replace=False))
+    ref = orc.ray_field(o, 1.0, zs, [m[0] for m in media], [m[1] for m in media],
+                        tuple(a[sel] for a in pts), [cfg.freq])[0]
+    err = rel(out[sel], ref)
+    print(f"ray field ({len(zs)} planes) fp32 full size: rel-L2 {err:.3e} on 48 samples")
+    assert err <= 1e-4
+    assert np.all(np.isfinite(out))

@@ -247,7 +247,8 @@ rsi_status alloc_chain(const AllocFn &alloc, const rsi_transducer *xd, const rsi
     W.setd.assign(n_if + 1, SrcSetD{});
     int64_t nmax = 1, nslot = 0;
     auto slots = [&](int64_t ns, int64_t nt) {
-        const int64_t ps = partial_slots(default_shape(ns, nt), ns, nt);
+        const PairShape sh = default_shape(ns, nt, prec == RSI_FP32 ? kFewWaves / 8 : 0);
+        const int64_t ps = partial_slots(sh, ns, nt);
         if (ps > nslot) nslot = ps;
     };
     for (int m = 0; m <= n_if; ++m) {
@@ -375,7 +376,7 @@ rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, 
         // one pair sum of source set m (medium mm, kernel kind) onto t into dst
         auto psum = [&](int m, int mm, rsi_kernel kind, const Targets &t, void *dst) -> rsi_status {
             const rsi_points &sp = (m == 0) ? xd->pts : ifaces[m - 1].pts;
-            const PairShape sh = default_shape(sp.n, t.n);
+            const PairShape sh = default_shape(sp.n, t.n, fp32 ? kFewWaves / 8 : 0);
             if (fp32)
                 // interface samples lie on their plane (ABI contract): planar kernel
                 return pairsum_f32(W.setf[m], t, kind, m == 0 ? nullptr : nz, media[mm].c, freqs[f], sh,

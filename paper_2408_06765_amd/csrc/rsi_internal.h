@@ -182,7 +182,8 @@ rsi_status set_strength_f64(SrcSetD &set, const double *w, const double *field,
 // Waves a few-field-point launch aims for (64 per CU).  default_shape switches to it when
 // the launch with one field point per lane would have fewer than `few_below` waves: the
 // RSI pair sum (short pairs, scalar records) from below 8 waves per CU, the ray model
-// (long, divergent pairs) from below 32.
+// (long, divergent pairs) from below 32.  few_below = 0: never (the FP64 paths, which
+// have one launch only; their source splits then follow the one-point-per-lane rule).
 constexpr int64_t kFewWaves = 16384;
 PairShape default_shape(int64_t n_src, int64_t n_tgt, int64_t few_below = kFewWaves / 8);
 int64_t partial_slots(const PairShape &sh, int64_t n_src, int64_t n_tgt);

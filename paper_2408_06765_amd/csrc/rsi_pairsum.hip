@@ -389,6 +389,7 @@ PairShape default_shape(int64_t n_src, int64_t n_tgt, int64_t few_below) {
     bool few = 4 * bx * splits < few_below;
     if (const char *e = std::getenv("RSI_PAIRSUM_FEW"))
         if ((e[0] == '0' || e[0] == '1') && e[1] == 0) few = e[0] == '1';
+    if (few_below <= 0) few = false;
     if (few && n_tgt > 0) {
         int64_t fs = (kFewWaves + n_tgt - 1) / n_tgt;
         const int64_t fmax = (n_src + 255) / 256;
@@ -549,7 +550,7 @@ extern "C" rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_
     // RSI_OMNI = the monopole sum of strengths times ik
     const Cplx F = kind == RSI_OMNI ? Cplx{0.0, kTwoPi * freq / medium.c} : Cplx{1.0, 0.0};
     const rsi_kernel kk = kind == RSI_OMNI ? RSI_MONOPOLE : kind;
-    const PairShape sh = default_shape(src->n, tgt->n);
+    const PairShape sh = default_shape(src->n, tgt->n, prec == RSI_FP32 ? kFewWaves / 8 : 0);
     const int64_t nslots = partial_slots(sh, src->n, tgt->n);
     if (prec == RSI_FP32) {
         SrcSetF set;

@@ -59,7 +59,9 @@ constexpr int kRayMaxIt = 12;              // FP32 Newton evaluations per pair (
 // One transducer sample of the FP32 path (read with wave-uniform scalar loads).
 struct alignas(32) RayRecF {
     float ex, ey, ez, eh2;   // offset from the anchor; |horizontal offset|^2
-    float a, pad0, pad1, pad2;  // -(1/2pi) w_j v0 2 rho_0 (see ray_pair_f32)
+    float a;                 // -(1/2pi) w_j v0 2 rho_0 S_f (see ray_pair_f32)
+    float h0, hf0, hf0S2;    // h_0 = zif[0] - z_j (positive: samples below it have a = 0),
+                             // S_f h_0 and S_f h_0 S_0^2
 };
 // FP64 path: absolute position and folded strength.
 struct alignas(32) RayRecD {
@@ -75,9 +77,9 @@ struct RayStack {
     double rhod[kRayMaxL];   // densities
     double zif0, zlast;      // first and last plane
     double Smind;            // min_l S_l
-    float S2[kRayMaxL], h[kRayMaxL], hS2[kRayMaxL], rho[kRayMaxL], rho2[kRayMaxL];
-    float Cmax;              // largest FP32 slowness: S_l^2 - C^2 > 0 in FP32 for every l
-    float hCmax;             // Cmax / 2
+    float S2[kRayMaxL], h[kRayMaxL], hf[kRayMaxL], hfS2[kRayMaxL], rho[kRayMaxL], rho2[kRayMaxL];
+    float dS2[kRayMaxL];     // S_l^2 - S_f^2 >= 0, S_f the smallest slowness (fastest layer)
+    float Sf;                // S_f
 };
 struct RayFreqs {
     double f[kRayFB];
@@ -106,8 +108,8 @@ __device__ inline void ray_anchor(const double *__restrict__ partials, double &a
 __global__ void __launch_bounds__(256) ray_prep_f32_kernel(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ w, double v0, double zif0,
-    double rho0, const double *__restrict__ partials, double *__restrict__ anchor_out,
-    RayRecF *__restrict__ rec) {
+    double rho0, double S20, double Sf, const double *__restrict__ partials,
+    double *__restrict__ anchor_out, RayRecF *__restrict__ rec) {
     double ax, ay, az, radius;
     ray_anchor(partials, ax, ay, az, radius);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -125,8 +127,12 @@ __global__ void __launch_bounds__(256) ray_prep_f32_kernel(
     r.ey = ey;
     r.ez = ez;
     r.eh2 = (float)(dex * dex + dey * dey);
-    r.a = zif0 - z[j] > 0.0 ? (float)(-w[j] * v0 * 2.0 * rho0 / kTwoPi) : 0.0f;
-    r.pad0 = r.pad1 = r.pad2 = 0.0f;
+    const double h0 = zif0 - z[j];
+    const double hp = fmax(h0, 1e-12);  // a masked sample keeps the iteration finite
+    r.a = h0 > 0.0 ? (float)(-w[j] * v0 * 2.0 * rho0 * Sf / kTwoPi) : 0.0f;
+    r.h0 = (float)hp;
+    r.hf0 = (float)(hp * Sf);
+    r.hf0S2 = (float)(hp * Sf * S20);
     rec[j] = r;
 }
 
@@ -190,21 +196,26 @@ __device__ inline double ray_guess(double rho, double H, const RayStack &st) {
 }
 
 // Per-target constants of the FP32 path.
-// Start of the pair's Newton iteration: the pair's F at C_0 is exactly -R with
-// R = drho + e_z C_0 / eta_0^0 (the reference ray solves the reference equation), and its
-// derivatives at C_0 are the reference's with h_0 lowered by e_z.  Series reversion of
-// F(C_0 + delta) = 0 to third order:
+// The pair's iteration runs in v = tan(theta_f), theta_f the angle in the fastest layer
+// (slowness S_f), on F(v) = S_f v sum_l h_l q_l(v) - rho, q_l = (S_l^2 + (S_l^2 - S_f^2) v^2)^(-1/2).
+// Its start: the pair's F at the reference root v_0 is exactly -R with
+// R = drho + e_z tan(theta_0) (the reference ray solves the reference equation, and the
+// sample sits e_z deeper, shortening h_0 by e_z), and its derivatives at v_0 are the
+// reference's with h_0 lowered by e_z.  Series reversion of F(v_0 + delta) = 0 to third order:
 //   d = R / F1,  delta = d - a d^2 + (2 a^2 - b) d^3,  a = F2 / (2 F1),  b = F3 / (6 F1),
-// with 1/F1 = (1/F1_0)(1 + e_z g1 / F1_0), F2 = F2_0 - e_z g2 (g1, g2 the h_0-derivatives).
+// with 1/F1 = (1/F1_0)(1 + e_z g1 / F1_0), F2 = F2_0 - e_z g2 (g1, g2 the h_0-derivatives
+// of F1 and F2).
 template <int L, int NF>
 struct RayTgtF {
     float dmx, dmy;         // -2 (P - C_A) horizontal
     float rho0, rho02;      // reference horizontal distance, squared
-    float C0, c0e0;         // reference root, C_0 / eta_0^0
+    float C0, c0e0;         // reference root, C_0 / eta_0^0 (= tan(theta_0))
+    float v0;               // reference root in v
     float iF1, k1;          // 1/F1_0 and g1 / F1_0^2
     float F2h, g2h, b3;     // F2_0 / 2, g2 / 2, F3_0 / (6 F1_0)
-    float h00, hn, hnS2;    // h_0 of the anchor; h_n of the field point (> 0) and h_n S_n^2
+    float hn, hfn, hfnS2;   // h_n of the field point (> 0), S_f h_n and S_f h_n S_n^2
     float eta0[L];
+    float S2[L];            // S_l^2 (lane copies: the iteration's FMA takes one SGPR operand)
     float ph0[NF];          // frac(f_q t_0)
     bool valid;             // field point below the last plane
 };
@@ -228,39 +239,54 @@ __device__ __forceinline__ void ray_setup_f32(RayTgtF<L, NF> &T, double px, doub
     }
     const double C0 = ray_root_f64<L>(rho0, hc, st, ray_guess(rho0, H, st));
     // t_0 with the true extents: dt = t - t_0 holds for any C_0 and any h_0^0.  The
-    // derivatives of F for the start use the clamped extents (well posed).
-    const double C02 = C0 * C0;
-    double t0 = C0 * rho0, F1 = 0.0, F2 = 0.0, F3 = 0.0;
+    // derivatives of F for the start use the clamped extents (well posed).  In v:
+    // q_l(v_0) = sqrt(S_f^2 - C_0^2) / (S_f eta_l), and with p_l = h_l S_l^2 q_l^3,
+    //   F1 = S_f sum p_l,  F2 = -3 S_f v_0 sum p_l k_l,  F3 = -3 S_f sum p_l k_l (1 - 5 v_0^2 k_l),
+    // k_l = (S_l^2 - S_f^2) q_l^2.
+    const double C02 = C0 * C0, Sf = st.Smind, Sf2 = Sf * Sf;
+    const double cf = sqrt(Sf2 - C02), v0 = C0 / cf;
+    double t0 = C0 * rho0, F1 = 0.0, F2 = 0.0, F3 = 0.0, g1 = 0.0, g2 = 0.0;
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-        const double e2 = st.S2d[l] - C02;
-        const double eta = sqrt(e2);
-        const double ie2 = 1.0 / e2, ie3 = ie2 / eta;
+        const double eta = sqrt(st.S2d[l] - C02);
         T.eta0[l] = (float)eta;
         t0 += h[l] * eta;
-        const double u = hc[l] * st.S2d[l] * ie3;  // h S^2 / eta^3
-        F1 += u;
-        F2 += 3.0 * C0 * u * ie2;
-        F3 += 3.0 * u * ie2 * (1.0 + 5.0 * C02 * ie2);
+        const double ql = cf / (Sf * eta);
+        const double kl = (st.S2d[l] - Sf2) * ql * ql;
+        const double p1 = st.S2d[l] * ql * ql * ql;  // per unit extent
+        F1 += hc[l] * p1;
+        F2 += hc[l] * p1 * kl;
+        F3 += hc[l] * p1 * kl * (1.0 - 5.0 * v0 * v0 * kl);
+        if (l == 0) {
+            g1 = Sf * p1;
+            g2 = -3.0 * Sf * v0 * p1 * kl;
+        }
     }
-    const double e20 = st.S2d[0] - C02, eta00 = sqrt(e20);
-    const double g1 = st.S2d[0] / (eta00 * e20), g2 = 3.0 * C0 * g1 / e20;
+    F1 *= Sf;
+    F2 *= -3.0 * Sf * v0;
+    F3 *= -3.0 * Sf;
     const double iF1 = 1.0 / F1;
     T.dmx = (float)(-2.0 * dx);
     T.dmy = (float)(-2.0 * dy);
     T.rho0 = (float)rho0;
     T.rho02 = (float)(rho0 * rho0);
     T.C0 = (float)C0;
-    T.c0e0 = (float)(C0 / eta00);
+    T.c0e0 = (float)(C0 / T.eta0[0]);
+    T.v0 = (float)v0;
     T.iF1 = (float)iF1;
     T.k1 = (float)(g1 * iF1 * iF1);
     T.F2h = (float)(0.5 * F2);
     T.g2h = (float)(0.5 * g2);
     T.b3 = (float)(F3 * iF1 / 6.0);
-    T.h00 = (float)h[0];
     T.hn = (float)hc[L - 1];  // positive, so the pair's iteration stays well posed
-    T.hnS2 = (float)(hc[L - 1] * st.S2d[L - 1]);
+    T.hfn = (float)(hc[L - 1] * st.Smind);
+    T.hfnS2 = (float)(hc[L - 1] * st.Smind * st.S2d[L - 1]);
     T.valid = h[L - 1] > 0.0;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        T.S2[l] = st.S2[l];
+        asm volatile("" : "+v"(T.S2[l]));  // keep a lane copy: the FMA below takes one SGPR
+    }
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
         double p = t0 * fr.f[q];
@@ -281,48 +307,57 @@ __device__ __forceinline__ void ray_pair_f32(const RayTgtF<L, NF> &T, const Rec 
     const float r2 = fmaxf(T.rho02 + q, 0.0f);
     const float rho = __builtin_amdgcn_sqrtf(r2);
     const float drho = q * __builtin_amdgcn_rcpf(fmaxf(rho + T.rho0, FLT_MIN));
-    // extents and h S^2 per layer (a sample on or below the first plane has a = 0; its
-    // extent is kept positive so that the iteration stays finite)
-    float h[L], hS2[L];
-    h[0] = fmaxf(T.h00 - s.ez, 1e-12f);
-    hS2[0] = h[0] * st.S2[0];
+    // extents, and S_f h and S_f h S^2 per layer (the sample's own from its record)
+    float h[L], hf[L], hfS2[L];
+    h[0] = s.h0;
+    hf[0] = s.hf0;
+    hfS2[0] = s.hf0S2;
 #pragma unroll
     for (int l = 1; l < L - 1; ++l) {
         h[l] = st.h[l];
-        hS2[l] = st.hS2[l];
+        hf[l] = st.hf[l];
+        hfS2[l] = st.hfS2[l];
     }
     h[L - 1] = T.hn;
-    hS2[L - 1] = T.hnS2;
-    // start: third-order series reversion about the reference root
+    hf[L - 1] = T.hfn;
+    hfS2[L - 1] = T.hfnS2;
+    // start: third-order series reversion about the reference root (in v)
     const float R = fmaf(s.ez, T.c0e0, drho);
     const float iF1 = fmaf(s.ez, T.k1, T.iF1);
     const float d = R * iF1;
     const float a = fmaf(-s.ez, T.g2h, T.F2h) * iF1;
     const float u = fmaf(a + a, a, -T.b3);
-    float C = fmaf(d, fmaf(fmaf(u, d, -a), d, 1.0f), T.C0);
-    C = __builtin_amdgcn_fmed3f(C, 0.0f, st.Cmax);
-    // Newton on F(C) = C S1 - rho, F' = S3, until |F| is within a few units of its FP32
-    // rounding (the phase is stationary in C; the amplitude moves by ~1e-6 relative)
+    float v = fmaxf(fmaf(d, fmaf(fmaf(u, d, -a), d, 1.0f), T.v0), 0.0f);
+    // Newton in v: every layer's tan(theta_l) = S_f v q_l, so
+    //   F(v) = v Q1 - rho,  Q1 = S_f sum h_l q_l,   F'(v) = Q3,  Q3 = S_f sum h_l S_l^2 q_l^3,
+    // the fastest layer's term is linear (no pole at grazing), nothing cancels, and F is
+    // concave and increasing on [0, inf) with F(0) = -rho <= 0: a step from the right lands
+    // at or left of the root (clamped at 0), steps from the left rise monotonically.
+    // Iterate until |F| is within a few units of its FP32 rounding (the phase is stationary
+    // in the root; the amplitude moves by ~1e-6 relative).
     const float tolF = fmaf(4e-6f, rho, 1e-9f);
-    float e2[L], r[L], S1, S3;
+    float e2[L], qs[L], Q1, Q3;
     for (int it = 0;; ++it) {
-        S1 = 0.0f;
-        S3 = 0.0f;
+        const float vv = v * v;
+        Q1 = 0.0f;
+        Q3 = 0.0f;
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-            e2[l] = fmaf(-C, C, st.S2[l]);
-            r[l] = __builtin_amdgcn_rsqf(e2[l]);  // 1 / eta_l
-            S1 = fmaf(h[l], r[l], S1);
-            S3 = fmaf(hS2[l] * r[l], r[l] * r[l], S3);
+            e2[l] = fmaf(st.dS2[l], vv, T.S2[l]);
+            qs[l] = __builtin_amdgcn_rsqf(e2[l]);
+            Q1 = fmaf(hf[l], qs[l], Q1);
+            Q3 = fmaf(hfS2[l] * qs[l], qs[l] * qs[l], Q3);
         }
-        const float F = fmaf(C, S1, -rho);
+        const float F = fmaf(v, Q1, -rho);
         if (fabsf(F) <= tolF || it == kRayMaxIt) break;
-        // Newton step, kept below C_max (steps from the left can overshoot the pole)
-        C = fminf(fmaf(-F, __builtin_amdgcn_rcpf(S3), C), fmaf(0.5f, C, st.hCmax));
+        v = fmaxf(fmaf(-F, __builtin_amdgcn_rcpf(Q3), v), 0.0f);
     }
+    // back to C and eta_l: with w = 1 + v^2, C = S_f v / sqrt(w), eta_l = sqrt(e2_l / w)
+    const float rw = __builtin_amdgcn_rsqf(fmaf(v, v, 1.0f));
+    const float C = st.Sf * v * rw;
     float eta[L];
 #pragma unroll
-    for (int l = 0; l < L; ++l) eta[l] = e2[l] * r[l];
+    for (int l = 0; l < L; ++l) eta[l] = e2[l] * qs[l] * rw;
     // sum_l h_l / (eta_l + eta_l^0)
     float hsum;
     if constexpr (L <= 5) {
@@ -343,8 +378,11 @@ __device__ __forceinline__ void ray_pair_f32(const RayTgtF<L, NF> &T, const Rec 
     const float dt = fmaf(C - T.C0, B, fmaf(T.C0, drho, -s.ez * T.eta0[0]));
     // T / A = prod(2 rho_l eta_l) / (eta_0 sqrt(S1 S3) prod(den_l)),
     // den_l = rho_{l+1} eta_l + rho_l eta_{l+1}; the first factor 2 rho_0 eta_0 / eta_0 is
-    // the constant 2 rho_0, folded into the sample's strength a
-    float num = s.a, den2 = S1 * S3;
+    // the constant 2 rho_0, folded into the sample's strength a.  S1 = sum h_l/eta_l =
+    // sqrt(w) Q1 / S_f and S3 = sum h_l S_l^2/eta_l^3 = w^(3/2) Q3 / S_f, so
+    // S1 S3 = w^2 Q1 Q3 / S_f^2 (the S_f is in a as well).
+    const float w = fmaf(v, v, 1.0f);
+    float num = s.a, den2 = (w * w) * (Q1 * Q3);
 #pragma unroll
     for (int l = 0; l < L - 1; ++l) {
         const float dn = fmaf(st.rho[l + 1], eta[l], st.rho[l] * eta[l + 1]);
@@ -710,23 +748,14 @@ RayStack make_stack(const double *zif, int n_if, const rsi_medium *media) {
     for (int l = 1; l < L - 1; ++l) {
         st.hd[l] = zif[l] - zif[l - 1];
         st.h[l] = (float)st.hd[l];
-        st.hS2[l] = (float)(st.hd[l] * st.S2d[l]);
+        st.hf[l] = (float)(st.hd[l] * Smin);
+        st.hfS2[l] = (float)(st.hd[l] * Smin * st.S2d[l]);
     }
     st.zif0 = zif[0];
     st.zlast = zif[n_if - 1];
     st.Smind = Smin;
-    // C_max: within 2^-20 of the fastest layer's slowness (rays closer to grazing than
-    // that carry an amplitude below ~1e-4 of a normal ray), and with S_l^2 - C^2 > 0 in
-    // FP32 for every layer, so the FP32 iteration needs no floor
-    float cm = (float)(Smin * (1.0 - 0x1p-20));
-    for (;;) {
-        bool ok = true;
-        for (int l = 0; l < L; ++l) ok = ok && std::fmaf(-cm, cm, st.S2[l]) > st.S2[l] * 0x1p-22f;
-        if (ok) break;
-        cm = std::nextafterf(cm, 0.0f);
-    }
-    st.Cmax = cm;
-    st.hCmax = 0.5f * cm;
+    for (int l = 0; l < L; ++l) st.dS2[l] = (float)(st.S2d[l] - Smin * Smin);
+    st.Sf = (float)Smin;
     return st;
 }
 
@@ -771,7 +800,7 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
     RSI_TRY(bbox_partials(xd->pts, partials, s));
     if (n_if == 0) {
         // one medium: eq. (12) is eq. (3), the monopole pair sum (with its own shape rule)
-        const PairShape sh = default_shape(n_src, tgt->n);
+        const PairShape sh = default_shape(n_src, tgt->n, prec == RSI_FP32 ? kFewWaves / 8 : 0);
         const int64_t nslots = partial_slots(sh, n_src, tgt->n);
         const double c0 = media[0].c;
         if (prec == RSI_FP32) {
@@ -797,7 +826,7 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
                                 static_cast<double2 *>(out) + (int64_t)q * tgt->n, s));
         return RSI_OK;
     }
-    const PairShape sh = default_shape(n_src, tgt->n, kFewWaves / 2);
+    const PairShape sh = default_shape(n_src, tgt->n, prec == RSI_FP32 ? kFewWaves / 2 : 0);
     const RayStack st = make_stack(zif, n_if, media);
     const int L = n_if + 1;
     // FP32 with too few field points to give every CU 32 waves one per lane: one wave per
@@ -821,7 +850,7 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
         if (ns > 1) RSI_TRY(scratch.alloc(&partial, (size_t)(ns * nfb_max * tgt->n)));
         hipLaunchKernelGGL(ray_prep_f32_kernel, dim3(blocks_of(n_src)), dim3(256), 0, s, n_src,
                            xd->pts.x, xd->pts.y, xd->pts.z, xd->w, xd->v0, zif[0], media[0].rho,
-                           partials, anchor, rec);
+                           st.S2d[0], st.Smind, partials, anchor, rec);
         RSI_HIP(hipGetLastError());
         for (int q0 = 0; q0 < n_freq; q0 += kRayFB) {
             const int nb = n_freq - q0 < kRayFB ? n_freq - q0 : kRayFB;

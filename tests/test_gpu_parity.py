@@ -504,3 +504,26 @@ def test_ray_field_both_fp32_launches(gpu, orc, nf, launch, monkeypatch):
     got = _ray_gpu(gpu, xd, zs, media, tgt, freqs, 0)
     for q in range(nf):
         assert rel(got[q], ref[q]) <= TOL[0], (q, rel(got[q], ref[q]))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ray_field_extreme_geometry(gpu, orc, prec):
+    """Edge cases of the root of eq. 14: field points 0.05-1 mm under the last plane far to
+    the side (rays within a few degrees of grazing in the fast layer), points straight
+    under samples (horizontal distance 0), a thin fast layer (aluminium, 0.5 mm) between
+    water and steel, and a near-normal point; FP32 and FP64 against the reference."""
+    rng = np.random.default_rng(21)
+    xd = orc.sample_disc(6, 3000, W.PISTON_RADIUS, (0.0, 0.0, 0.0), math.radians(5.0))
+    zs = [0.02, 0.0205]
+    media = (W.WATER, W.ALU_PAPER, W.STEEL_PAPER)
+    n = 400
+    depth = np.concatenate([rng.uniform(5e-5, 1e-3, n // 2), rng.uniform(1e-3, 0.02, n // 2)])
+    x = rng.uniform(-0.04, 0.04, n)
+    y = rng.uniform(-0.01, 0.01, n)
+    # straight under samples
+    x[:10], y[:10] = xd[0][:10], xd[1][:10]
+    tgt = (x, y, zs[-1] + depth)
+    ref = orc.ray_field(xd, 1.0, zs, [m[0] for m in media], [m[1] for m in media], tgt, [3.0e6])
+    got = _ray_gpu(gpu, xd, zs, media, tgt, [3.0e6], prec)
+    assert np.all(np.isfinite(got))
+    assert rel(got, ref) <= TOL[prec], rel(got, ref)

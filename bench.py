@@ -463,9 +463,10 @@ def ray_crossover(args):
             rows.append(row)
             print(f"planes {len(zs)} n_field {nf}: rsi {t_rsi:.3f} ms ray {t_ray:.3f} ms", file=sys.stderr,
                   flush=True)
-        # crossover: first interval where the ray time overtakes the RSI time (log-log)
+        # crossover: first interval where the ray time overtakes the RSI time (log-log);
+        # without a plane both calls run the same monopole pair sum, so there is none
         cross = None
-        for a, b in zip(rows[:-1], rows[1:]):
+        for a, b in zip(rows[:-1], rows[1:]) if zs else ():
             da, db = math.log(a["ray_ms"] / a["rsi_ms"]), math.log(b["ray_ms"] / b["rsi_ms"])
             if da < 0 <= db:
                 u = da / (da - db)

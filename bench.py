@@ -49,6 +49,10 @@ def parse():
                          "measurements printed in the same format")
     ap.add_argument("--autotune", action="store_true",
                     help="scan_batch: run the autotuner (writes the cache) before planning")
+    ap.add_argument("--sur-train-f-max", type=float, default=None,
+                    help="surrogate: highest training frequency (Hz; default the recipe's)")
+    ap.add_argument("--sur-train-tilt-max", type=float, default=None,
+                    help="surrogate: largest training tilt (degrees; default the recipe's)")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="layered_stack: FP32 vs FP64 rel-L2 per frequency on a volume subsample")
     return ap.parse_args()
@@ -522,6 +526,10 @@ def surrogate(args):
     from paper_2408_06765_amd import surrogate as S
 
     cfg = S.SurrogateConfig()
+    if args.sur_train_f_max is not None:
+        cfg.train_f_max = args.sur_train_f_max
+    if args.sur_train_tilt_max is not None:
+        cfg.train_tilt_max = math.radians(args.sur_train_tilt_max)
     sur = S.Surrogate(cfg)
     t0 = time.perf_counter()
     q, t = sur.dataset(S.training_configs(cfg, 5120, 3), points_per_config=1953)
@@ -573,6 +581,14 @@ def surrogate(args):
         for f, d, tl in S.cell_configs(cfg, 101):
             if f <= cfg.train_f_max and tl <= cfg.train_tilt_max:
                 carrier.append(S.rel_l2(sur.src.ray_pressure(f, d, tl), sur.src.rsi_pressure(f, d, tl)))
+    # the judge's own noise: RSI against RSI with both sample counts doubled, per cell (a
+    # cell whose RSI moves by more than the threshold cannot be matched by a smooth model)
+    judge = {}
+    for f, d, tl in S.cell_configs(cfg, 101):
+        judge[S.cell_of(cfg, f, d, tl)] = S.rel_l2(sur.src.rsi_pressure(f, d, tl, scale=2),
+                                                  sur.src.rsi_pressure(f, d, tl))
+    jn = np.array([judge[c] for c in sorted(judge)])
+    reach = [c for c in sorted(judge) if judge[c] <= cfg.threshold]
     rsi_s, routed_s, sur_s, net_s = t5 - t4, t4 - t3, t6 - t5, t7 - t6
     n_q = len(qc) * cfg.nx * cfg.nz
     thresholds = [1e-3, 1e-2, 1e-1, 0.3, 1.0]
@@ -583,7 +599,8 @@ def surrogate(args):
         "vs_baseline": None, "dtype": "bf16 (MFMA, FP32 accumulation)", "data": "synthetic",
         "config": {"workload": "surrogate: piston + water/5900 m/s interface, x, z, f 1-10 MHz, depth "
                                "30-70 mm, tilt 0-20 deg; 5 x 256 Fourier-feature MLP on the "
-                               + ("ray-model carrier (2^14 samples), trained on f <= 3.25 MHz, tilt <= 10 deg"
+                               + (f"ray-model carrier (2^14 samples), trained on f <= {cfg.train_f_max / 1e6:g} MHz, "
+                                  f"tilt <= {math.degrees(cfg.train_tilt_max):g} deg"
                                   if cfg.carrier == "ray" else "plane-wave carrier"),
                    "train_samples": 5120 * 1953, "queries": n_q},
         "data_generation_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2), "final_loss": loss,
@@ -598,6 +615,12 @@ def surrogate(args):
         "passing_configurations": len(pass_cfgs),
         "speedup_in_passing_cells": round(rsi_pass / sur_pass, 2) if pass_cfgs else None,
         "cells_passing_list": [int(c) for c in sorted(errs) if errs[c] <= cfg.threshold],
+        "rsi_self_change_when_doubled": {"min": float(jn.min()), "median": float(np.median(jn)),
+                                         "max": float(jn.max())},
+        "cells_where_rsi_is_within_threshold_of_itself": len(reach),
+        "of_those_passing": int(sum(1 for c in reach if errs[c] <= cfg.threshold)),
+        "rsi_self_change_per_cell": [float(judge[c]) for c in sorted(judge)],
+        "surrogate_residual_per_cell": [float(errs[c]) for c in sorted(errs)],
     }
     if carrier:
         cr = np.array(carrier)

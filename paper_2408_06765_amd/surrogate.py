@@ -320,11 +320,12 @@ class FieldSource:
         X, Z = np.meshgrid(np.linspace(*b.x_range, n), np.linspace(*b.z_below, n))
         return self.ray_pressure(f, depth, tilt, (X.ravel(), Z.ravel()))
 
-    def rsi_pressure(self, f: float, depth: float, tilt: float, xz=None) -> torch.Tensor:
-        """p = i omega rho2 phi at the grid points from the RSI chain (FP32)."""
+    def rsi_pressure(self, f: float, depth: float, tilt: float, xz=None, scale: int = 1) -> torch.Tensor:
+        """p = i omega rho2 phi at the grid points from the RSI chain (FP32); scale multiplies
+        both sample counts (the first scale x n points of the same sequences)."""
         cfg, b = self.cfg, self.cfg.box
-        xs = rsi.rsi_sample_disc(0, cfg.n_xd, b.radius, (0.0, 0.0, 0.0), tilt)
-        qs = rsi.rsi_sample_square(1, cfg.n_if, depth * math.tan(tilt), 0.0, depth, cfg.half_width)
+        xs = rsi.rsi_sample_disc(0, cfg.n_xd * scale, b.radius, (0.0, 0.0, 0.0), tilt)
+        qs = rsi.rsi_sample_square(1, cfg.n_if * scale, depth * math.tan(tilt), 0.0, depth, cfg.half_width)
         T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), (math.sin(tilt), 0.0, math.cos(tilt)))
         I = [rsi.Interface(*qs[:3], qs[3], depth)]
         tgt = self._targets(self.queries(f, depth, tilt, xz))

@@ -121,8 +121,11 @@ def _case(seed, ns, nt, kind):
     return src, w, s, tgt
 
 
-@pytest.mark.parametrize("launch", ["auto", "0", "1"])
-@pytest.mark.parametrize("prec", [0, 1])
+# (precision, launch): the FP64 path has one launch; FP32 also runs with each launch forced
+PREC_LAUNCH = [(0, "auto"), (0, "0"), (0, "1"), (1, "auto")]
+
+
+@pytest.mark.parametrize("prec,launch", PREC_LAUNCH)
 @pytest.mark.parametrize("kind", [0, 1, 2])
 @pytest.mark.parametrize("ns,nt", SIZES)
 def test_propagate_matches_reference(gpu, orc, kind, prec, ns, nt, launch, monkeypatch):
@@ -130,8 +133,6 @@ def test_propagate_matches_reference(gpu, orc, kind, prec, ns, nt, launch, monke
     point per lane ("0") or one wave per field point ("1"), which these sizes would
     otherwise choose ("auto")."""
     if launch != "auto":
-        if prec == 1:
-            pytest.skip("the launch choice is an FP32 matter")
         monkeypatch.setenv("RSI_PAIRSUM_FEW", launch)
     src, w, s, tgt = _case(11 + ns, ns, nt, kind)
     c, f = (5900.0, 5.0e6) if kind == 1 else (1480.0, 5.0e6)

@@ -46,7 +46,7 @@ typedef enum {
     RSI_ERR_SIZE = 3,        /* a count is negative or exceeds a documented limit   */
     RSI_ERR_DEVICE = 4,      /* a HIP runtime call failed (message via last_error) */
     RSI_ERR_WORKSPACE = 5,   /* workspace allocation failed                         */
-    RSI_ERR_NONFINITE = 6,   /* reserved: non-finite input detected                 */
+    RSI_ERR_NONFINITE = 6,   /* non-finite input (only with the finite check on)   */
     RSI_ERR_UNSUPPORTED = 7  /* the combination of options is not implemented       */
 } rsi_status;
 
@@ -100,6 +100,16 @@ const char *rsi_last_error(void);
 
 /* ABI version: (major << 16) | minor. */
 int rsi_version(void);
+
+/* Input check for debugging: with enable != 0 the pair-sum entry points (rsi_propagate,
+ * rsi_propagate_ex, rsi_chain, rsi_chain_ex, rsi_ray_field, rsi_propagate_batched and the
+ * plan constructors) scan their device inputs -- coordinates, weights, complex strengths,
+ * interface samples, field points -- and return RSI_ERR_NONFINITE, launching nothing, if
+ * any value is NaN or infinite.  The scan costs one pass over the inputs and a stream
+ * synchronisation, so it is off by default and must not be used on a stream under graph
+ * capture.  Setting the environment variable RSI_CHECK_FINITE=1 turns it on at load.
+ * Process-wide; returns the previous setting. */
+int rsi_set_check_finite(int enable);
 
 /* ------------------------------------------------------------------------------
  * a1. Sampling (Sec. 2.3, eqs. 16-18).

@@ -42,6 +42,7 @@ SIGNATURES = {
     "rsi_status_string": ([C.c_int], C.c_char_p),
     "rsi_last_error": ([], C.c_char_p),
     "rsi_version": ([], C.c_int),
+    "rsi_set_check_finite": ([C.c_int], C.c_int),
     "rsi_sobol2d": ([C.c_uint32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "rsi_sample_disc": ([C.c_uint32, C.c_int64, C.c_double, _dp, C.c_double, C.c_void_p,
                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),

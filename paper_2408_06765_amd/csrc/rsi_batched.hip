@@ -276,6 +276,18 @@ struct BatchBuffers {
     DeviceBuffer rec, partial, bbox, anchor;
 };
 
+// The device inputs of a batch, for check_finite.
+static std::vector<DevSpan> instance_inputs(const rsi_instance *inst, int n_inst) {
+    std::vector<DevSpan> in;
+    for (int i = 0; i < n_inst; ++i) {
+        add_points(in, inst[i].src);
+        in.push_back({inst[i].w, inst[i].src.n});
+        in.push_back({inst[i].vel, 2 * inst[i].src.n});
+        add_points(in, inst[i].tgt);
+    }
+    return in;
+}
+
 static rsi_status validate_instances(const rsi_instance *inst, int n_inst, rsi_precision prec) {
     if (n_inst < 0) return RSI_ERR_SIZE;
     if (n_inst > 0 && !inst) return RSI_ERR_NULL;
@@ -632,6 +644,7 @@ rsi_status rsi_plan_create_chain_ex(rsi_plan **plan, const rsi_transducer *xd,
     if (!plan) return RSI_ERR_NULL;
     *plan = nullptr;
     RSI_TRY(validate_chain(xd, ifaces, n_if, media, tgt, freqs, n_freq, tmode, prec, flags, out));
+    RSI_TRY(check_finite(nullptr, chain_inputs(xd, ifaces, n_if, tgt)));
     std::unique_ptr<rsi_plan> p(new rsi_plan);
     p->type = 0;
     auto alloc = [&](void **ptr, size_t bytes) -> rsi_status {
@@ -666,6 +679,7 @@ rsi_status rsi_plan_create_batched(rsi_plan **plan, const rsi_instance *inst, in
     if (!plan) return RSI_ERR_NULL;
     *plan = nullptr;
     RSI_TRY(validate_instances(inst, n_inst, prec));
+    RSI_TRY(check_finite(nullptr, instance_inputs(inst, n_inst)));
     std::unique_ptr<rsi_plan> p(new rsi_plan);
     p->type = 1;
     BatchShape sh = default_batch_shape(inst, n_inst);
@@ -700,6 +714,7 @@ rsi_status rsi_propagate_batched(const rsi_instance *inst, int n_inst, rsi_preci
                                  void *stream) {
     RSI_TRY(validate_instances(inst, n_inst, prec));
     if (n_inst == 0) return RSI_OK;
+    RSI_TRY(check_finite(as_stream(stream), instance_inputs(inst, n_inst)));
     BatchShape sh = default_batch_shape(inst, n_inst);
     (void)cache_lookup(workload_key(inst, n_inst, prec), sh);
     BatchTables T;

@@ -424,6 +424,19 @@ rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, 
 
 using namespace rsi;
 
+std::vector<DevSpan> rsi::chain_inputs(const rsi_transducer *xd, const rsi_interface *ifaces,
+                                       int n_if, const rsi_points *tgt) {
+    std::vector<DevSpan> in;
+    add_points(in, xd->pts);
+    in.push_back({xd->w, xd->pts.n});
+    for (int m = 0; m < n_if; ++m) {
+        add_points(in, ifaces[m].pts);
+        in.push_back({ifaces[m].w, ifaces[m].pts.n});
+    }
+    add_points(in, *tgt);
+    return in;
+}
+
 extern "C" {
 
 rsi_status rsi_transmission(rsi_tmode tmode, int m, const double *zif, const rsi_medium *media,
@@ -464,6 +477,7 @@ rsi_status rsi_chain_ex(const rsi_transducer *xd, const rsi_interface *ifaces, i
     RSI_TRY(validate_chain(xd, ifaces, n_if, media, tgt, freqs, n_freq, tmode, prec, flags, out));
     if (tgt->n == 0 || n_freq == 0) return RSI_OK;
     hipStream_t s = as_stream(stream);
+    RSI_TRY(check_finite(s, chain_inputs(xd, ifaces, n_if, tgt)));
     Scratch scratch(s);
     ChainWork W;
     RSI_TRY(alloc_chain([&](void **p, size_t bytes) { return scratch.alloc((char **)p, bytes); },

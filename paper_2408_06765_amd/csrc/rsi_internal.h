@@ -41,6 +41,20 @@ void set_last_error(const char *what, hipError_t e);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Debug check of device inputs (rsi_set_check_finite): RSI_ERR_NONFINITE if any of the
+// given arrays (device pointer, element count; null pointers and empty arrays skipped)
+// holds a NaN or an infinity; RSI_OK at once when the check is off.  Synchronises s.
+struct DevSpan {
+    const double *p;
+    int64_t n;
+};
+rsi_status check_finite(hipStream_t s, const std::vector<DevSpan> &arrays);
+inline void add_points(std::vector<DevSpan> &v, const rsi_points &p) {
+    v.push_back({p.x, p.n});
+    v.push_back({p.y, p.n});
+    v.push_back({p.z, p.n});
+}
+
 // Stream-ordered scratch allocations released together (hipFreeAsync) on scope exit.
 class Scratch {
 public:
@@ -234,6 +248,9 @@ rsi_status alloc_chain(const AllocFn &alloc, const rsi_transducer *xd,
                        const rsi_interface *ifaces, int n_if, const rsi_points *tgt,
                        const double *freqs, int n_freq, rsi_precision prec, uint32_t flags,
                        ChainWork &W);
+// The device inputs of a chain, for check_finite.
+std::vector<DevSpan> chain_inputs(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
+                                  const rsi_points *tgt);
 rsi_status enqueue_chain(const rsi_transducer *xd, const rsi_interface *ifaces, int n_if,
                          const rsi_medium *media, const rsi_points *tgt, const double *freqs,
                          int n_freq, rsi_tmode tmode, rsi_precision prec, void *out,

@@ -545,6 +545,14 @@ extern "C" rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_
         if (planar && (normal[0] != 0.0 || normal[1] != 0.0)) return RSI_ERR_ARG;
     }
     hipStream_t s = as_stream(stream);
+    {
+        std::vector<DevSpan> in;
+        add_points(in, *src);
+        in.push_back({src_w, src->n});
+        in.push_back({src_vel, 2 * src->n});
+        add_points(in, *tgt);
+        RSI_TRY(check_finite(s, in));
+    }
     Scratch scratch(s);
     const Targets t{tgt->x, tgt->y, tgt->z, tgt->n};
     // RSI_OMNI = the monopole sum of strengths times ik

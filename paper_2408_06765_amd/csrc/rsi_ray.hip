@@ -782,6 +782,13 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
     RSI_TRY(validate_ray(xd, zif, n_if, media, tgt, freqs, n_freq, prec, out));
     if (tgt->n == 0 || n_freq == 0) return RSI_OK;
     hipStream_t s = as_stream(stream);
+    {
+        std::vector<DevSpan> in;
+        add_points(in, xd->pts);
+        in.push_back({xd->w, xd->pts.n});
+        add_points(in, *tgt);
+        RSI_TRY(check_finite(s, in));
+    }
     Scratch scratch(s);
     const Targets t{tgt->x, tgt->y, tgt->z, tgt->n};
     const int64_t n_src = xd->pts.n, n_out = (int64_t)n_freq * tgt->n;

@@ -1,11 +1,12 @@
 // rsi_sampling.hip -- sample points on the radiating surfaces (Sec. 2.3, eqs. 16-18)
-// and the small ABI utilities (status strings, last error, version).
+// and the small ABI utilities (status strings, last error, version, the input check).
 //
 // The paper draws its QMC points from a Halton sequence; this library uses a
 // two-dimensional Sobol sequence with a hash-based nested uniform (Owen) scramble,
 // which keeps the (0, m, 2)-net property of every power-of-two prefix.  Each point is
 // computed from its index alone, so any range of points is one independent launch.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "rsi_internal.h"
@@ -13,6 +14,43 @@
 namespace rsi {
 
 static thread_local std::string g_last_error;
+static int g_check_finite = [] {
+    const char *e = std::getenv("RSI_CHECK_FINITE");
+    return (e && e[0] == '1' && e[1] == 0) ? 1 : 0;
+}();
+
+// Sets *flag when a value of a[0, n) is not finite (lanes that see one store 1).
+__global__ void __launch_bounds__(256) nonfinite_kernel(const double *__restrict__ a, int64_t n,
+                                                         int *__restrict__ flag) {
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        bad = bad || !isfinite(a[i]);
+    if (bad) flag[0] = 1;
+}
+
+__global__ void __launch_bounds__(64) clear_flag_kernel(int *__restrict__ flag) {
+    if (threadIdx.x == 0) flag[0] = 0;
+}
+
+rsi_status check_finite(hipStream_t s, const std::vector<DevSpan> &arrays) {
+    if (!__atomic_load_n(&g_check_finite, __ATOMIC_RELAXED)) return RSI_OK;
+    Scratch scratch(s);
+    int *flag = nullptr;
+    RSI_TRY(scratch.alloc(&flag, 1));
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(64), 0, s, flag);
+    RSI_HIP(hipGetLastError());
+    for (const DevSpan &a : arrays) {
+        if (!a.p || a.n <= 0) continue;
+        const int64_t blocks = (a.n + 255) / 256;
+        hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s,
+                           a.p, a.n, flag);
+        RSI_HIP(hipGetLastError());
+    }
+    int host = 0;
+    RSI_HIP(hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    RSI_HIP(hipStreamSynchronize(s));
+    return host ? RSI_ERR_NONFINITE : RSI_OK;
+}
 
 void set_last_error(const char *what, hipError_t e) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -214,7 +252,11 @@ const char *rsi_status_string(rsi_status s) {
 
 const char *rsi_last_error(void) { return g_last_error.c_str(); }
 
-int rsi_version(void) { return (1 << 16) | 1; }
+int rsi_version(void) { return (1 << 16) | 2; }
+
+int rsi_set_check_finite(int enable) {
+    return __atomic_exchange_n(&g_check_finite, enable ? 1 : 0, __ATOMIC_RELAXED);
+}
 
 rsi_status rsi_sobol2d(uint32_t seed, int64_t first, int64_t n, uint32_t *out, void *stream) {
     if (first < 0 || n < 0 || first + n > (int64_t(1) << 32)) return RSI_ERR_SIZE;

@@ -23,6 +23,12 @@ RSI_CHAIN_OMNI, RSI_CHAIN_ABOVE = 1, 2
 RSI_SEQ_SOBOL, RSI_SEQ_HALTON = 0, 1
 
 _OUT_DTYPE = {RSI_FP32: torch.complex64, RSI_FP64: torch.complex128}
+RSIError = L.RSIError
+
+
+def rsi_set_check_finite(enable: bool) -> bool:
+    """Turn the library's non-finite input check on or off; returns the previous setting."""
+    return bool(L.load().rsi_set_check_finite(1 if enable else 0))
 
 
 def _stream() -> C.c_void_p:

@@ -74,6 +74,19 @@ def test_status_strings_and_version():
     assert lib.rsi_version() >> 16 == 1
 
 
+def test_finite_check_toggle():
+    """rsi_set_check_finite returns the previous setting (host state only)."""
+    from paper_2408_06765_amd import _lib
+    lib = _lib.load()
+    prev = lib.rsi_set_check_finite(1)
+    try:
+        assert lib.rsi_set_check_finite(1) == 1
+        assert lib.rsi_set_check_finite(0) == 1
+        assert lib.rsi_set_check_finite(0) == 0
+    finally:
+        lib.rsi_set_check_finite(prev)
+
+
 def test_argument_errors_before_any_device_work():
     from paper_2408_06765_amd import _lib
     lib = _lib.load()

@@ -528,3 +528,61 @@ def test_ray_field_extreme_geometry(gpu, orc, prec):
     got = _ray_gpu(gpu, xd, zs, media, tgt, [3.0e6], prec)
     assert np.all(np.isfinite(got))
     assert rel(got, ref) <= TOL[prec], rel(got, ref)
+
+
+# ----------------------------------------------------------------------------- boundary
+def test_nonfinite_inputs_rejected_when_checked(gpu):
+    """With the finite check on, a NaN or an infinity in any device input of the pair-sum
+    entry points gives RSI_ERR_NONFINITE before anything launches; finite inputs pass.
+    (With the check off nothing is scanned: that path is every other test here.)"""
+    import torch
+    src, w, s, tgt = _case(5, 300, 70, 1)
+    xd = W.random_cloud(8, 200, (0.0, 0.0, 0.0), (0.005, 0.005, 0.0))
+    q = W.random_cloud(9, 300, (0.0, 0.0, 0.02), (0.02, 0.02, 0.0))
+    wx, wq = W.random_weights(10, 200, 1e-6), W.random_weights(11, 300, 1e-6)
+    media = [(1480.0, 1000.0), (5900.0, 7800.0)]
+    prev = gpu.rsi_set_check_finite(True)
+
+    def spoil(a, i, v):
+        b = np.array(a, copy=True)
+        b[i] = v
+        return b
+
+    def propagate(src_, w_, s_, tgt_):
+        return gpu.rsi_propagate(devpts(src_), dev(w_), dev(s_), devpts(tgt_), 5900.0, 5.0e6, 1, 0,
+                                 normal=(0.0, 0.0, 1.0))
+
+    def chain(xd_, q_, tgt_):
+        T = gpu.Transducer(*devpts(xd_[:3]), dev(wx), 1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+        I = [gpu.Interface(*devpts(q_[:3]), dev(wq), 0.02)]
+        return gpu.rsi_chain(T, I, media, devpts(tgt_), [2.0e6], 1, 0)
+
+    def ray(wx_, tgt_):
+        T = gpu.Transducer(*devpts(xd[:3]), dev(wx_), 1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+        return gpu.rsi_ray_field(T, [0.02], media, devpts(tgt_), [2.0e6], 0)
+
+    def batched(tgt_):
+        out = torch.empty(len(tgt_[0]), dtype=torch.complex64, device="cuda")
+        inst = gpu.Instance(devpts(src), dev(w), devpts(tgt_), 1480.0, 1.0e6, out=out)
+        gpu.rsi_propagate_batched([inst], 0)
+
+    tgt_below = (tgt[0], tgt[1], tgt[2] + 0.02)
+    try:
+        propagate(src, w, s, tgt)
+        chain(xd, q, tgt_below)
+        ray(wx, tgt_below)
+        batched(tgt)
+        bad_calls = [
+            lambda: propagate(src, w, s, (tgt[0], tgt[1], spoil(tgt[2], 7, np.nan))),
+            lambda: propagate((spoil(src[0], 0, np.inf), src[1], src[2]), w, s, tgt),
+            lambda: propagate(src, spoil(w, 299, -np.inf), s, tgt),
+            lambda: propagate(src, w, spoil(s, 3, complex(np.nan, 0.0)), tgt),
+            lambda: chain(xd, (q[0], spoil(q[1], 5, np.nan), q[2]), tgt_below),
+            lambda: ray(spoil(wx, 0, np.nan), tgt_below),
+            lambda: batched((tgt[0], spoil(tgt[1], 69, np.inf), tgt[2])),
+        ]
+        for k, call in enumerate(bad_calls):
+            with pytest.raises(gpu.RSIError, match="RSI_ERR_NONFINITE"):
+                call()
+    finally:
+        gpu.rsi_set_check_finite(prev)

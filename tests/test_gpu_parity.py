@@ -421,6 +421,45 @@ def test_chain_plan_replay(gpu, orc, prec):
     plan.destroy()
 
 
+def test_calls_on_two_streams_match_one_stream(gpu, orc):
+    """Calls are asynchronous on the caller's stream and independent across streams: a
+    pair sum, a chain plan and a ray field enqueued on two side streams at once give the
+    bits of the same calls run one after another on the default stream."""
+    import torch
+    cfg = W.LayeredStack()
+    src, w, s, tgt = _case(21, 5000, 3001, 1)
+    pargs = (devpts(src), dev(w), dev(s), devpts(tgt), 5900.0, 5.0e6, 1, 0)
+    xd, ifs, ctgt = _small_chain(orc, 1 << 11, cfg.z_if[:2], cfg.media[:3], cfg.tilt, 400)
+    T = gpu.Transducer(*devpts(xd[:3]), dev(xd[3]), 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    I = [gpu.Interface(*devpts(q[:3]), dev(q[3]), z) for q, z in zip(ifs, cfg.z_if[:2])]
+    ctg = devpts(ctgt)
+    rxd, zs, media, rtgt = _ray_case(orc, "one", 3000, 500)
+    RT = gpu.Transducer(*devpts(rxd[:3]), dev(rxd[3]), 1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    rtg = devpts(rtgt)
+    ref_p = host(gpu.rsi_propagate(*pargs, normal=(0.0, 0.0, 1.0)))
+    ref_c = host(gpu.rsi_chain(T, I, cfg.media[:3], ctg, [2e6, 3e6], 1, 0))
+    ref_r = host(gpu.rsi_ray_field(RT, zs, media, rtg, [2.5e6], 0))
+    plan = gpu.Plan.chain(T, I, cfg.media[:3], ctg, [2e6, 3e6], 1, 0)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for rep in range(3):
+        with torch.cuda.stream(s1):
+            p = gpu.rsi_propagate(*pargs, normal=(0.0, 0.0, 1.0))
+        with torch.cuda.stream(s2):
+            plan.execute()
+            c = plan.out.clone()
+        with torch.cuda.stream(s1):
+            r = gpu.rsi_ray_field(RT, zs, media, rtg, [2.5e6], 0)
+        outs.append((p, c, r))
+    torch.cuda.synchronize()
+    for p, c, r in outs:
+        assert np.array_equal(host(p).view(np.uint64), ref_p.view(np.uint64))
+        assert np.array_equal(host(c).view(np.uint64), ref_c.view(np.uint64))
+        assert np.array_equal(host(r).view(np.uint64), ref_r.view(np.uint64))
+    plan.destroy()
+
+
 # ----------------------------------------------------------------------------- ray tracing (Sec. 2.2)
 def _ray_case(orc, layout, n_xd, n_tgt, seed=0):
     tilt = math.radians(10.0)

@@ -401,6 +401,44 @@ def test_batched_plan_replay_bitwise(gpu):
     plan.destroy()
 
 
+def test_autotune_cache_and_corrupt_cache(gpu, orc, tmp_path, monkeypatch):
+    """The autotuner writes its choice to the cache file; a later call reads it (results
+    still match the reference); garbage appended to the file is skipped line by line (the
+    last valid entry still wins: same bits); a file of random bytes leaves the default
+    shape (results still match the reference)."""
+    import os
+    cache = tmp_path / "autotune.txt"
+    monkeypatch.setenv("RSI_AUTOTUNE_CACHE", str(cache))
+    insts, refs = _instances(gpu, 9, 0, seed=5)
+
+    def run_and_check():
+        for i in insts:
+            i.out.zero_()
+        gpu.rsi_propagate_batched(insts, 0)
+        outs = [host(i.out).copy() for i in insts]
+        for got, (kind, src, w, s, tgt, c, f) in zip(outs, refs):
+            if len(src[0]) == 0:
+                assert np.all(got == 0)
+            else:
+                assert rel(got, orc.propagate(kind, src, w, s, tgt, c, f, normal=(0, 0, 1))) <= TOL[0]
+        return outs
+
+    gpu.rsi_autotune_batched(insts, 0)
+    lines = [ln.split() for ln in cache.read_text().splitlines() if ln.strip()]
+    assert lines and all(len(ln) == 4 for ln in lines)
+    key, tpl, chunk = lines[-1][0], int(lines[-1][1]), int(lines[-1][2])
+    assert tpl in (1, 2, 4) and chunk in (4096, 16384, 65536)
+    tuned = run_and_check()
+    with open(cache, "ab") as fh:
+        fh.write(b"\x00\xff not a line of the cache\n" + f"{key} 3 4096 1.0\n".encode()
+                 + f"{key} 2 12\n".encode() + f"{key} 1 -5 2.0\n".encode() + b"truncated " + key.encode())
+    again = run_and_check()
+    for a, b in zip(again, tuned):
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    cache.write_bytes(os.urandom(4096))
+    run_and_check()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_chain_plan_replay(gpu, orc, prec):
     import torch

@@ -199,7 +199,12 @@ rsi_status set_strength_f64(SrcSetD &set, const double *w, const double *field,
 // (long, divergent pairs) from below 32.  few_below = 0: never (the FP64 paths, which
 // have one launch only; their source splits then follow the one-point-per-lane rule).
 constexpr int64_t kFewWaves = 16384;
-PairShape default_shape(int64_t n_src, int64_t n_tgt, int64_t few_below = kFewWaves / 8);
+// min_chunk: fewest sources per split (the RSI pair sum keeps 4096; the ray model, whose
+// pairs cost ~6x more, splits finer).
+PairShape default_shape(int64_t n_src, int64_t n_tgt, int64_t few_below = kFewWaves / 8,
+                        int64_t min_chunk = 4096);
+// Integer environment override (tuning knobs): the value if it parses as 1 .. 2^30 - 1.
+int env_int(const char *name, int dflt);
 int64_t partial_slots(const PairShape &sh, int64_t n_src, int64_t n_tgt);
 // planar_z: every source lies on the plane z = const through the set's anchor (normal
 // +z); the kernel then drops the z terms (interface samples, by the ABI contract).

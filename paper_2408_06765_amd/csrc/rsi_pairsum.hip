@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(256) zero_kernel(int64_t n, T2 *__restrict__ o
 
 // Optional overrides of the default launch shape, for tuning sweeps:
 // RSI_PAIRSUM_TPL (1, 2 or 4 targets per lane) and RSI_PAIRSUM_MIN_WG (workgroup goal).
-static int env_int(const char *name, int dflt) {
+int env_int(const char *name, int dflt) {
     const char *v = std::getenv(name);
     if (!v || !*v) return dflt;
     char *end = nullptr;
@@ -368,16 +368,17 @@ static int env_int(const char *name, int dflt) {
     return (end && *end == 0 && x > 0 && x < (1L << 30)) ? (int)x : dflt;
 }
 
-PairShape default_shape(int64_t n_src, int64_t n_tgt, int64_t few_below) {
+PairShape default_shape(int64_t n_src, int64_t n_tgt, int64_t few_below, int64_t min_chunk) {
     static const int tpl_env = env_int("RSI_PAIRSUM_TPL", 1);
     static const int min_wg = env_int("RSI_PAIRSUM_MIN_WG", 32768);
     PairShape sh;
     sh.tpl = (tpl_env == 2 || tpl_env == 4) ? tpl_env : 1;
     const int64_t bx = (n_tgt + kBlock * sh.tpl - 1) / (kBlock * sh.tpl);
     // aim for >= min_wg workgroups (128 per CU: small items balance the CUs at the end
-    // of the launch) while keeping >= 4096 sources per split
+    // of the launch) while keeping >= min_chunk sources per split
+    if (min_chunk < kSub) min_chunk = kSub;
     int64_t splits = (min_wg + bx - 1) / (bx > 0 ? bx : 1);
-    const int64_t max_splits = (n_src + 4095) / 4096;
+    const int64_t max_splits = (n_src + min_chunk - 1) / min_chunk;
     if (splits > max_splits) splits = max_splits;
     if (splits < 1) splits = 1;
     int64_t chunk = (n_src + splits - 1) / splits;

@@ -833,7 +833,10 @@ extern "C" rsi_status rsi_ray_field(const rsi_transducer *xd, const double *zif,
                                 static_cast<double2 *>(out) + (int64_t)q * tgt->n, s));
         return RSI_OK;
     }
-    const PairShape sh = default_shape(n_src, tgt->n, prec == RSI_FP32 ? kFewWaves / 2 : 0);
+    // ray pairs cost ~6x an RSI pair: splits of >= 1024 sources keep enough waves for the
+    // one-point-per-lane launch down to ~10^4 field points (measured best of 256 .. 4096)
+    static const int ray_min_chunk = env_int("RSI_RAY_MIN_CHUNK", 1024);
+    const PairShape sh = default_shape(n_src, tgt->n, prec == RSI_FP32 ? kFewWaves / 2 : 0, ray_min_chunk);
     const RayStack st = make_stack(zif, n_if, media);
     const int L = n_if + 1;
     // FP32 with too few field points to give every CU 32 waves one per lane: one wave per

@@ -316,9 +316,20 @@ class FieldSource:
 
     def ray_reference(self, f: float, depth: float, tilt: float) -> torch.Tensor:
         """The ray field on the fixed n_ref_side^2 grid that sets a configuration's scale."""
+        return self.ray_pressure(f, depth, tilt, self._ref_xz())
+
+    def _ref_xz(self):
         b, n = self.cfg.box, self.cfg.n_ref_side
         X, Z = np.meshgrid(np.linspace(*b.x_range, n), np.linspace(*b.z_below, n))
-        return self.ray_pressure(f, depth, tilt, (X.ravel(), Z.ravel()))
+        return X.ravel(), Z.ravel()
+
+    def ray_carrier(self, f: float, depth: float, tilt: float, xz=None):
+        """The ray field at the query points and on the reference grid, from one call
+        (the points are independent, so this is ray_pressure and ray_reference at once)."""
+        xg, zg = (self.xg, self.zg) if xz is None else xz
+        rx, rz = self._ref_xz()
+        p = self.ray_pressure(f, depth, tilt, (np.concatenate([xg, rx]), np.concatenate([zg, rz])))
+        return p[:xg.size], p[xg.size:]
 
     def rsi_pressure(self, f: float, depth: float, tilt: float, xz=None, scale: int = 1) -> torch.Tensor:
         """p = i omega rho2 phi at the grid points from the RSI chain (FP32); scale multiplies
@@ -361,8 +372,8 @@ class Surrogate:
             q = self.src.queries(f, d, t, xz)
             p = self.src.rsi_pressure(f, d, t, xz)
             if self.cfg.carrier == "ray":
-                env = rsi_surrogate_ray_frame(self.src.ray_pressure(f, d, t, xz), self.src.ray_reference(f, d, t),
-                                              self.cfg.sigma, 0, p, self.cfg.clip)
+                pr, ref = self.src.ray_carrier(f, d, t, xz)
+                env = rsi_surrogate_ray_frame(pr, ref, self.cfg.sigma, 0, p, self.cfg.clip)
             else:
                 env = rsi_surrogate_carrier(q, self.m1, self.m2, 0, p)
             qs.append(q)
@@ -408,8 +419,8 @@ class Surrogate:
         q = self.src.queries(f, depth, tilt, xz)
         y = self.network(q)
         if self.cfg.carrier == "ray":
-            return rsi_surrogate_ray_frame(self.src.ray_pressure(f, depth, tilt, xz),
-                                           self.src.ray_reference(f, depth, tilt), self.cfg.sigma, 1, y)
+            pr, ref = self.src.ray_carrier(f, depth, tilt, xz)
+            return rsi_surrogate_ray_frame(pr, ref, self.cfg.sigma, 1, y)
         return rsi_surrogate_carrier(q, self.m1, self.m2, 1, y)
 
     def validate(self, configs: np.ndarray) -> Dict[int, float]:

@@ -42,9 +42,12 @@ __global__ void __launch_bounds__(kBlock) multifreq_f32_kernel(
 #pragma unroll
     for (int q = 0; q < kFB; ++q) kq[q] = (float)(kTwoPi * (fb + q * df) * inv_c);
 
-    float mre[kFB], mim[kFB], cre[kFB], cim[kFB];
+    // running FP32 sums of the 64-source block sums, without compensation: the registers
+    // go to 16 frequencies per pair (one geometry and two transcendental phasors shared by
+    // all of them), which measured faster than 8 frequencies with a compensated sum
+    float mre[kFB], mim[kFB];
 #pragma unroll
-    for (int q = 0; q < kFB; ++q) mre[q] = mim[q] = cre[q] = cim[q] = 0.0f;
+    for (int q = 0; q < kFB; ++q) mre[q] = mim[q] = 0.0f;
     for (int64_t jb = 0; jb < n_src; jb += kSub) {
         const int64_t je = (jb + kSub < n_src) ? jb + kSub : n_src;
         float are[kFB], aim[kFB];
@@ -95,14 +98,8 @@ __global__ void __launch_bounds__(kBlock) multifreq_f32_kernel(
         }
 #pragma unroll
         for (int q = 0; q < kFB; ++q) {
-            float y = are[q] - cre[q];
-            float t = mre[q] + y;
-            cre[q] = (t - mre[q]) - y;
-            mre[q] = t;
-            y = aim[q] - cim[q];
-            t = mim[q] + y;
-            cim[q] = (t - mim[q]) - y;
-            mim[q] = t;
+            mre[q] += are[q];
+            mim[q] += aim[q];
         }
     }
     if (!valid) return;

@@ -53,6 +53,8 @@ def parse():
                     help="surrogate: highest training frequency (Hz; default the recipe's)")
     ap.add_argument("--sur-train-tilt-max", type=float, default=None,
                     help="surrogate: largest training tilt (degrees; default the recipe's)")
+    ap.add_argument("--sur-carrier-samples", type=int, default=None,
+                    help="surrogate: transducer samples of the ray-model carrier (default the recipe's)")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="layered_stack: FP32 vs FP64 rel-L2 per frequency on a volume subsample")
     return ap.parse_args()
@@ -561,6 +563,8 @@ def surrogate(args):
         cfg.train_f_max = args.sur_train_f_max
     if args.sur_train_tilt_max is not None:
         cfg.train_tilt_max = math.radians(args.sur_train_tilt_max)
+    if args.sur_carrier_samples is not None:
+        cfg.n_carrier = args.sur_carrier_samples
     sur = S.Surrogate(cfg)
     t0 = time.perf_counter()
     q, t = sur.dataset(S.training_configs(cfg, 5120, 3), points_per_config=1953)
@@ -630,7 +634,7 @@ def surrogate(args):
         "vs_baseline": None, "dtype": "bf16 (MFMA, FP32 accumulation)", "data": "synthetic",
         "config": {"workload": "surrogate: piston + water/5900 m/s interface, x, z, f 1-10 MHz, depth "
                                "30-70 mm, tilt 0-20 deg; 5 x 256 Fourier-feature MLP on the "
-                               + (f"ray-model carrier (2^14 samples), trained on f <= {cfg.train_f_max / 1e6:g} MHz, "
+                               + (f"ray-model carrier ({cfg.n_carrier} samples), trained on f <= {cfg.train_f_max / 1e6:g} MHz, "
                                   f"tilt <= {math.degrees(cfg.train_tilt_max):g} deg"
                                   if cfg.carrier == "ray" else "plane-wave carrier"),
                    "train_samples": 5120 * 1953, "queries": n_q},

@@ -203,7 +203,7 @@ class SurrogateConfig:
     threshold: float = 1e-3
     seed: int = 0
     carrier: str = "ray"          # "ray" (rsi_ray_field) or "plane" (refracted plane wave)
-    n_carrier: int = 1 << 14      # transducer samples of the ray carrier
+    n_carrier: int = 1 << 13      # transducer samples of the ray carrier (2^12: one cell fewer)
     sigma: float = 0.02           # expected departure of RSI from the ray model (frame scale)
     clip: float = 5.0             # cap on training targets in that frame
     n_ref_side: int = 16          # ref grid of the frame's scale: n_ref_side^2 points

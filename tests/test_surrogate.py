@@ -82,7 +82,7 @@ def test_routing_infinite_threshold_is_the_network(small):
 
 def test_network_is_faster_than_rsi_on_a_million_queries(small):
     """10^6 query points (64 configurations x 125^2): the network alone, and the whole
-    surrogate answer (ray carrier with 2^14 samples + network + frame), against the RSI
+    surrogate answer (ray carrier with the recipe's samples + network + frame), against the RSI
     chain (2^16 piston and 2^18 interface samples per configuration)."""
     import torch
     S, cfg, sur = small
@@ -97,8 +97,8 @@ def test_network_is_faster_than_rsi_on_a_million_queries(small):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for (f, d, t), q in zip(qc, qs):
-        S.rsi_surrogate_ray_frame(full.ray_pressure(f, d, t), full.ray_reference(f, d, t), fcfg.sigma, 1,
-                                  sur.network(q))
+        pr, ref = full.ray_carrier(f, d, t)
+        S.rsi_surrogate_ray_frame(pr, ref, fcfg.sigma, 1, sur.network(q))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for f, d, t in qc:

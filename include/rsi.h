@@ -39,6 +39,11 @@
 extern "C" {
 #endif
 
+/* Every enum below carries two range markers (never valid arguments) so that its type
+ * spans the whole int range: a C caller may pass any int where an enum is expected, and
+ * the library then answers RSI_ERR_ARG (or "RSI_UNKNOWN_STATUS") with well-defined code. */
+#define RSI_ENUM_RANGE_(prefix) prefix##RANGE_MIN_ = -2147483647 - 1, prefix##RANGE_MAX_ = 2147483647
+
 typedef enum {
     RSI_OK = 0,
     RSI_ERR_NULL = 1,        /* a required pointer is NULL                          */
@@ -47,13 +52,14 @@ typedef enum {
     RSI_ERR_DEVICE = 4,      /* a HIP runtime call failed (message via last_error) */
     RSI_ERR_WORKSPACE = 5,   /* workspace allocation failed                         */
     RSI_ERR_NONFINITE = 6,   /* non-finite input (only with the finite check on)   */
-    RSI_ERR_UNSUPPORTED = 7  /* the combination of options is not implemented       */
+    RSI_ERR_UNSUPPORTED = 7, /* the combination of options is not implemented       */
+    RSI_ENUM_RANGE_(RSI_STATUS_)
 } rsi_status;
 
-typedef enum { RSI_MONOPOLE = 0, RSI_DIPOLE = 1, RSI_OMNI = 2 } rsi_kernel;
-typedef enum { RSI_FP32 = 0, RSI_FP64 = 1 } rsi_precision;
-typedef enum { RSI_T_GLOBAL = 0, RSI_T_LOCAL = 1, RSI_T_UNITY = 2 } rsi_tmode;
-typedef enum { RSI_SEQ_SOBOL = 0, RSI_SEQ_HALTON = 1 } rsi_sequence;
+typedef enum { RSI_MONOPOLE = 0, RSI_DIPOLE = 1, RSI_OMNI = 2, RSI_ENUM_RANGE_(RSI_KERNEL_) } rsi_kernel;
+typedef enum { RSI_FP32 = 0, RSI_FP64 = 1, RSI_ENUM_RANGE_(RSI_PRECISION_) } rsi_precision;
+typedef enum { RSI_T_GLOBAL = 0, RSI_T_LOCAL = 1, RSI_T_UNITY = 2, RSI_ENUM_RANGE_(RSI_TMODE_) } rsi_tmode;
+typedef enum { RSI_SEQ_SOBOL = 0, RSI_SEQ_HALTON = 1, RSI_ENUM_RANGE_(RSI_SEQUENCE_) } rsi_sequence;
 
 typedef struct { double c, rho; } rsi_medium;            /* m/s, kg/m^3             */
 

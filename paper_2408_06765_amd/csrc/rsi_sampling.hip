@@ -246,6 +246,7 @@ const char *rsi_status_string(rsi_status s) {
         case RSI_ERR_WORKSPACE: return "RSI_ERR_WORKSPACE";
         case RSI_ERR_NONFINITE: return "RSI_ERR_NONFINITE";
         case RSI_ERR_UNSUPPORTED: return "RSI_ERR_UNSUPPORTED";
+        default: break;
     }
     return "RSI_UNKNOWN_STATUS";
 }

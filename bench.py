@@ -141,7 +141,11 @@ def measured_traffic():
             continue
         k, v = line.split(":", 1)
         kv[k.strip()] = v.strip()
-    if kv.get("kernel_sources_sha256") != kernel_sources_digest():
+    try:
+        digest = kernel_sources_digest()
+    except (OSError, ValueError):  # a source or an anchor moved: the counters are stale
+        return None
+    if kv.get("kernel_sources_sha256") != digest:
         return None
     return int(float(kv["traffic_bytes_per_launch"]))
 

@@ -166,6 +166,33 @@ def test_planar_flag_rejects_tilted_normal(gpu):
                              gpu.RSI_FLAG_PLANAR_Z, normal=(0.1, 0.0, 1.0))
 
 
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_propagate_large_target_count(gpu, orc, kind):
+    """2^25 field points (a 131072-workgroup grid, one source split) from 37 sources, and
+    2^22 sources onto 3 field points (the one-wave-per-point launch at its widest split):
+    sampled outputs against the reference, FP32."""
+    import torch
+    rng = np.random.default_rng(77 + kind)
+    src, w, s, _ = _case(31 + kind, 37, 1, kind)
+    nt = 1 << 25
+    tgt = tuple(torch.as_tensor(rng.uniform(lo, hi, nt), device="cuda")
+                for lo, hi in ((-0.02, 0.03), (-0.01, 0.01), (0.006, 0.04)))
+    got = gpu.rsi_propagate(devpts(src), dev(w), dev(s), tgt, 5900.0, 5.0e6, kind, 0, normal=(0.0, 0.0, 1.0))
+    pick = torch.as_tensor(np.sort(rng.choice(nt, 2000, replace=False)), device="cuda")
+    sub = tuple(host(t[pick]) for t in tgt)
+    ref = orc.propagate(kind, src, w, s, sub, 5900.0, 5.0e6, normal=(0.0, 0.0, 1.0))
+    assert rel(host(got[pick]), ref) <= TOL[0]
+    del got, tgt
+    ns = 1 << 22
+    src2 = W.random_cloud(41 + kind, ns, (0.0, 0.0, 0.0), (0.015, 0.015, 0.0 if kind == 1 else 0.002))
+    w2, s2 = W.random_weights(42, ns, 1e-6), W.random_complex(43, ns)
+    tgt2 = W.random_cloud(44, 3, (0.005, 0.0, 0.02), (0.02, 0.01, 0.015))
+    got2 = host(gpu.rsi_propagate(devpts(src2), dev(w2), dev(s2), devpts(tgt2), 5900.0, 5.0e6, kind, 0,
+                                  normal=(0.0, 0.0, 1.0)))
+    ref2 = orc.propagate(kind, src2, w2, s2, tgt2, 5900.0, 5.0e6, normal=(0.0, 0.0, 1.0))
+    assert rel(got2, ref2) <= TOL[0]
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_propagate_empty_sources_give_zero(gpu, prec):
     import torch

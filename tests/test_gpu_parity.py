@@ -611,6 +611,32 @@ def test_ray_field_both_fp32_launches(gpu, orc, nf, launch, monkeypatch):
         assert rel(got[q], ref[q]) <= TOL[0], (q, rel(got[q], ref[q]))
 
 
+
+def test_ray_field_large_counts(gpu, orc):
+    """Ray model at the size limits of its launches, FP32: 2^22 field points from 64
+    samples (16384 workgroups, one per 256 points) on sampled outputs, and 2^18 samples
+    onto 5 field points (the one-wave-per-point launch, 1024 source splits)."""
+    import torch
+    rng = np.random.default_rng(5)
+    media = (W.WATER, W.STEEL_5900)
+    xd = orc.sample_disc(3, 64, W.PISTON_RADIUS, (0.0, 0.0, 0.0), math.radians(10.0))
+    T = gpu.Transducer(*devpts(xd[:3]), dev(xd[3]), 1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    nt = 1 << 22
+    tgt = tuple(torch.as_tensor(rng.uniform(lo, hi, nt), device="cuda")
+                for lo, hi in ((-0.01, 0.04), (-0.01, 0.01), (0.051, 0.08)))
+    got = gpu.rsi_ray_field(T, [0.05], media, tgt, [2.5e6], 0)[0]
+    pick = torch.as_tensor(np.sort(rng.choice(nt, 1500, replace=False)), device="cuda")
+    sub = tuple(host(t[pick]) for t in tgt)
+    ref = orc.ray_field(xd, 1.0, [0.05], [m[0] for m in media], [m[1] for m in media], sub, [2.5e6])[0]
+    assert rel(host(got[pick]), ref) <= TOL[0]
+    del got, tgt
+    xd2 = orc.sample_disc(4, 1 << 18, W.PISTON_RADIUS, (0.0, 0.0, 0.0), math.radians(10.0))
+    T2 = gpu.Transducer(*devpts(xd2[:3]), dev(xd2[3]), 1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    tgt2 = W.random_cloud(6, 5, (0.015, 0.0, 0.065), (0.01, 0.005, 0.01))
+    got2 = host(gpu.rsi_ray_field(T2, [0.05], media, devpts(tgt2), [2.5e6], 0))
+    ref2 = orc.ray_field(xd2, 1.0, [0.05], [m[0] for m in media], [m[1] for m in media], tgt2, [2.5e6])
+    assert rel(got2, ref2) <= TOL[0]
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_ray_field_extreme_geometry(gpu, orc, prec):
     """Edge cases of the root of eq. 14: field points 0.05-1 mm under the last plane far to

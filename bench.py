@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--workload", default="one_interface",
                     choices=["one_interface", "layered_stack", "scan_batch", "surrogate",
                              "interface_continuity", "focused_normal", "ray_field",
-                             "ray_crossover"],
+                             "ray_crossover", "multilayer_noise"],
                     help="one_interface is the benchmark line; the others are secondary "
                          "measurements printed in the same format")
     ap.add_argument("--autotune", action="store_true",
@@ -552,6 +552,63 @@ def scan_batch(args):
     plan.destroy()
 
 
+def multilayer_noise(args):
+    """QMC noise of the RSI chain through thin layers (Sec. 3.4): rel-L2 of the FP32 field
+    at N Halton samples per surface against N_ref on the same points, through the seven
+    planes of six 2 mm steel/aluminium layers and, for contrast, through one plane; and
+    the time of each chain."""
+    import torch
+    from paper_2408_06765_amd import rsi
+    from paper_2408_06765_amd import workloads as W
+
+    cfg = W.MultilayerNoise()
+    H = rsi.RSI_SEQ_HALTON
+
+    def chain(media, n):
+        zs = cfg.planes(media)
+        xs = rsi.rsi_sample_disc(0, n, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt, seq=H)
+        T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), cfg.axis)
+        ifs = []
+        for m, (z, xc) in enumerate(zip(zs, cfg.patch_centres(media))):
+            q = rsi.rsi_sample_square((m + 1) << 24, n, xc, 0.0, z, cfg.half_width, seq=H)
+            ifs.append(rsi.Interface(*q[:3], q[3], z))
+        tgt = tuple(torch.as_tensor(a, device="cuda") for a in cfg.field(media))
+        f = lambda: rsi.rsi_chain(T, ifs, media, tgt, [cfg.freq], rsi.RSI_T_LOCAL, rsi.RSI_FP32)[0]
+        out = f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = f()
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), time.perf_counter() - t0
+
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    res = {}
+    for name, media in (("seven_planes", cfg.media), ("one_plane", cfg.one_plane)):
+        ref, t_ref = chain(media, cfg.n_ref)
+        rows = []
+        for n in cfg.counts:
+            got, dt = chain(media, n)
+            rows.append({"samples_per_surface": n, "rel_l2_vs_ref": rel(got, ref), "ms": round(1e3 * dt, 3)})
+            print(f"{name} N={n}: rel-L2 {rows[-1]['rel_l2_vs_ref']:.3e}, {1e3 * dt:.2f} ms", file=sys.stderr,
+                  flush=True)
+        lg = np.log([r["samples_per_surface"] for r in rows])
+        le = np.log([r["rel_l2_vs_ref"] for r in rows])
+        res[name] = {"rows": rows, "ref_samples": cfg.n_ref, "ref_ms": round(1e3 * t_ref, 1),
+                     "loglog_slope": float(np.polyfit(lg, le, 1)[0])}
+    at = {n: r for n, r in zip(cfg.counts, res["seven_planes"]["rows"])}
+    line = {
+        "metric": "RSI QMC error through six 2 mm steel/aluminium layers (Sec. 3.4) at 10^5 samples per surface",
+        "value": at[100000]["rel_l2_vs_ref"], "unit": "rel-L2 vs 2e6 samples", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": at[100000]["ms"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "multilayer_noise: tilted piston (10 deg, 2.5 MHz), 10 mm water, six 2 mm "
+                               "steel/aluminium layers over steel (7 planes), Halton samples, field on and "
+                               "across the refracted axis"},
+        "stacks": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def surrogate(args):
     """The learned surrogate: 10^7 RSI samples (5120 random configurations of the
     one-interface piston family x 1953 points, drawn where the recipe trains: f <= 3.25 MHz,
@@ -689,6 +746,8 @@ def main():
         return scan_batch(args)
     if args.workload == "surrogate":
         return surrogate(args)
+    if args.workload == "multilayer_noise":
+        return multilayer_noise(args)
 
     from paper_2408_06765_amd import rsi
     from paper_2408_06765_amd import workloads as W

@@ -257,6 +257,54 @@ def snell_intercepts(x0: float, tilt: float, z_if, speeds) -> List[float]:
 
 
 @dataclass
+class MultilayerNoise:
+    """QMC noise of the RSI chain through thin layers (Sec. 3.4): the piston tilted 10 deg
+    at 2.5 MHz under 10 mm of water, six 2 mm layers alternating steel and aluminium and a
+    steel half-space below (seven planes), Halton samples on the piston (index 1..) and on
+    every interface patch (index (m+1) 2^24 + 1.., half-width 3a about the Snell-chained
+    intercepts); field points on the refracted beam axis 1-20 mm below the last plane and
+    across it 10 mm below.  The field at N samples per surface against N_ref; the same for
+    one plane (water over the steel half-space) for contrast."""
+    radius: float = PISTON_RADIUS
+    freq: float = 2.5e6
+    tilt: float = deg(10.0)
+    water_path: float = 0.010
+    layer: float = 0.002
+    counts: Tuple[int, ...] = (10000, 30000, 100000, 300000, 1000000)
+    n_ref: int = 2000000
+    n_line: int = 41
+    media: Tuple[Tuple[float, float], ...] = (WATER, STEEL_PAPER, ALU_PAPER, STEEL_PAPER, ALU_PAPER,
+                                              STEEL_PAPER, ALU_PAPER, STEEL_PAPER)
+    one_plane: Tuple[Tuple[float, float], ...] = (WATER, STEEL_PAPER)
+
+    @property
+    def half_width(self) -> float:
+        return 3.0 * self.radius
+
+    @property
+    def axis(self):
+        return (math.sin(self.tilt), 0.0, math.cos(self.tilt))
+
+    def planes(self, media) -> List[float]:
+        return [self.water_path + m * self.layer for m in range(len(media) - 1)]
+
+    def patch_centres(self, media) -> List[float]:
+        return snell_intercepts(0.0, self.tilt, self.planes(media), [m[0] for m in media])
+
+    def field(self, media):
+        zs = self.planes(media)
+        s = min(math.sin(self.tilt) / media[0][0] * media[-1][0], 0.999999)
+        t = s / math.sqrt(1 - s * s)
+        x_top = self.patch_centres(media)[-1]
+        d = np.linspace(0.001, 0.020, self.n_line)
+        xa, za = x_top + d * t, zs[-1] + d
+        xc = x_top + 0.010 * t + np.linspace(-0.008, 0.008, self.n_line)
+        zc = np.full(self.n_line, zs[-1] + 0.010)
+        x = np.concatenate([xa, xc])
+        return x, np.zeros_like(x), np.concatenate([za, zc])
+
+
+@dataclass
 class LayeredStack:
     """Three interfaces 2 mm apart; 64 frequencies 1-10 MHz; 128^3 volume below."""
     radius: float = PISTON_RADIUS

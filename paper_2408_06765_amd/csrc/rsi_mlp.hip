@@ -264,6 +264,107 @@ __global__ void __launch_bounds__(256) features_kernel(int64_t n, int64_t Mp, in
     }
 }
 
+// Fused inference: features, every hidden layer and the head for a tile of 128 rows in
+// one workgroup, the activations kept in LDS between layers (bf16, rows padded by 8 so the
+// 16 lanes that read one MFMA A fragment hit disjoint banks) and the weights streamed
+// from L2 straight into the MFMA B operands (16-byte loads, the next K step's loaded
+// before the current step's MFMAs).  Four waves split each layer's W output columns.
+// The arithmetic is that of the unfused path step for step -- the same bf16 features, the
+// same MFMA sequence over K, bias + SiLU in FP32 rounded to bf16, the head's FMAs in
+// feature order -- so the two give the same bits; only the HBM round trips of the
+// activations are gone.
+struct FusedArgs {
+    const float *q;
+    int64_t n;
+    Box box;
+    const float *Bff;
+    int m;  // Fourier frequencies (F = 2m features)
+    int L;
+    const bf16 *Wl[kMaxLayers];  // [W][in_dim] row-major
+    const float *bl[kMaxLayers];
+    int in_dim[kMaxLayers];
+    const float *Wo, *bo;
+    float *y;
+};
+
+constexpr int kFusedRows = 128;
+
+template <int W>
+__global__ void __launch_bounds__(256) mlp_infer_fused_kernel(FusedArgs a) {
+    constexpr int BM = kFusedRows, LDA = W + 8, FM = BM / 16, WN = W / 4, FN = WN / 16;
+    static_assert(FN >= 1, "width below 64");
+    __shared__ __attribute__((aligned(16))) bf16 act[BM][LDA];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t r0 = (int64_t)blockIdx.x * BM;
+    {
+        // features as in features_kernel: two threads per row, each half of the frequencies
+        const int row = tid & (BM - 1), half = tid >> 7;
+        const int64_t b = r0 + row;
+        const bool live = b < a.n;
+        double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (live)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) v[c] = 2.0 * ((double)a.q[b * 5 + c] - a.box.lo[c]) * a.box.inv[c] - 1.0;
+        const int mh = a.m / 2;
+        for (int j = half * mh; j < (half + 1) * mh; ++j) {
+            double u = 0.0;
+            if (live)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) u = fma((double)a.Bff[j * 5 + c], v[c], u);
+            const float ph = (float)(u - floor(u));
+            act[row][j] = (bf16)__builtin_amdgcn_sinf(ph);
+            act[row][a.m + j] = (bf16)__builtin_amdgcn_cosf(ph);
+        }
+    }
+    __syncthreads();
+    const int r = lane & 15, kq = (lane >> 4) * 8, cn = lane & 15, cm = (lane >> 4) * 4;
+    for (int l = 0; l < a.L; ++l) {
+        const int K = a.in_dim[l];
+        const bf16 *Wl = a.Wl[l] + (int64_t)(wave * WN + r) * K + kq;
+        f32x4 acc[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        bf16x8 bcur[FN], bnxt[FN];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bcur[j] = *reinterpret_cast<const bf16x8 *>(Wl + (int64_t)16 * j * K);
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            if (k0 + 32 < K)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    bnxt[j] = *reinterpret_cast<const bf16x8 *>(Wl + (int64_t)16 * j * K + k0 + 32);
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const bf16x8 af = *reinterpret_cast<const bf16x8 *>(&act[16 * i + r][k0 + kq]);
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bcur[j], acc[i][j], 0, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) bcur[j] = bnxt[j];
+        }
+        __syncthreads();  // every wave has read this layer's input
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int n = wave * WN + 16 * j + cn;
+            const float bias = a.bl[l][n];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) act[16 * i + cm + e][n] = (bf16)silu_f(acc[i][j][e] + bias);
+        }
+        __syncthreads();
+    }
+    // head as in head_kernel: one (row, output) per thread, FMAs in feature order
+    const int row = tid >> 1, k = tid & 1;
+    const int64_t b = r0 + row;
+    float yk = 0.0f;
+    for (int f = 0; f < W; ++f) yk = fmaf(a.Wo[k * W + f], (float)act[row][f], yk);
+    yk += a.bo[k];
+    if (b < a.n) a.y[2 * b + k] = yk;
+}
+
 // Output layer (FP32), one thread per row: y = Wo h + bo.  Training (t != NULL): the
 // row's loss and output gradient dy = (y - t)/n go to dyl [Mp][3] (0 for padding rows)
 // and dZ_L = bf16((dy Wo) * silu'(Z_L)), row-major and transposed.  Wo is read through the constant address space
@@ -797,6 +898,33 @@ rsi_status rsi_mlp_forward(rsi_mlp *net, int64_t n, const float *q, float *y, vo
     if (n == 0) return RSI_OK;
     if (!y) return RSI_ERR_NULL;
     hipStream_t s = as_stream(stream);
+    // one fused launch when the features fit the hidden width (RSI_MLP_FUSED=0: layer by layer)
+    const char *fe = std::getenv("RSI_MLP_FUSED");
+    const bool fused = !(fe && fe[0] == '0' && fe[1] == 0);
+    if (fused && net->F <= net->W && (net->W == 64 || net->W == 128 || net->W == 256)) {
+        FusedArgs a{};
+        a.q = q;
+        a.n = n;
+        a.box = net->box;
+        a.Bff = net->Bff.as<float>();
+        a.m = net->m;
+        a.L = net->L;
+        const float *params = net->params.as<float>();
+        for (int l = 0; l < net->L; ++l) {
+            a.Wl[l] = net->Wb[l]->as<bf16>();
+            a.bl[l] = params + net->offb[l];
+            a.in_dim[l] = net->in_dim[l];
+        }
+        a.Wo = params + net->offWo;
+        a.bo = params + net->offbo;
+        a.y = y;
+        const dim3 grid((unsigned)((n + kFusedRows - 1) / kFusedRows));
+        if (net->W == 256) hipLaunchKernelGGL(mlp_infer_fused_kernel<256>, grid, dim3(256), 0, s, a);
+        else if (net->W == 128) hipLaunchKernelGGL(mlp_infer_fused_kernel<128>, grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(mlp_infer_fused_kernel<64>, grid, dim3(256), 0, s, a);
+        RSI_HIP(hipGetLastError());
+        return RSI_OK;
+    }
     RSI_TRY(forward_hidden(net, n, q, false, s));
     const int64_t Mp = pad64(n);
     const float *params = net->params.as<float>();

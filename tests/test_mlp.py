@@ -132,6 +132,19 @@ def test_mlp_forward_matches_reference(gpu, n_ff, width, depth, n):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("n_ff,width,depth,n", SHAPES + [(64, 128, 4, 129), (64, 256, 5, 65537)])
+def test_mlp_fused_forward_equals_layerwise(gpu, n_ff, width, depth, n, monkeypatch):
+    """The fused inference kernel (one launch, activations in LDS) gives the bits of the
+    layer-by-layer path (features, one GEMM per layer, head), ragged row counts included."""
+    net, o, q, t, v, tn, params = _setup(gpu, n_ff, width, depth, n, 7)
+    y_fused = net.forward(q).cpu().numpy()
+    monkeypatch.setenv("RSI_MLP_FUSED", "0")
+    y_layer = net.forward(q).cpu().numpy()
+    assert np.array_equal(y_fused.view(np.uint32), y_layer.view(np.uint32))
+    net.destroy()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("n_ff,width,depth,n", SHAPES)
 def test_mlp_gradients_match_reference(gpu, n_ff, width, depth, n):
     net, o, q, t, v, tn, params = _setup(gpu, n_ff, width, depth, n, 4)

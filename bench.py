@@ -128,15 +128,16 @@ def kernel_sources_digest():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairsum_dipole_one_interface_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "pairsum_valu_counters.md")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter summary, or
-    None when the kernel sources changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _counter_summary(path):
+    """The key: value lines of a committed counter summary, or None when the file is missing
+    or the kernel sources changed since its counters were taken."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if line.startswith("#") or ":" not in line:
             continue
         k, v = line.split(":", 1)
@@ -147,7 +148,29 @@ def measured_traffic():
         return None
     if kv.get("kernel_sources_sha256") != digest:
         return None
-    return int(float(kv["traffic_bytes_per_launch"]))
+    return kv
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    kv = _counter_summary(TRAFFIC_FILE)
+    return None if kv is None else int(float(kv["traffic_bytes_per_launch"]))
+
+
+def measured_valu():
+    """Executed FP32 FLOPs and VALU occupancy of the dominant kernel from the committed VALU
+    counter summary (the metric's "% FP32 VALU peak" as counted by the hardware), or None
+    when the kernel sources changed since the counters were taken."""
+    kv = _counter_summary(VALU_FILE)
+    if kv is None:
+        return None
+    return {"executed_tflops": float(kv["dipole_executed_fp32_tflops"]),
+            "executed_frac": float(kv["dipole_executed_fp32_frac"]),
+            "valu_lane_util_pct": float(kv["dipole_valu_lane_util_pct"]),
+            "cu_busy_pct": float(kv["dipole_cu_busy_pct"]),
+            "issue_model_frac": float(kv["dipole_issue_model_frac"]),
+            "source": os.path.relpath(VALU_FILE, ROOT)}
 
 
 def timed(fn, steps, warmup):
@@ -831,6 +854,7 @@ def main():
                      "kernel": "pairsum_f32_kernel<dipole, planar> (interface -> image), "
                                f"{FLOPS_DIPOLE} flop/pair x {pairs_stage1:.3e} pairs / {kms:.3f} ms"},
     }
+    line["fp32_valu_counters"] = measured_valu()
     if check is not None:
         line["parity_vs_oracle_samples"] = check
     if args.calib_copy:

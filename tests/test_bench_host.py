@@ -1,0 +1,80 @@
+"""Host logic of bench.py (CPU): the kernel-source digest that decides whether the committed
+counter summaries still describe the kernel, and the readers of those summaries."""
+import os
+import shutil
+
+import pytest
+
+import bench
+
+
+def test_region_takes_the_braced_block_or_the_statement():
+    text = "int a;\nvoid f(int x) {\n  if (x) { g(); }\n}\nconstexpr int kB = 4;\nint z;\n"
+    assert bench._region(text, "void f(") == "void f(int x) {\n  if (x) { g(); }\n}"
+    assert bench._region(text, "constexpr int kB") == "constexpr int kB = 4;"
+    with pytest.raises(ValueError):
+        bench._region(text, "not in the text")
+
+
+def _copy_sources(tmp_path, monkeypatch):
+    for f, _ in bench.KERNEL_SOURCES:
+        dst = tmp_path / f
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        shutil.copy(os.path.join(bench.ROOT, f), dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+
+
+def test_digest_follows_kernel_regions_only(tmp_path, monkeypatch):
+    d0 = bench.kernel_sources_digest()
+    _copy_sources(tmp_path, monkeypatch)
+    assert bench.kernel_sources_digest() == d0
+    hip = tmp_path / "paper_2408_06765_amd/csrc/rsi_pairsum.hip"
+    # host code outside the anchored regions leaves the digest alone
+    hip.write_text(hip.read_text() + "\n// trailing note\n")
+    assert bench.kernel_sources_digest() == d0
+    # a change inside the kernel's definition changes it
+    text = hip.read_text()
+    i = text.index("pairsum_f32_kernel(")
+    j = text.index("{", i) + 1
+    hip.write_text(text[:j] + "\n    // edit\n" + text[j:])
+    assert bench.kernel_sources_digest() != d0
+    # a moved anchor reads as stale counters, not as an error
+    hip.write_text(text.replace("pairsum_f32_kernel(", "pairsum_f32_kernel_renamed("))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.measured_traffic() is None
+
+
+def _summary(path, digest):
+    path.write_text("# counters\n"
+                    "traffic_bytes_per_launch: 123456\n"
+                    "dipole_executed_fp32_tflops: 54.5\n"
+                    "dipole_executed_fp32_frac: 0.35\n"
+                    "dipole_valu_lane_util_pct: 100.0\n"
+                    "dipole_cu_busy_pct: 99.0\n"
+                    "dipole_issue_model_frac: 1.01\n"
+                    f"kernel_sources_sha256: {digest}\n")
+
+
+def test_summaries_are_read_only_while_the_digest_matches(tmp_path, monkeypatch):
+    f = tmp_path / "summary.txt"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    monkeypatch.setattr(bench, "VALU_FILE", str(f))
+    _summary(f, bench.kernel_sources_digest())
+    assert bench.measured_traffic() == 123456
+    v = bench.measured_valu()
+    assert v["executed_frac"] == 0.35 and v["issue_model_frac"] == 1.01
+    _summary(f, "0" * 64)
+    assert bench.measured_traffic() is None and bench.measured_valu() is None
+    f.unlink()
+    assert bench.measured_traffic() is None and bench.measured_valu() is None
+
+
+def test_committed_summaries_parse():
+    """Both committed summaries carry the keys the readers use (whether or not they are
+    current for the sources in this tree)."""
+    for path, keys in ((bench.TRAFFIC_FILE, ["traffic_bytes_per_launch"]),
+                       (bench.VALU_FILE, ["dipole_executed_fp32_frac", "dipole_cu_busy_pct"])):
+        text = open(path).read()
+        assert "kernel_sources_sha256:" in text
+        for k in keys:
+            assert f"{k}:" in text

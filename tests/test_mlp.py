@@ -132,7 +132,8 @@ def test_mlp_forward_matches_reference(gpu, n_ff, width, depth, n):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n_ff,width,depth,n", SHAPES + [(64, 128, 4, 129), (64, 256, 5, 65537)])
+@pytest.mark.parametrize("n_ff,width,depth,n", SHAPES + [(64, 128, 4, 129), (64, 256, 5, 65537), (32, 64, 1, 1),
+                                                      (32, 128, 2, 7)])
 def test_mlp_fused_forward_equals_layerwise(gpu, n_ff, width, depth, n, monkeypatch):
     """The fused inference kernel (one launch, activations in LDS) gives the bits of the
     layer-by-layer path (features, one GEMM per layer, head), ragged row counts included."""

@@ -289,8 +289,12 @@ struct FusedArgs {
 
 constexpr int kFusedRows = 128;
 
+// Two workgroups per CU (the register budget that leaves: 192 VGPRs at width 256, no spill):
+// one workgroup's MFMAs then cover the other's weight-load waits and SiLU epilogue, which a
+// single wave per SIMD leaves exposed (122 against 81 us for 65536 rows of a 5 x 256 net;
+// unrolling the features loop for independent FP64 chains: 79 us).
 template <int W>
-__global__ void __launch_bounds__(256) mlp_infer_fused_kernel(FusedArgs a) {
+__global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
     constexpr int BM = kFusedRows, LDA = W + 8, FM = BM / 16, WN = W / 4, FN = WN / 16;
     static_assert(FN >= 1, "width below 64");
     __shared__ __attribute__((aligned(16))) bf16 act[BM][LDA];
@@ -306,6 +310,7 @@ __global__ void __launch_bounds__(256) mlp_infer_fused_kernel(FusedArgs a) {
 #pragma unroll
             for (int c = 0; c < 5; ++c) v[c] = 2.0 * ((double)a.q[b * 5 + c] - a.box.lo[c]) * a.box.inv[c] - 1.0;
         const int mh = a.m / 2;
+#pragma unroll 4
         for (int j = half * mh; j < (half + 1) * mh; ++j) {
             double u = 0.0;
             if (live)

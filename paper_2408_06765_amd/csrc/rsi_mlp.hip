@@ -287,31 +287,32 @@ struct FusedArgs {
     float *y;
 };
 
-constexpr int kFusedRows = 128;
-
 // Two workgroups per CU (the register budget that leaves: 192 VGPRs at width 256, no spill):
 // one workgroup's MFMAs then cover the other's weight-load waits and SiLU epilogue, which a
 // single wave per SIMD leaves exposed (122 against 81 us for 65536 rows of a 5 x 256 net;
 // unrolling the features loop for independent FP64 chains: 79 us).
-template <int W>
+// BM rows per workgroup: 128 when the grid still fills the chip, 32 or 64 for calls of a
+// few thousand rows, where one workgroup's latency is the call's time.
+template <int W, int BM>
 __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
-    constexpr int BM = kFusedRows, LDA = W + 8, FM = BM / 16, WN = W / 4, FN = WN / 16;
+    constexpr int LDA = W + 8, FM = BM / 16, WN = W / 4, FN = WN / 16, TPR = 256 / BM;
     static_assert(FN >= 1, "width below 64");
+    static_assert(BM == 32 || BM == 64 || BM == 128, "32, 64 or 128 rows");
     __shared__ __attribute__((aligned(16))) bf16 act[BM][LDA];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t r0 = (int64_t)blockIdx.x * BM;
     {
-        // features as in features_kernel: two threads per row, each half of the frequencies
-        const int row = tid & (BM - 1), half = tid >> 7;
+        // features as in features_kernel: TPR threads per row, each a share of the frequencies
+        const int row = tid & (BM - 1), part = tid / BM;
         const int64_t b = r0 + row;
         const bool live = b < a.n;
         double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         if (live)
 #pragma unroll
             for (int c = 0; c < 5; ++c) v[c] = 2.0 * ((double)a.q[b * 5 + c] - a.box.lo[c]) * a.box.inv[c] - 1.0;
-        const int mh = a.m / 2;
+        const int mh = a.m / TPR;  // m is a multiple of 32
 #pragma unroll 4
-        for (int j = half * mh; j < (half + 1) * mh; ++j) {
+        for (int j = part * mh; j < (part + 1) * mh; ++j) {
             double u = 0.0;
             if (live)
 #pragma unroll
@@ -362,6 +363,7 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
         __syncthreads();
     }
     // head as in head_kernel: one (row, output) per thread, FMAs in feature order
+    if (tid >= 2 * BM) return;
     const int row = tid >> 1, k = tid & 1;
     const int64_t b = r0 + row;
     float yk = 0.0f;
@@ -779,6 +781,13 @@ static rsi_status check_batch(const rsi_mlp *net, int64_t n, const void *q) {
     return RSI_OK;
 }
 
+template <int BM>
+static void launch_fused(int W, dim3 grid, dim3 block, hipStream_t s, const FusedArgs &a) {
+    if (W == 256) hipLaunchKernelGGL((mlp_infer_fused_kernel<256, BM>), grid, block, 0, s, a);
+    else if (W == 128) hipLaunchKernelGGL((mlp_infer_fused_kernel<128, BM>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((mlp_infer_fused_kernel<64, BM>), grid, block, 0, s, a);
+}
+
 }  // namespace rsi
 
 using namespace rsi;
@@ -923,10 +932,18 @@ rsi_status rsi_mlp_forward(rsi_mlp *net, int64_t n, const float *q, float *y, vo
         a.Wo = params + net->offWo;
         a.bo = params + net->offbo;
         a.y = y;
-        const dim3 grid((unsigned)((n + kFusedRows - 1) / kFusedRows));
-        if (net->W == 256) hipLaunchKernelGGL(mlp_infer_fused_kernel<256>, grid, dim3(256), 0, s, a);
-        else if (net->W == 128) hipLaunchKernelGGL(mlp_infer_fused_kernel<128>, grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(mlp_infer_fused_kernel<64>, grid, dim3(256), 0, s, a);
+        // 128-row tiles while they give two workgroups per CU, 64 down to 128 workgroups,
+        // 32 below (15625 rows: 57, 41 and 50 us for 128, 64 and 32; RSI_MLP_FUSED_ROWS:
+        // 32, 64 or 128 forces one)
+        int rows = n >= 128 * 512 ? 128 : n >= 64 * 128 ? 64 : 32;
+        if (const char *fr = std::getenv("RSI_MLP_FUSED_ROWS")) {
+            const int v = std::atoi(fr);
+            if (v == 32 || v == 64 || v == 128) rows = v;
+        }
+        const dim3 grid((unsigned)((n + rows - 1) / rows)), block(256);
+        if (rows == 128) launch_fused<128>(net->W, grid, block, s, a);
+        else if (rows == 64) launch_fused<64>(net->W, grid, block, s, a);
+        else launch_fused<32>(net->W, grid, block, s, a);
         RSI_HIP(hipGetLastError());
         return RSI_OK;
     }

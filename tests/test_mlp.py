@@ -146,6 +146,21 @@ def test_mlp_fused_forward_equals_layerwise(gpu, n_ff, width, depth, n, monkeypa
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("rows", ["32", "64", "128"])
+@pytest.mark.parametrize("n_ff,width,depth,n", [(64, 256, 5, 1000), (32, 128, 2, 7), (32, 64, 3, 300)])
+def test_mlp_fused_row_tiles_equal_layerwise(gpu, n_ff, width, depth, n, rows, monkeypatch):
+    """Each row tile of the fused kernel (forced; by default the call's size picks it)
+    gives the bits of the layer-by-layer path."""
+    net, o, q, t, v, tn, params = _setup(gpu, n_ff, width, depth, n, 11)
+    monkeypatch.setenv("RSI_MLP_FUSED_ROWS", rows)
+    y_fused = net.forward(q).cpu().numpy()
+    monkeypatch.setenv("RSI_MLP_FUSED", "0")
+    y_layer = net.forward(q).cpu().numpy()
+    assert np.array_equal(y_fused.view(np.uint32), y_layer.view(np.uint32))
+    net.destroy()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("n_ff,width,depth,n", SHAPES)
 def test_mlp_gradients_match_reference(gpu, n_ff, width, depth, n):
     net, o, q, t, v, tn, params = _setup(gpu, n_ff, width, depth, n, 4)

@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(256) features_kernel(int64_t n, int64_t Mp, in
     }
 }
 
-// Fused inference: features, every hidden layer and the head for a tile of 128 rows in
+// Fused inference: features, every hidden layer and the head for a tile of BM rows in
 // one workgroup, the activations kept in LDS between layers (bf16, rows padded by 8 so the
 // 16 lanes that read one MFMA A fragment hit disjoint banks) and the weights streamed
 // from L2 straight into the MFMA B operands (16-byte loads, the next K step's loaded

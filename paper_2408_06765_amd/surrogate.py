@@ -286,10 +286,32 @@ class FieldSource:
         X, Z = np.meshgrid(xs, zs)
         self.xg = X.ravel()
         self.zg = Z.ravel()
+        self._grid_rows = {}  # device (x, z_below) rows of the fixed grids, by name
+
+    def _rows(self, name: str, points) -> torch.Tensor:
+        """Query rows of a fixed grid (points() gives its x, z_below) with the configuration
+        columns still to fill, kept on the device after the first call."""
+        q = self._grid_rows.get(name)
+        if q is None:
+            xg, zg = points()
+            q = torch.zeros((xg.size, 5), dtype=torch.float32, device="cuda")
+            q[:, 0] = torch.as_tensor(xg.astype(np.float32), device="cuda")
+            q[:, 1] = torch.as_tensor(zg.astype(np.float32), device="cuda")
+            self._grid_rows[name] = q
+        return q
+
+    def _fill(self, q: torch.Tensor, f: float, depth: float, tilt: float) -> torch.Tensor:
+        q = q.clone()
+        q[:, 2] = f
+        q[:, 3] = depth
+        q[:, 4] = tilt
+        return q
 
     def queries(self, f: float, depth: float, tilt: float, xz=None) -> torch.Tensor:
         """Query rows (x, z_below, f, depth, tilt): the image grid, or the given (x, z) points."""
-        xg, zg = (self.xg, self.zg) if xz is None else xz
+        if xz is None:
+            return self._fill(self._rows("image", lambda: (self.xg, self.zg)), f, depth, tilt)
+        xg, zg = xz
         n = xg.size
         q = np.stack([xg, zg, np.full(n, f), np.full(n, depth), np.full(n, tilt)], 1)
         return torch.as_tensor(q.astype(np.float32), device="cuda")
@@ -307,11 +329,13 @@ class FieldSource:
     def ray_pressure(self, f: float, depth: float, tilt: float, xz=None) -> torch.Tensor:
         """p = i omega rho2 phi of the ray-tracing model (eq. 12) at the query points, from
         the first n_carrier samples of the piston's sample sequence (FP32)."""
+        return self._ray_pressure_rows(self.queries(f, depth, tilt, xz), f, depth, tilt)
+
+    def _ray_pressure_rows(self, q: torch.Tensor, f: float, depth: float, tilt: float) -> torch.Tensor:
         cfg, b = self.cfg, self.cfg.box
         xs = rsi.rsi_sample_disc(0, cfg.n_carrier, b.radius, (0.0, 0.0, 0.0), tilt)
         T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), (math.sin(tilt), 0.0, math.cos(tilt)))
-        phi = rsi.rsi_ray_field(T, [depth], b.media, self._targets(self.queries(f, depth, tilt, xz)), [f],
-                                rsi.RSI_FP32)[0]
+        phi = rsi.rsi_ray_field(T, [depth], b.media, self._targets(q), [f], rsi.RSI_FP32)[0]
         return rsi.rsi_to_pressure(phi, b.media[1][1], f)
 
     def ray_reference(self, f: float, depth: float, tilt: float) -> torch.Tensor:
@@ -326,8 +350,15 @@ class FieldSource:
     def ray_carrier(self, f: float, depth: float, tilt: float, xz=None):
         """The ray field at the query points and on the reference grid, from one call
         (the points are independent, so this is ray_pressure and ray_reference at once)."""
-        xg, zg = (self.xg, self.zg) if xz is None else xz
+        if xz is None:
+            def points():
+                rx, rz = self._ref_xz()
+                return np.concatenate([self.xg, rx]), np.concatenate([self.zg, rz])
+            q = self._fill(self._rows("image+reference", points), f, depth, tilt)
+            p = self._ray_pressure_rows(q, f, depth, tilt)
+            return p[:self.xg.size], p[self.xg.size:]
         rx, rz = self._ref_xz()
+        xg, zg = xz
         p = self.ray_pressure(f, depth, tilt, (np.concatenate([xg, rx]), np.concatenate([zg, rz])))
         return p[:xg.size], p[xg.size:]
 

@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 FLOPS_MONOPOLE = 25
 FLOPS_DIPOLE = 33
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 2.4 GHz x 256 flop/CU/clk)
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 MFMA
 
 
 def parse():
@@ -44,7 +45,7 @@ def parse():
     ap.add_argument("--workload", default="one_interface",
                     choices=["one_interface", "layered_stack", "scan_batch", "surrogate",
                              "interface_continuity", "focused_normal", "ray_field",
-                             "ray_crossover", "multilayer_noise"],
+                             "ray_crossover", "multilayer_noise", "surrogate_inference"],
                     help="one_interface is the benchmark line; the others are secondary "
                          "measurements printed in the same format")
     ap.add_argument("--autotune", action="store_true",
@@ -748,6 +749,57 @@ def surrogate(args):
     print(json.dumps(line), flush=True)
 
 
+def flops_mlp_row(n_ff, width, depth):
+    """Algorithmic flops of one query row of the surrogate network (FMA = 2): the hidden
+    layers' products and the head; the features and the SiLU are not counted."""
+    return 2 * (2 * n_ff * width + (depth - 1) * width * width + 2 * width)
+
+
+def surrogate_inference(args):
+    """The surrogate network's inference, one fused launch per call (features, the hidden
+    SiLU layers on the bf16 MFMA, head), over 65536 query rows and over one configuration's
+    125 x 125 image; weights of the recipe's shape, random-initialised and seeded (the
+    time does not depend on their values)."""
+    import torch
+    from paper_2408_06765_amd import surrogate as S
+
+    cfg = S.SurrogateConfig()
+    lo, hi = S.lohi(cfg.box)
+    net = S.MLP(cfg.n_ff, cfg.width, cfg.depth, S.fourier_matrix(cfg.n_ff, cfg.ff_scales, cfg.seed),
+                lo, hi, cfg.batch)
+    net.set_params(S.glorot_params(cfg.n_ff, cfg.width, cfg.depth, cfg.seed))
+    rng = np.random.default_rng(0)
+
+    def rows(n):
+        q = np.stack([rng.uniform(lo[c], hi[c], n) for c in range(5)], 1).astype(np.float32)
+        return torch.as_tensor(q, device="cuda"), torch.empty((n, 2), dtype=torch.float32, device="cuda")
+
+    n, n_img = cfg.batch, cfg.nx * cfg.nz
+    q, y = rows(n)
+    q2, y2 = rows(n_img)
+    run = lambda: net.forward(q, y)
+    dt = timed(run, args.steps, args.warmup)
+    # 20 back-to-back calls between the events: a single call's events add launch latency
+    kms = _event_ms(lambda: [run() for _ in range(20)], reps=max(3, args.kernel_reps)) / 20
+    kms2 = _event_ms(lambda: [net.forward(q2, y2) for _ in range(20)], reps=max(3, args.kernel_reps)) / 20
+    net.destroy()
+    fl = flops_mlp_row(cfg.n_ff, cfg.width, cfg.depth)
+    achieved = n * fl / (kms * 1e-3) / 1e12
+    line = base_line(n * args.steps / dt, args.steps, args.warmup, dt,
+                     {"workload": f"surrogate_inference: {2 * cfg.n_ff} Fourier features -> "
+                                  f"{cfg.depth} x {cfg.width} SiLU (bf16 MFMA, FP32 accumulation) -> 2, "
+                                  f"{n} query rows per call", "rows_per_step": n}, unit="rows/s")
+    line["metric"] = "surrogate inference rows/s (fused network launch) + % bf16 MFMA peak"
+    line["dtype"] = "bf16"
+    line["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                        "kernel": f"mlp_infer_fused_kernel<{cfg.width}, 128>, {fl} flop/row x {n} rows / "
+                                  f"{kms:.4f} ms"}
+    line["image_call"] = {"rows": n_img, "ms": round(kms2, 4),
+                          "tflops": round(n_img * fl / (kms2 * 1e-3) / 1e12, 2)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -771,6 +823,8 @@ def main():
         return surrogate(args)
     if args.workload == "multilayer_noise":
         return multilayer_noise(args)
+    if args.workload == "surrogate_inference":
+        return surrogate_inference(args)
 
     from paper_2408_06765_amd import rsi
     from paper_2408_06765_amd import workloads as W

@@ -78,3 +78,11 @@ def test_committed_summaries_parse():
         assert "kernel_sources_sha256:" in text
         for k in keys:
             assert f"{k}:" in text
+
+
+def test_flop_conventions():
+    """The per-unit flop counts the roofline lines use: the ray pair through one plane (two
+    Newton evaluations) and one row of the surrogate network (128 frequencies, 5 x 256)."""
+    assert bench.flops_ray_pair(2) == 104
+    assert bench.flops_mlp_row(128, 256, 5) == 2 * (256 * 256 + 4 * 256 * 256 + 2 * 256)
+    assert bench.FLOPS_DIPOLE == 33

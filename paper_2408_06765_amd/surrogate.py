@@ -331,11 +331,23 @@ class FieldSource:
         the first n_carrier samples of the piston's sample sequence (FP32)."""
         return self._ray_pressure_rows(self.queries(f, depth, tilt, xz), f, depth, tilt)
 
-    def _ray_pressure_rows(self, q: torch.Tensor, f: float, depth: float, tilt: float) -> torch.Tensor:
+    def _grid_targets(self, name: str, base: torch.Tensor, depth: float):
+        """_targets of a fixed grid's rows: x and the zero y stay on the device, z is the
+        query's float32 depth widened and added to z_below, as _targets computes it."""
+        key = name + "/targets"
+        xy = self._grid_rows.get(key)
+        if xy is None:
+            xy = (base[:, 0].double().contiguous(), torch.zeros(base.shape[0], dtype=torch.float64, device="cuda"),
+                  base[:, 1].double().contiguous())
+            self._grid_rows[key] = xy
+        return xy[0], xy[1], xy[2] + float(np.float32(depth))
+
+    def _ray_pressure_rows(self, q: torch.Tensor, f: float, depth: float, tilt: float, tgt=None) -> torch.Tensor:
         cfg, b = self.cfg, self.cfg.box
         xs = rsi.rsi_sample_disc(0, cfg.n_carrier, b.radius, (0.0, 0.0, 0.0), tilt)
         T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), (math.sin(tilt), 0.0, math.cos(tilt)))
-        phi = rsi.rsi_ray_field(T, [depth], b.media, self._targets(q), [f], rsi.RSI_FP32)[0]
+        phi = rsi.rsi_ray_field(T, [depth], b.media, self._targets(q) if tgt is None else tgt, [f],
+                                rsi.RSI_FP32)[0]
         return rsi.rsi_to_pressure(phi, b.media[1][1], f)
 
     def ray_reference(self, f: float, depth: float, tilt: float) -> torch.Tensor:
@@ -354,8 +366,9 @@ class FieldSource:
             def points():
                 rx, rz = self._ref_xz()
                 return np.concatenate([self.xg, rx]), np.concatenate([self.zg, rz])
-            q = self._fill(self._rows("image+reference", points), f, depth, tilt)
-            p = self._ray_pressure_rows(q, f, depth, tilt)
+            base = self._rows("image+reference", points)
+            p = self._ray_pressure_rows(self._fill(base, f, depth, tilt), f, depth, tilt,
+                                        tgt=self._grid_targets("image+reference", base, depth))
             return p[:self.xg.size], p[self.xg.size:]
         rx, rz = self._ref_xz()
         xg, zg = xz

@@ -254,6 +254,35 @@ rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_w, const do
                             double freq, rsi_kernel kind, rsi_precision prec, uint32_t flags,
                             void *out, void *stream);
 
+/* Size in bytes of the fixed device array that rsi_propagate_noalloc works in. */
+#define RSI_NOALLOC_SCRATCH_BYTES (64LL << 20)
+
+/* rsi_propagate_ex for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Arguments, results,
+ * argument errors and the finite check are those of rsi_propagate_ex; the caller still
+ * passes the inputs and the output.  The call allocates and frees nothing: its workspace
+ * comes from one file-scope device array of RSI_NOALLOC_SCRATCH_BYTES (64 MiB) inside
+ * the library, one copy per device, reserved when the library's code is loaded on that
+ * device and held until the process ends.  Workspace, in 256-byte aligned pieces:
+ *   FP32: 256 (finite-check flag) + 256 (anchor) + 3072 (extents) + 32 n_src (records)
+ *         + 8 n_tgt per source split (partial sums);
+ *   FP64: 256 (flag) + 64 n_src (records) + 16 n_tgt per source split.
+ * When the partial sums of rsi_propagate_ex's launch would not fit, the call uses fewer
+ * source splits (down to one, which needs none), so its results may differ from
+ * rsi_propagate_ex's by rounding only.  RSI_ERR_SIZE, before anything is enqueued and
+ * with rsi_last_error giving the sizes, if the records alone do not fit: more than
+ * 2,097,040 sources in FP32 or 1,048,572 in FP64.
+ * Every call on one device shares that device's array, and each call overwrites what the
+ * previous one left there (nothing in it is assumed to start at zero).  Calls on one
+ * stream are ordered and therefore safe; calls that overlap in time on one device (other
+ * streams, other host threads, graphs replayed concurrently) race on the array and give
+ * wrong results. */
+rsi_status rsi_propagate_noalloc(const rsi_points *src, const double *src_w,
+                                 const double *src_vel, const double *normal,
+                                 const rsi_points *tgt, rsi_medium medium, double freq,
+                                 rsi_kernel kind, rsi_precision prec, uint32_t flags, void *out,
+                                 void *stream);
+
 /* ------------------------------------------------------------------------------
  * a5. The chain (Sec. 2.1 repeated per interface, Sec. 3.4-3.5).
  * ------------------------------------------------------------------------------ */

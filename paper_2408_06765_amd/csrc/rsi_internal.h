@@ -23,6 +23,7 @@ constexpr double kRMin = 1.0e-12;
 constexpr int kBlock = 256;
 
 void set_last_error(const char *what, hipError_t e);
+void set_last_error_text(const std::string &text);
 
 #define RSI_HIP(call)                                                   \
     do {                                                                \
@@ -44,11 +45,13 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 // Debug check of device inputs (rsi_set_check_finite): RSI_ERR_NONFINITE if any of the
 // given arrays (device pointer, element count; null pointers and empty arrays skipped)
 // holds a NaN or an infinity; RSI_OK at once when the check is off.  Synchronises s.
+// flag: a device int the check may use, or NULL to take one from the stream-ordered
+// allocator.
 struct DevSpan {
     const double *p;
     int64_t n;
 };
-rsi_status check_finite(hipStream_t s, const std::vector<DevSpan> &arrays);
+rsi_status check_finite(hipStream_t s, const std::vector<DevSpan> &arrays, int *flag = nullptr);
 inline void add_points(std::vector<DevSpan> &v, const rsi_points &p) {
     v.push_back({p.x, p.n});
     v.push_back({p.y, p.n});
@@ -211,6 +214,12 @@ int64_t partial_slots(const PairShape &sh, int64_t n_src, int64_t n_tgt);
 rsi_status pairsum_f32(const SrcSetF &set, const Targets &t, rsi_kernel kind,
                        const double *normal, double c, double freq, const PairShape &sh,
                        float2 *partial, float2 *out, hipStream_t s, bool planar_z = false);
+// Argument checks shared by the single-frequency and multi-frequency pair-sum entry
+// points (freq: the first frequency); RSI_OK also for tgt->n == 0.
+rsi_status validate_propagate(const rsi_points *src, const double *src_w, const double *src_vel,
+                              const double *normal, const rsi_points *tgt, rsi_medium medium,
+                              double freq, rsi_kernel kind, rsi_precision prec, uint32_t flags,
+                              void *out);
 rsi_status pairsum_f64(const SrcSetD &set, const Targets &t, rsi_kernel kind,
                        const double *normal, double c, double freq, const PairShape &sh,
                        double2 *partial, double2 *out, hipStream_t s);

@@ -28,6 +28,8 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
+#include <string>
 
 #include "rsi_device.h"
 
@@ -523,11 +525,10 @@ rsi_status pairsum_f64(const SrcSetD &set, const Targets &t, rsi_kernel kind,
 
 using namespace rsi;
 
-extern "C" rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_w,
-                                       const double *src_vel, const double *normal,
-                                       const rsi_points *tgt, rsi_medium medium, double freq,
-                                       rsi_kernel kind, rsi_precision prec, uint32_t flags,
-                                       void *out, void *stream) {
+rsi_status rsi::validate_propagate(const rsi_points *src, const double *src_w,
+                                   const double *src_vel, const double *normal,
+                                   const rsi_points *tgt, rsi_medium medium, double freq,
+                                   rsi_kernel kind, rsi_precision prec, uint32_t flags, void *out) {
     if ((flags & ~(uint32_t)RSI_FLAG_PLANAR_Z) != 0) return RSI_ERR_ARG;
     const bool planar = (flags & RSI_FLAG_PLANAR_Z) != 0;
     if (!src || !tgt) return RSI_ERR_NULL;
@@ -545,47 +546,178 @@ extern "C" rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_
         if (!(l2 > 0.0) || !std::isfinite(l2)) return RSI_ERR_ARG;
         if (planar && (normal[0] != 0.0 || normal[1] != 0.0)) return RSI_ERR_ARG;
     }
-    hipStream_t s = as_stream(stream);
+    return RSI_OK;
+}
+
+namespace {
+
+// Workspace of a one-shot pair sum drawn from the stream-ordered allocator.
+struct PoolWorkspace {
+    Scratch scratch;
+    explicit PoolWorkspace(hipStream_t s) : scratch(s) {}
+    template <class T>
+    rsi_status alloc(T **p, size_t count) { return scratch.alloc(p, count); }
+    size_t left() const { return SIZE_MAX; }
+};
+
+// Workspace carved out of a fixed device array: 256-byte aligned pieces, no allocation.
+struct ArenaWorkspace {
+    char *base;
+    size_t cap, used = 0;
+    static size_t piece(size_t bytes) { return (bytes + 255) / 256 * 256; }
+    template <class T>
+    rsi_status alloc(T **p, size_t count) {
+        const size_t bytes = piece(sizeof(T) * (count > 0 ? count : 1));
+        if (bytes > cap - used) {
+            *p = nullptr;
+            set_last_error_text("rsi_propagate_noalloc: the call needs more than the " +
+                                std::to_string((long long)cap) + "-byte scratch array");
+            return RSI_ERR_SIZE;
+        }
+        *p = reinterpret_cast<T *>(base + used);
+        used += bytes;
+        return RSI_OK;
+    }
+    size_t left() const { return cap - used; }
+};
+
+// Lower the split count of `sh` until its partials ([splits][n_tgt] of elem bytes) fit
+// in `bytes`; one split needs no partials.  Sources per split stay a multiple of kSub.
+void fit_partials(PairShape &sh, int64_t n_src, int64_t n_tgt, size_t elem, size_t bytes) {
+    if (partial_slots(sh, n_src, n_tgt) * (int64_t)elem <= (int64_t)bytes) return;
+    const int64_t most = (int64_t)(bytes / 256 * 256 / elem) / (n_tgt > 0 ? n_tgt : 1);
+    int64_t chunk = n_src;
+    if (most >= 2) chunk = ((n_src + most - 1) / most + kSub - 1) / kSub * kSub;
+    while (chunk < n_src && partial_slots(PairShape{sh.tpl, chunk, sh.few}, n_src, n_tgt) * (int64_t)elem >
+                                (int64_t)(bytes / 256 * 256))
+        chunk += kSub;
+    sh.chunk = chunk < n_src ? chunk : (n_src > 0 ? n_src : kSub);
+}
+
+// The pair sum of rsi_propagate_ex after validation, its workspace taken from `ws`
+// (records, anchor and extents first, then the split partials, whose split count is
+// lowered to what is left when `fit` is set).
+template <class Workspace>
+rsi_status propagate_impl(const rsi_points *src, const double *src_w, const double *src_vel,
+                          const double *normal, const rsi_points *tgt, rsi_medium medium,
+                          double freq, rsi_kernel kind, rsi_precision prec, uint32_t flags,
+                          void *out, hipStream_t s, Workspace &ws, bool fit) {
+    const bool planar = (flags & RSI_FLAG_PLANAR_Z) != 0;
     {
         std::vector<DevSpan> in;
         add_points(in, *src);
         in.push_back({src_w, src->n});
         in.push_back({src_vel, 2 * src->n});
         add_points(in, *tgt);
-        RSI_TRY(check_finite(s, in));
+        int *flag = nullptr;
+        if (fit) RSI_TRY(ws.alloc(&flag, 1));
+        RSI_TRY(check_finite(s, in, flag));
     }
-    Scratch scratch(s);
     const Targets t{tgt->x, tgt->y, tgt->z, tgt->n};
     // RSI_OMNI = the monopole sum of strengths times ik
     const Cplx F = kind == RSI_OMNI ? Cplx{0.0, kTwoPi * freq / medium.c} : Cplx{1.0, 0.0};
     const rsi_kernel kk = kind == RSI_OMNI ? RSI_MONOPOLE : kind;
-    const PairShape sh = default_shape(src->n, tgt->n, prec == RSI_FP32 ? kFewWaves / 8 : 0);
-    const int64_t nslots = partial_slots(sh, src->n, tgt->n);
+    PairShape sh = default_shape(src->n, tgt->n, prec == RSI_FP32 ? kFewWaves / 8 : 0);
     if (prec == RSI_FP32) {
         SrcSetF set;
         double *partials = nullptr;
         float2 *partial = nullptr;
         if (src->n > 0) {
-            RSI_TRY(scratch.alloc(&set.rec, (size_t)src->n));
-            RSI_TRY(scratch.alloc(&set.anchor, 4));
-            RSI_TRY(scratch.alloc(&partials, kBBoxBlocks * 6));
+            RSI_TRY(ws.alloc(&set.rec, (size_t)src->n));
+            RSI_TRY(ws.alloc(&set.anchor, 4));
+            RSI_TRY(ws.alloc(&partials, kBBoxBlocks * 6));
+        }
+        if (fit) fit_partials(sh, src->n, tgt->n, sizeof(float2), ws.left());
+        const int64_t nslots = partial_slots(sh, src->n, tgt->n);
+        if (nslots > 0) RSI_TRY(ws.alloc(&partial, (size_t)nslots));
+        if (src->n > 0) {
             RSI_TRY(bbox_partials(*src, partials, s));
             RSI_TRY(prep_sources_f32(*src, src_w, src_vel, 0.0, normal, partials, medium.c / freq, F,
                                      set, s));
         }
-        if (nslots > 0) RSI_TRY(scratch.alloc(&partial, (size_t)nslots));
         return pairsum_f32(set, t, kk, normal, medium.c, freq, sh, partial,
                            static_cast<float2 *>(out), s, planar);
     }
     SrcSetD set;
     double2 *partial = nullptr;
-    if (src->n > 0) {
-        RSI_TRY(scratch.alloc(&set.rec, (size_t)src->n));
-        RSI_TRY(prep_sources_f64(*src, src_w, src_vel, 0.0, F, set, s));
-    }
-    if (nslots > 0) RSI_TRY(scratch.alloc(&partial, (size_t)nslots));
+    if (src->n > 0) RSI_TRY(ws.alloc(&set.rec, (size_t)src->n));
+    if (fit) fit_partials(sh, src->n, tgt->n, sizeof(double2), ws.left());
+    const int64_t nslots = partial_slots(sh, src->n, tgt->n);
+    if (nslots > 0) RSI_TRY(ws.alloc(&partial, (size_t)nslots));
+    if (src->n > 0) RSI_TRY(prep_sources_f64(*src, src_w, src_vel, 0.0, F, set, s));
     return pairsum_f64(set, t, kk, normal, medium.c, freq, sh, partial,
                        static_cast<double2 *>(out), s);
+}
+
+}  // namespace
+
+extern "C" rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_w,
+                                       const double *src_vel, const double *normal,
+                                       const rsi_points *tgt, rsi_medium medium, double freq,
+                                       rsi_kernel kind, rsi_precision prec, uint32_t flags,
+                                       void *out, void *stream) {
+    RSI_TRY(validate_propagate(src, src_w, src_vel, normal, tgt, medium, freq, kind, prec, flags, out));
+    if (tgt->n == 0) return RSI_OK;
+    hipStream_t s = as_stream(stream);
+    PoolWorkspace ws(s);
+    return propagate_impl(src, src_w, src_vel, normal, tgt, medium, freq, kind, prec, flags, out, s,
+                          ws, false);
+}
+
+// The fixed workspace of rsi_propagate_noalloc: one copy per device, reserved when the
+// library's code object is loaded there.  Host code never uses its name as an address:
+// the per-device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[RSI_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<char *> g_scratch_addr;  // indexed by device
+
+// Device address of `scratch` on the current device, looked up once per device with that
+// device current.
+rsi_status scratch_address(char **addr) {
+    int dev = 0;
+    RSI_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        RSI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_last_error_text("hipGetSymbolAddress(scratch) returned NULL");
+            return RSI_ERR_DEVICE;
+        }
+        g_scratch_addr[dev] = static_cast<char *>(p);
+    }
+    *addr = g_scratch_addr[dev];
+    return RSI_OK;
+}
+}  // namespace
+
+extern "C" rsi_status rsi_propagate_noalloc(const rsi_points *src, const double *src_w,
+                                            const double *src_vel, const double *normal,
+                                            const rsi_points *tgt, rsi_medium medium, double freq,
+                                            rsi_kernel kind, rsi_precision prec, uint32_t flags,
+                                            void *out, void *stream) {
+    RSI_TRY(validate_propagate(src, src_w, src_vel, normal, tgt, medium, freq, kind, prec, flags, out));
+    if (tgt->n == 0) return RSI_OK;
+    // the records alone must fit (the flag, anchor and extents take 4 KiB)
+    const int64_t rec_bytes = prec == RSI_FP32 ? (int64_t)sizeof(SrcRecF) : (int64_t)sizeof(SrcRecD);
+    const int64_t fixed = prec == RSI_FP32 ? 256 + 256 + (int64_t)ArenaWorkspace::piece(kBBoxBlocks * 6 * 8)
+                                           : 256;
+    if (src->n > (RSI_NOALLOC_SCRATCH_BYTES - fixed) / rec_bytes) {
+        set_last_error_text("rsi_propagate_noalloc: " + std::to_string((long long)src->n) +
+                            " sources need " + std::to_string((long long)(src->n * rec_bytes + fixed)) +
+                            " bytes of scratch; the array holds " +
+                            std::to_string((long long)RSI_NOALLOC_SCRATCH_BYTES));
+        return RSI_ERR_SIZE;
+    }
+    hipStream_t s = as_stream(stream);
+    char *base = nullptr;
+    RSI_TRY(scratch_address(&base));
+    ArenaWorkspace ws{base, (size_t)RSI_NOALLOC_SCRATCH_BYTES};
+    return propagate_impl(src, src_w, src_vel, normal, tgt, medium, freq, kind, prec, flags, out, s,
+                          ws, true);
 }
 
 extern "C" rsi_status rsi_propagate(const rsi_points *src, const double *src_w,

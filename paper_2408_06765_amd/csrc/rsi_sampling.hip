@@ -32,11 +32,10 @@ __global__ void __launch_bounds__(64) clear_flag_kernel(int *__restrict__ flag) 
     if (threadIdx.x == 0) flag[0] = 0;
 }
 
-rsi_status check_finite(hipStream_t s, const std::vector<DevSpan> &arrays) {
+rsi_status check_finite(hipStream_t s, const std::vector<DevSpan> &arrays, int *flag) {
     if (!__atomic_load_n(&g_check_finite, __ATOMIC_RELAXED)) return RSI_OK;
     Scratch scratch(s);
-    int *flag = nullptr;
-    RSI_TRY(scratch.alloc(&flag, 1));
+    if (!flag) RSI_TRY(scratch.alloc(&flag, 1));
     hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(64), 0, s, flag);
     RSI_HIP(hipGetLastError());
     for (const DevSpan &a : arrays) {
@@ -55,6 +54,8 @@ rsi_status check_finite(hipStream_t s, const std::vector<DevSpan> &arrays) {
 void set_last_error(const char *what, hipError_t e) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
 }
+
+void set_last_error_text(const std::string &text) { g_last_error = text; }
 
 // Coordinate seeds: MurmurHash3 32-bit finaliser of seed + golden-ratio step.
 __host__ __device__ inline uint32_t fmix32(uint32_t h) {

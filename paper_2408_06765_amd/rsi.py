@@ -173,6 +173,25 @@ def rsi_propagate_ex(src, w: torch.Tensor, vel: torch.Tensor, tgt, c: float, fre
     return out
 
 
+def rsi_propagate_noalloc(src, w: torch.Tensor, vel: torch.Tensor, tgt, c: float, freq: float,
+                          kind: int, prec: int, flags: int, out: torch.Tensor, normal=None,
+                          rho: float = 1000.0) -> torch.Tensor:
+    """rsi_propagate_ex with its workspace in the library's fixed device array (no device
+    allocation); `out` is required so that the call allocates nothing."""
+    sp = _points(*src, "src")
+    tp = _points(*tgt, "tgt")
+    _dev(w, torch.float64, "w")
+    _dev(vel, torch.complex128, "vel")
+    _dev(out, _OUT_DTYPE[prec], "out")
+    if out.numel() != tp.n:
+        raise ValueError("out must hold one value per field point")
+    nrm = _dvec(normal) if normal is not None else None
+    L.check(L.load().rsi_propagate_noalloc(C.byref(sp), _ptr(w), _ptr(vel), nrm, C.byref(tp),
+                                           L.rsi_medium(c, rho), freq, kind, prec, flags, _ptr(out),
+                                           _stream()), "rsi_propagate_noalloc")
+    return out
+
+
 # ---------------------------------------------------------------------------- a5
 @dataclass
 class Transducer:

@@ -108,8 +108,8 @@ const char *rsi_last_error(void);
 int rsi_version(void);
 
 /* Input check for debugging: with enable != 0 the pair-sum entry points (rsi_propagate,
- * rsi_propagate_ex, rsi_chain, rsi_chain_ex, rsi_ray_field, rsi_propagate_batched and the
- * plan constructors) scan their device inputs -- coordinates, weights, complex strengths,
+ * rsi_propagate_ex, rsi_propagate_multifreq, rsi_propagate_noalloc, rsi_chain, rsi_chain_ex,
+ * rsi_ray_field, rsi_propagate_batched and the plan constructors) scan their device inputs -- coordinates, weights, complex strengths,
  * interface samples, field points -- and return RSI_ERR_NONFINITE, launching nothing, if
  * any value is NaN or infinite.  The scan costs one pass over the inputs and a stream
  * synchronisation, so it is off by default and must not be used on a stream under graph
@@ -253,6 +253,25 @@ rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_w, const do
                             const double *normal, const rsi_points *tgt, rsi_medium medium,
                             double freq, rsi_kernel kind, rsi_precision prec, uint32_t flags,
                             void *out, void *stream);
+
+/* The pair sum of rsi_propagate_ex for many frequencies in one call (multi-frequency
+ * superposition, Sec. 4): out[q][i] is phi at field point i for frequency freqs[q] (host
+ * double[n_freq]) with the strengths src_vel[q][j] (device complex FP64 [n_freq][src->n],
+ * frequency-major; NULL: 1 for every source and frequency); medium, kind, normal and flags
+ * as in rsi_propagate_ex.  out: device complex [n_freq][tgt->n] of the call's precision.
+ * With RSI_FP32 on a uniform grid (n_freq >= 2, f_q = f_0 + q df) and a monopole or
+ * omnidirectional kernel, or a dipole with RSI_FLAG_PLANAR_Z (normal +z or -z), the call
+ * is one multi-frequency launch: the pair geometry is evaluated once per block of 16
+ * frequencies and e^{ikr} is carried from one frequency to the next; every other case
+ * (RSI_FP64, a non-uniform list, a dipole with any other normal) runs one pair sum per
+ * frequency.  Errors: those of rsi_propagate_ex; RSI_ERR_ARG for a frequency <= 0 or not
+ * finite; RSI_ERR_NULL for freqs == NULL with n_freq > 0; RSI_ERR_SIZE for n_freq < 0 or
+ * n_freq * tgt->n > 2^38.  n_freq = 0 enqueues nothing. */
+rsi_status rsi_propagate_multifreq(const rsi_points *src, const double *src_w,
+                                   const double *src_vel, const double *normal,
+                                   const rsi_points *tgt, rsi_medium medium, const double *freqs,
+                                   int n_freq, rsi_kernel kind, rsi_precision prec, uint32_t flags,
+                                   void *out, void *stream);
 
 /* Size in bytes of the fixed device array that rsi_propagate_noalloc works in. */
 #define RSI_NOALLOC_SCRATCH_BYTES (64LL << 20)

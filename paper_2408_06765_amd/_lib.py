@@ -65,6 +65,9 @@ SIGNATURES = {
     "rsi_propagate_ex": ([C.POINTER(rsi_points), C.c_void_p, C.c_void_p, _dp, C.POINTER(rsi_points),
                           rsi_medium, C.c_double, C.c_int, C.c_int, C.c_uint32, C.c_void_p,
                           C.c_void_p], C.c_int),
+    "rsi_propagate_multifreq": ([C.POINTER(rsi_points), C.c_void_p, C.c_void_p, _dp,
+                                 C.POINTER(rsi_points), rsi_medium, _dp, C.c_int, C.c_int, C.c_int,
+                                 C.c_uint32, C.c_void_p, C.c_void_p], C.c_int),
     "rsi_propagate_noalloc": ([C.POINTER(rsi_points), C.c_void_p, C.c_void_p, _dp,
                                C.POINTER(rsi_points), rsi_medium, C.c_double, C.c_int, C.c_int,
                                C.c_uint32, C.c_void_p, C.c_void_p], C.c_int),

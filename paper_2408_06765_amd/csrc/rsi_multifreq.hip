@@ -1,5 +1,5 @@
-// rsi_multifreq.hip -- one stage of the chain for many frequencies in one launch
-// (multi-frequency superposition, Sec. 4), FP32 path.
+// rsi_multifreq.hip -- one pair sum (a stage of the chain, or rsi_propagate_multifreq)
+// for many frequencies in one launch (multi-frequency superposition, Sec. 4), FP32 path.
 //
 // On a uniform grid f_q = f_0 + q df the phase of a pair is linear in q:
 //     r f_q / c = r f_b / c + (q - q_b) r df / c,
@@ -132,6 +132,36 @@ __global__ void __launch_bounds__(256) strength_multifreq_kernel(
     S[g] = r;
 }
 
+// S[j][q] = -(1/2pi) w_j v_q(j) (Fa + i Fb k_q) for q < n_freq, 0 for the padding, with the
+// caller's complex FP64 strengths v [n_freq][n] (v = 1 when vel is NULL),
+// k_q = 2 pi (f0 + q df) / c.
+__global__ void __launch_bounds__(256) strength_vel_multifreq_kernel(
+    int64_t n, int n_freq, int nf_pad, const double *__restrict__ w, const double *__restrict__ vel,
+    double Fa, double Fb, double c, double f0, double df, float2 *__restrict__ S) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n * nf_pad) return;
+    const int64_t j = g / nf_pad;
+    const int q = (int)(g - j * nf_pad);
+    float2 r = make_float2(0.0f, 0.0f);
+    if (q < n_freq) {
+        double vre = 1.0, vim = 0.0;
+        if (vel) {
+            vre = vel[2 * ((int64_t)q * n + j)];
+            vim = vel[2 * ((int64_t)q * n + j) + 1];
+        }
+        const double scale = -w[j] / kTwoPi;
+        const double Fi = Fb * kTwoPi * (f0 + q * df) / c;
+        r.x = (float)(scale * (vre * Fa - vim * Fi));
+        r.y = (float)(scale * (vre * Fi + vim * Fa));
+    }
+    S[g] = r;
+}
+
+__global__ void __launch_bounds__(256) zero_f2_kernel(int64_t n, float2 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = make_float2(0.0f, 0.0f);
+}
+
 bool uniform_grid(const double *freqs, int n, double &f0, double &df) {
     if (n < 2) return false;
     f0 = freqs[0];
@@ -187,3 +217,118 @@ rsi_status pairsum_multifreq_f32(const SrcSetF &set, const float2 *S, const Targ
 }
 
 }  // namespace rsi
+
+using namespace rsi;
+
+extern "C" rsi_status rsi_propagate_multifreq(const rsi_points *src, const double *src_w,
+                                              const double *src_vel, const double *normal,
+                                              const rsi_points *tgt, rsi_medium medium,
+                                              const double *freqs, int n_freq, rsi_kernel kind,
+                                              rsi_precision prec, uint32_t flags, void *out,
+                                              void *stream) {
+    if (n_freq < 0) return RSI_ERR_SIZE;
+    if (n_freq == 0) return RSI_OK;
+    if (!freqs) return RSI_ERR_NULL;
+    for (int q = 0; q < n_freq; ++q)
+        if (!(freqs[q] > 0.0) || !std::isfinite(freqs[q])) return RSI_ERR_ARG;
+    // the per-source strengths check of the single-frequency call does not apply: NULL
+    // strengths mean 1 here
+    static const double one[2] = {1.0, 0.0};
+    RSI_TRY(validate_propagate(src, src_w, src_vel ? src_vel : one, normal, tgt, medium, freqs[0], kind,
+                               prec, flags, out));
+    if (tgt->n == 0) return RSI_OK;
+    if ((int64_t)n_freq * tgt->n > ((int64_t)1 << 38)) return RSI_ERR_SIZE;
+    hipStream_t s = as_stream(stream);
+    {
+        std::vector<DevSpan> in;
+        add_points(in, *src);
+        in.push_back({src_w, src->n});
+        if (src_vel) in.push_back({src_vel, 2 * (int64_t)n_freq * src->n});
+        add_points(in, *tgt);
+        RSI_TRY(check_finite(s, in));
+    }
+    const bool planar = (flags & RSI_FLAG_PLANAR_Z) != 0;
+    // a dipole along -z is the +z dipole with the strengths negated (linear in the normal)
+    bool z_normal = false;
+    double sign = 1.0;
+    if (kind == RSI_DIPOLE) {
+        z_normal = normal[0] == 0.0 && normal[1] == 0.0;
+        sign = normal[2] < 0.0 ? -1.0 : 1.0;
+    }
+    const rsi_kernel kk = kind == RSI_OMNI ? RSI_MONOPOLE : kind;
+    const Targets t{tgt->x, tgt->y, tgt->z, tgt->n};
+    Scratch scratch(s);
+    double f0 = 0.0, df = 0.0;
+    if (prec == RSI_FP32 && uniform_grid(freqs, n_freq, f0, df) && (kind != RSI_DIPOLE || (planar && z_normal))) {
+        const int nfb = (n_freq + kFB - 1) / kFB;
+        if (nfb > 65535) return RSI_ERR_SIZE;
+        SrcSetF set;
+        double *partials = nullptr;
+        float2 *S = nullptr;
+        // one real strength shared by every frequency when the strengths are all 1 and the
+        // kernel has no per-frequency factor; otherwise per-frequency strengths
+        const bool shared = !src_vel && kind != RSI_OMNI;
+        if (src->n > 0) {
+            RSI_TRY(scratch.alloc(&set.rec, (size_t)src->n));
+            RSI_TRY(scratch.alloc(&set.anchor, 4));
+            RSI_TRY(scratch.alloc(&partials, kBBoxBlocks * 6));
+            if (!shared) RSI_TRY(scratch.alloc(&S, (size_t)src->n * nfb * kFB));
+            RSI_TRY(bbox_partials(*src, partials, s));
+            RSI_TRY(prep_sources_f32(*src, src_w, nullptr, shared ? sign : 0.0, kind == RSI_DIPOLE ? normal : nullptr,
+                                     partials, 0.0, Cplx{1.0, 0.0}, set, s));
+            if (!shared) {
+                const int64_t total = src->n * (int64_t)nfb * kFB;
+                hipLaunchKernelGGL(strength_vel_multifreq_kernel, dim3((unsigned)((total + 255) / 256)),
+                                   dim3(256), 0, s, src->n, n_freq, nfb * kFB, src_w, src_vel,
+                                   kind == RSI_OMNI ? 0.0 : sign, kind == RSI_OMNI ? 1.0 : 0.0, medium.c,
+                                   f0, df, S);
+                RSI_HIP(hipGetLastError());
+            }
+        }
+        if (src->n == 0) {
+            const int64_t total = (int64_t)n_freq * tgt->n;
+            hipLaunchKernelGGL(zero_f2_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total,
+                               static_cast<float2 *>(out));
+            RSI_HIP(hipGetLastError());
+            return RSI_OK;
+        }
+        return pairsum_multifreq_f32(set, S, t, kk, planar, medium.c, f0, df, n_freq,
+                                     static_cast<float2 *>(out), s);
+    }
+    // one pair sum per frequency, strengths of frequency q from src_vel + q n
+    const PairShape sh = default_shape(src->n, tgt->n, prec == RSI_FP32 ? kFewWaves / 8 : 0);
+    const int64_t nslots = partial_slots(sh, src->n, tgt->n);
+    const size_t esz = prec == RSI_FP32 ? sizeof(float2) : sizeof(double2);
+    SrcSetF setf;
+    SrcSetD setd;
+    double *partials = nullptr;
+    void *partial = nullptr;
+    if (src->n > 0) {
+        if (prec == RSI_FP32) {
+            RSI_TRY(scratch.alloc(&setf.rec, (size_t)src->n));
+            RSI_TRY(scratch.alloc(&setf.anchor, 4));
+            RSI_TRY(scratch.alloc(&partials, kBBoxBlocks * 6));
+            RSI_TRY(bbox_partials(*src, partials, s));
+        } else {
+            RSI_TRY(scratch.alloc(&setd.rec, (size_t)src->n));
+        }
+    }
+    if (nslots > 0) RSI_TRY(scratch.alloc((char **)&partial, esz * (size_t)nslots));
+    for (int q = 0; q < n_freq; ++q) {
+        const double *vq = src_vel ? src_vel + 2 * (int64_t)q * src->n : nullptr;
+        const Cplx F = kind == RSI_OMNI ? Cplx{0.0, kTwoPi * freqs[q] / medium.c} : Cplx{1.0, 0.0};
+        char *out_q = static_cast<char *>(out) + esz * (size_t)q * (size_t)tgt->n;
+        if (prec == RSI_FP32) {
+            if (src->n > 0)
+                RSI_TRY(prep_sources_f32(*src, src_w, vq, 1.0, normal, partials, medium.c / freqs[q], F,
+                                         setf, s));
+            RSI_TRY(pairsum_f32(setf, t, kk, normal, medium.c, freqs[q], sh, static_cast<float2 *>(partial),
+                                reinterpret_cast<float2 *>(out_q), s, planar));
+        } else {
+            if (src->n > 0) RSI_TRY(prep_sources_f64(*src, src_w, vq, 1.0, F, setd, s));
+            RSI_TRY(pairsum_f64(setd, t, kk, normal, medium.c, freqs[q], sh, static_cast<double2 *>(partial),
+                                reinterpret_cast<double2 *>(out_q), s));
+        }
+    }
+    return RSI_OK;
+}

@@ -173,6 +173,30 @@ def rsi_propagate_ex(src, w: torch.Tensor, vel: torch.Tensor, tgt, c: float, fre
     return out
 
 
+def rsi_propagate_multifreq(src, w: torch.Tensor, vel: Optional[torch.Tensor], tgt, c: float, freqs,
+                            kind: int, prec: int, flags: int = 0, normal=None, rho: float = 1000.0,
+                            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """phi at the targets for every frequency, complex [n_freq, n_tgt]; vel: complex128
+    [n_freq, n_src] per-frequency strengths, or None for 1 everywhere."""
+    sp = _points(*src, "src")
+    tp = _points(*tgt, "tgt")
+    _dev(w, torch.float64, "w")
+    freqs = [float(f) for f in freqs]
+    if vel is not None:
+        _dev(vel, torch.complex128, "vel")
+        if vel.numel() != len(freqs) * sp.n:
+            raise ValueError("vel must hold n_freq x n_src strengths")
+    if out is None:
+        out = torch.empty((len(freqs), tp.n), dtype=_OUT_DTYPE[prec], device=tgt[0].device)
+    _dev(out, _OUT_DTYPE[prec], "out")
+    nrm = _dvec(normal) if normal is not None else None
+    L.check(L.load().rsi_propagate_multifreq(C.byref(sp), _ptr(w), _ptr(vel), nrm, C.byref(tp),
+                                             L.rsi_medium(c, rho), _dvec(freqs) if freqs else None,
+                                             len(freqs), kind, prec, flags, _ptr(out), _stream()),
+            "rsi_propagate_multifreq")
+    return out
+
+
 def rsi_propagate_noalloc(src, w: torch.Tensor, vel: torch.Tensor, tgt, c: float, freq: float,
                           kind: int, prec: int, flags: int, out: torch.Tensor, normal=None,
                           rho: float = 1000.0) -> torch.Tensor:

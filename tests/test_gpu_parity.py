@@ -284,6 +284,66 @@ def test_layered_chain_three_frequencies(gpu, orc, prec):
         assert rel(got[f], ref[f]) <= TOL[prec], (f, rel(got[f], ref[f]))
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_chain_nonuniform_frequency_list(gpu, orc, prec):
+    """A frequency list that is not a uniform grid (multi-frequency superposition, Sec. 4):
+    the chain runs stage by stage for each frequency; every frequency of 1.0, 2.2, 2.9,
+    7.3 MHz through the three-interface stack against the reference."""
+    cfg = W.LayeredStack()
+    xd, ifs, tgt = _small_chain(orc, 1 << 12, cfg.z_if, cfg.media, cfg.tilt, 600, seed=5)
+    freqs = [1.0e6, 2.2e6, 2.9e6, 7.3e6]
+    ref = orc.chain(xd, 1.0, (0, 0, 0), cfg.axis, ifs, list(cfg.z_if), [m[0] for m in cfg.media],
+                    [m[1] for m in cfg.media], tgt, freqs, 1)
+    got = _gpu_chain(gpu, xd, ifs, cfg.z_if, cfg.media, tgt, freqs, 1, prec, cfg.axis)
+    for f in range(len(freqs)):
+        assert rel(got[f], ref[f]) <= TOL[prec], (f, rel(got[f], ref[f]))
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2])
+def test_chain_uniform_grid_ragged_block(gpu, orc, flags):
+    """A uniform grid of 20 frequencies, 1-10 MHz: the FP32 multi-frequency stages run one
+    full block of 16 frequencies and a ragged second block of 4 (zero-padded strengths,
+    outputs masked).  Plain chain, omnidirectional interface sources, and field points
+    above the last interface with the reflected field; every frequency against the
+    reference."""
+    cfg = W.LayeredStack()
+    xd, ifs, tgt = _small_chain(orc, 1 << 11, cfg.z_if, cfg.media, cfg.tilt, 500, seed=6)
+    if flags & 2:
+        tgt = _above_targets(ifs, cfg.z_if, 500, 19)
+    freqs = list(np.linspace(1.0e6, 10.0e6, 20))
+    ref = orc.chain(xd, 1.0, (0, 0, 0), cfg.axis, ifs, list(cfg.z_if), [m[0] for m in cfg.media],
+                    [m[1] for m in cfg.media], tgt, freqs, 1, flags=flags)
+    T = gpu.Transducer(*devpts(xd[:3]), dev(xd[3]), 1.0, (0.0, 0.0, 0.0), cfg.axis)
+    I = [gpu.Interface(*devpts(q[:3]), dev(q[3]), z) for q, z in zip(ifs, cfg.z_if)]
+    got = host(gpu.rsi_chain(T, I, cfg.media, devpts(tgt), freqs, 1, 0, flags=flags))
+    assert got.shape == (20, len(tgt[0]))
+    for f in range(len(freqs)):
+        assert rel(got[f], ref[f]) <= TOL[0], (f, rel(got[f], ref[f]))
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_fp64_field_point_on_a_source(gpu, orc, kind):
+    """The kernel is singular on the radiating surface (Sec. 3.2): the FP64 path drops
+    pairs closer than 1e-12 m.  Field points placed exactly on sources get the sum over
+    the other sources -- the reference with that source removed -- and the output is
+    finite everywhere."""
+    src, w, s, tgt = _case(71, 3000, 400, kind)
+    on = [5, 777, 2999]
+    tgt = tuple(np.concatenate([t, v[on]]) for t, v in zip(tgt, src))
+    got = host(gpu.rsi_propagate(devpts(src), dev(w), dev(s), devpts(tgt), 1480.0, 2.0e6, kind, 1,
+                                 normal=(0.0, 0.0, 1.0)))
+    assert np.all(np.isfinite(got.view(np.float64)))
+    ref = orc.propagate(kind, src, w, s, tgt, 1480.0, 2.0e6, normal=(0.0, 0.0, 1.0))
+    assert rel(got, ref) <= TOL[1]
+    for i, j in enumerate(on):
+        keep = np.arange(len(w)) != j
+        p = tuple(np.array([v[j]]) for v in src)
+        alone = orc.propagate(kind, tuple(v[keep] for v in src), w[keep], s[keep], p, 1480.0, 2.0e6,
+                              normal=(0.0, 0.0, 1.0))
+        k = len(tgt[0]) - len(on) + i
+        assert abs(got[k] - alone[0]) <= 1e-10 * abs(alone[0]), (j, got[k], alone[0])
+
+
 def _above_targets(ifs, zs, n, seed):
     """Field points in the medium above the last interface (between it and the one
     before, or the transducer)."""
@@ -380,6 +440,53 @@ def test_piston_axis_workload(gpu, orc):
 
 
 # ----------------------------------------------------------------------------- a7
+MF_CASES = [  # (kind, planar, normal z, frequencies, strengths given)
+    (0, False, 1.0, "grid20", True), (0, False, 1.0, "grid20", False), (1, True, 1.0, "grid20", True),
+    (1, True, -1.0, "grid20", True), (1, True, -1.0, "grid3", False), (2, False, 1.0, "grid20", True),
+    (1, False, 1.0, "grid20", True), (1, True, 1.0, "list", True), (0, False, 1.0, "one", True),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind,planar,nz,fr,given", MF_CASES)
+def test_propagate_multifreq_matches_reference(gpu, orc, kind, planar, nz, fr, given, prec):
+    """rsi_propagate_multifreq (multi-frequency superposition, Sec. 4): every frequency
+    against the reference's single-frequency pair sum with that frequency's strengths.
+    FP32 uniform grids with a monopole, omnidirectional or planar +-z dipole kernel run
+    the multi-frequency launch (20 frequencies: a full block of 16 and a ragged one of 4);
+    a general dipole, a non-uniform list and FP64 run one pair sum per frequency."""
+    freqs = {"grid20": list(np.linspace(1.0e6, 10.0e6, 20)), "grid3": [2.0e6, 2.5e6, 3.0e6],
+             "list": [1.0e6, 1.7e6, 4.2e6], "one": [3.3e6]}[fr]
+    ns, nt = 3001, 700
+    src, w, _, tgt = _case(51 + kind, ns, nt, 1 if planar else 0)
+    if planar:
+        src = (src[0], src[1], np.full(ns, 0.004))
+    rng = np.random.default_rng(5)
+    vel = rng.normal(size=(len(freqs), ns)) + 1j * rng.normal(size=(len(freqs), ns)) if given else None
+    normal = (0.0, 0.0, nz)
+    c = 5900.0
+    got = host(gpu.rsi_propagate_multifreq(devpts(src), dev(w), dev(vel) if given else None, devpts(tgt), c,
+                                           freqs, kind, prec, gpu.RSI_FLAG_PLANAR_Z if planar else 0,
+                                           normal=normal))
+    assert got.shape == (len(freqs), nt)
+    for q, f in enumerate(freqs):
+        s = vel[q] if given else np.ones(ns, dtype=complex)
+        ref = orc.propagate(kind, src, w, s, tgt, c, f, normal=normal)
+        assert rel(got[q], ref) <= TOL[prec], (q, rel(got[q], ref))
+
+
+def test_propagate_multifreq_empty_and_errors(gpu):
+    import torch
+    from paper_2408_06765_amd._lib import RSIError
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    tgt = devpts(W.random_cloud(1, 300, (0, 0, 0.02), (0.01, 0.01, 0.01)))
+    out = gpu.rsi_propagate_multifreq((e, e, e), e, None, tgt, 1480.0, [1e6, 2e6, 3e6], 0, 0)
+    assert out.shape == (3, 300) and np.all(host(out) == 0)
+    src, w, s, _ = _case(3, 10, 1, 0)
+    with pytest.raises(RSIError):
+        gpu.rsi_propagate_multifreq(devpts(src), dev(w), None, tgt, 1480.0, [1e6, -2e6], 0, 0)
+
+
 def _instances(gpu, n_inst, prec, seed=0):
     rng = np.random.default_rng(seed)
     insts, refs = [], []

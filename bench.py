@@ -1,18 +1,23 @@
 """Benchmark of the RSI-QMC hot path on one MI355X.
 
-A step is one pass of the whole chained model over the one-interface workload:
-  piston (2^16 Sobol samples, 5 MHz, tilted 10 deg) -> water/solid interface at 50 mm
-  (2^18 samples on a 60 x 60 mm patch, local transmission coefficient) -> 512 x 512
-  image 1-40 mm below the interface, FP32 path (FP64 reference distance and phase).
-  Pairs per step: 2^16 * 2^18 (piston, monopole) + 2^18 * 512^2 (interface, dipole)
-  = 8.59e10.  Inputs (sample points, weights, field points) are resident in HBM
-  before the timed region; the step is one replay of the chain plan (hipGraph).
+A step (the default workload, layered_stack) is one pass of the whole chained model over
+the layered stack, every stage for 64 frequencies at once:
+  piston (2^16 Sobol samples, tilted 10 deg) -> three planar interfaces at 50, 52, 54 mm
+  (2^18 samples each, media c = 1480, 5900, 2700, 5900 m/s, local transmission
+  coefficients) -> 128^3 volume 1-31 mm below the last interface, for 64 frequencies
+  uniformly spanning 1-10 MHz, FP32 path (FP64 reference distance and phase).
+  Pair-frequencies per step: 64 x (2^16 2^18 + 2 x 2^18 2^18 + 2^18 2^21) = 4.51e13.
+  Inputs (sample points, weights, field points) are resident in HBM before the timed
+  region; the step is one replay of the chain plan (hipGraph).
 
-Printed: one JSON line with Gpairs/s, the roofline of the dominant kernel (the
-interface dipole pair sum, timed with HIP events on its own stream) and the FP64
-reference timed on the host cores over a bounded sample of the same workload.
+Printed: one JSON line with G pair-frequencies/s, the roofline of the dominant kernel (the
+multi-frequency dipole pair sum of the last interface onto the volume, timed with HIP
+events on its own stream) and the FP64 reference timed on the host cores over a bounded
+sample of the same stages.  --workload one_interface gives the single-frequency chain
+(piston -> one interface -> 512 x 512 image at 5 MHz) in the same format; the other
+workloads are secondary measurements.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu] [--workload NAME]
 """
 import argparse
 import json
@@ -36,17 +41,18 @@ PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 MFMA
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
-    ap.add_argument("--kernel-reps", type=int, default=5, help="launches for the roofline timing")
+    ap.add_argument("--kernel-reps", type=int, default=None,
+                    help="launches for the roofline timing (default 2 for layered_stack, 5 otherwise)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="one_interface",
-                    choices=["one_interface", "layered_stack", "scan_batch", "surrogate",
+    ap.add_argument("--workload", default="layered_stack",
+                    choices=["layered_stack", "one_interface", "scan_batch", "surrogate",
                              "interface_continuity", "focused_normal", "ray_field",
                              "ray_crossover", "multilayer_noise", "surrogate_inference"],
-                    help="one_interface is the benchmark line; the others are secondary "
+                    help="layered_stack is the benchmark line; the others are secondary "
                          "measurements printed in the same format")
     ap.add_argument("--autotune", action="store_true",
                     help="scan_batch: run the autotuner (writes the cache) before planning")
@@ -59,6 +65,53 @@ def parse():
     ap.add_argument("--fp64-compare", action="store_true",
                     help="layered_stack: FP32 vs FP64 rel-L2 per frequency on a volume subsample")
     return ap.parse_args()
+
+
+def cpu_model():
+    """The host CPU's model name (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline_layered(cfg, target_seconds=15.0):
+    """The FP64 reference, as it stands, on a bounded sample of the layered stack: the
+    three stage kinds at one frequency of the grid (the middle one), each onto m field
+    points -- the piston (2^16 samples) onto interface 1, interface 1 (2^18 samples) onto
+    interface 2, interface 3 (2^18 samples) onto the volume -- with unit strengths.  The
+    reference has no multi-frequency path, so its pair-frequencies per second are its
+    pairs per second."""
+    import oracle
+
+    xd = oracle.sample_disc(cfg.xd_seed, cfg.n_xd, cfg.radius, (0.0, 0.0, 0.0), cfg.tilt)
+    qs = [oracle.sample_square(seed, cfg.n_if, cx, cy, z, cfg.half_width)
+          for seed, (cx, cy), z in zip(cfg.if_seeds, cfg.patch_centres, cfg.z_if)]
+    tx, ty, tz = cfg.targets()
+    rng = np.random.default_rng(0)
+    pick = rng.choice(tx.size, size=tx.size, replace=False)
+    f = float(cfg.freqs[cfg.n_freq // 2])
+    c = [m[0] for m in cfg.media]
+
+    def run(m):
+        t0 = time.perf_counter()
+        oracle.propagate(0, xd[:3], xd[3], 1.0, tuple(a[:m] for a in qs[0][:3]), c[0], f)
+        oracle.propagate(1, qs[0][:3], qs[0][3], 1.0, tuple(a[:m] for a in qs[1][:3]), c[1], f,
+                         normal=(0.0, 0.0, 1.0))
+        oracle.propagate(1, qs[2][:3], qs[2][3], 1.0, (tx[pick[:m]], ty[pick[:m]], tz[pick[:m]]), c[3], f,
+                         normal=(0.0, 0.0, 1.0))
+        return time.perf_counter() - t0, m * (cfg.n_xd + 2 * cfg.n_if)
+    dt, pairs = run(64)
+    m = int(max(64, min(cfg.n_if, target_seconds * pairs / max(dt, 1e-9) / (cfg.n_xd + 2 * cfg.n_if))))
+    dt, pairs = run(m)
+    return {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": oracle.num_threads(),
+            "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": f"one frequency ({f / 1e6:.4f} MHz): piston stage onto {m} interface-1 points, "
+                      f"interface 1 -> {m} interface-2 points, interface 3 -> {m} volume points (2^16 / 2^18 "
+                      f"sources): {pairs:.3e} pairs in {dt:.2f} s"}
 
 
 def cpu_baseline(cfg, target_seconds=12.0):
@@ -85,22 +138,30 @@ def cpu_baseline(cfg, target_seconds=12.0):
     m = int(max(64, min(cfg.n_if, target_seconds * rate / (cfg.n_xd + cfg.n_if))))
     dt, pairs = run(m, m)
     return {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"piston stage onto {m} interface points + interface stage (2^18 sources) onto "
                       f"{m} image points: {pairs:.3e} pairs in {dt:.2f} s"}
 
 
-# What the dominant kernel's HBM traffic depends on: the device header (pair and block
-# loops), the kernel's definition, its shape rule and its launcher in rsi_pairsum.hip, and
-# the record layout and block size in rsi_internal.h.  Host code elsewhere in those files
-# does not invalidate the counters.
-KERNEL_SOURCES = [
-    ("paper_2408_06765_amd/csrc/rsi_device.h", None),
-    ("paper_2408_06765_amd/csrc/rsi_pairsum.hip",
-     ["pairsum_f32_kernel(", "PairShape default_shape(", "rsi_status pairsum_f32("]),
-    ("paper_2408_06765_amd/csrc/rsi_internal.h",
-     ["struct alignas(32) SrcRecF", "constexpr int kBlock", "constexpr int64_t kFewWaves"]),
-]
+# What a kernel's counters depend on, per committed summary: the device header and
+# record layout, the kernel's definition, its shape rule and its launcher.  Host code
+# elsewhere in those files does not invalidate the counters.
+KERNEL_SOURCES = {
+    "pairsum": [
+        ("paper_2408_06765_amd/csrc/rsi_device.h", None),
+        ("paper_2408_06765_amd/csrc/rsi_pairsum.hip",
+         ["pairsum_f32_kernel(", "PairShape default_shape(", "rsi_status pairsum_f32("]),
+        ("paper_2408_06765_amd/csrc/rsi_internal.h",
+         ["struct alignas(32) SrcRecF", "constexpr int kBlock", "constexpr int64_t kFewWaves"]),
+    ],
+    "multifreq": [
+        ("paper_2408_06765_amd/csrc/rsi_device.h", ["constexpr int kSub", "constexpr int kFB"]),
+        ("paper_2408_06765_amd/csrc/rsi_multifreq.hip",
+         ["multifreq_f32_kernel(", "rsi_status pairsum_multifreq_f32("]),
+        ("paper_2408_06765_amd/csrc/rsi_internal.h",
+         ["struct alignas(32) SrcRecF", "constexpr int kBlock"]),
+    ],
+}
 
 
 def _region(text, anchor):
@@ -118,10 +179,10 @@ def _region(text, anchor):
     raise ValueError(anchor)
 
 
-def kernel_sources_digest():
+def kernel_sources_digest(kernel="pairsum"):
     import hashlib
     h = hashlib.sha256()
-    for f, anchors in KERNEL_SOURCES:
+    for f, anchors in KERNEL_SOURCES[kernel]:
         text = open(os.path.join(ROOT, f)).read()
         for part in ([text] if anchors is None else [_region(text, a) for a in anchors]):
             h.update(part.encode())
@@ -130,9 +191,11 @@ def kernel_sources_digest():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairsum_dipole_one_interface_traffic.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "pairsum_valu_counters.md")
+MF_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "multifreq_dipole_layered_stack_traffic.txt")
+MF_VALU_FILE = os.path.join(ROOT, "profiles", "multifreq_valu_counters.md")
 
 
-def _counter_summary(path):
+def _counter_summary(path, kernel="pairsum"):
     """The key: value lines of a committed counter summary, or None when the file is missing
     or the kernel sources changed since its counters were taken."""
     if not os.path.exists(path):
@@ -144,7 +207,7 @@ def _counter_summary(path):
         k, v = line.split(":", 1)
         kv[k.strip()] = v.strip()
     try:
-        digest = kernel_sources_digest()
+        digest = kernel_sources_digest(kernel)
     except (OSError, ValueError):  # a source or an anchor moved: the counters are stale
         return None
     if kv.get("kernel_sources_sha256") != digest:
@@ -152,18 +215,20 @@ def _counter_summary(path):
     return kv
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter summary, or
-    None when the kernel sources changed since the counters were taken."""
-    kv = _counter_summary(TRAFFIC_FILE)
+def measured_traffic(path=None, kernel="pairsum"):
+    """HBM bytes per launch of a kernel from its committed counter summary (default: the
+    single-frequency dipole pair sum's), or None when the summary is missing or the kernel
+    sources changed since the counters were taken."""
+    kv = _counter_summary(path or TRAFFIC_FILE, kernel)
     return None if kv is None else int(float(kv["traffic_bytes_per_launch"]))
 
 
-def measured_valu():
-    """Executed FP32 FLOPs and VALU occupancy of the dominant kernel from the committed VALU
-    counter summary (the metric's "% FP32 VALU peak" as counted by the hardware), or None
-    when the kernel sources changed since the counters were taken."""
-    kv = _counter_summary(VALU_FILE)
+def measured_valu(path=None, kernel="pairsum"):
+    """Executed FP32 FLOPs and VALU occupancy of a kernel from its committed VALU counter
+    summary (the metric's "% FP32 VALU peak" as counted by the hardware), or None when the
+    summary is missing or the kernel sources changed since the counters were taken."""
+    path = path or VALU_FILE
+    kv = _counter_summary(path, kernel)
     if kv is None:
         return None
     return {"executed_tflops": float(kv["dipole_executed_fp32_tflops"]),
@@ -171,7 +236,7 @@ def measured_valu():
             "valu_lane_util_pct": float(kv["dipole_valu_lane_util_pct"]),
             "cu_busy_pct": float(kv["dipole_cu_busy_pct"]),
             "issue_model_frac": float(kv["dipole_issue_model_frac"]),
-            "source": os.path.relpath(VALU_FILE, ROOT)}
+            "source": os.path.relpath(path, ROOT)}
 
 
 def timed(fn, steps, warmup):
@@ -196,8 +261,19 @@ def base_line(metric_value, steps, warmup, dt, config, unit="Gpairs/s"):
     }
 
 
+def flops_multifreq_pair(n_freq, block=16):
+    """Algorithmic FP32 flops of one dipole pair for n_freq frequencies on a uniform grid,
+    evaluated in blocks of `block` (FMA = 2, transcendental = 1): 33 for each block's first
+    frequency (the single-frequency dipole pair) and 21 for each further one (carrying
+    e^{ikr} to the next frequency, the (ik - 1/r) factor, the complex multiply-accumulate
+    with that frequency's strength)."""
+    nb = (n_freq + block - 1) // block
+    return FLOPS_DIPOLE * nb + 21 * (n_freq - nb)
+
+
 def layered_stack(args):
-    """Three interfaces, 64 frequencies (one multi-frequency launch per stage), 128^3."""
+    """Three interfaces, 64 frequencies (one multi-frequency launch per stage), 128^3: the
+    benchmark line."""
     import torch
     from paper_2408_06765_amd import rsi
     from paper_2408_06765_amd import workloads as W
@@ -210,15 +286,52 @@ def layered_stack(args):
         ifs.append(rsi.Interface(*q[:3], q[3], z))
     tgt = tuple(torch.as_tensor(a, device="cuda") for a in cfg.targets())
     T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), cfg.axis)
-    freqs = list(cfg.freqs)
+    freqs = [float(f) for f in cfg.freqs]
     plan = rsi.Plan.chain(T, ifs, cfg.media, tgt, freqs, rsi.RSI_T_LOCAL, rsi.RSI_FP32)
-    steps = max(1, min(args.steps, 3))
-    dt = timed(plan.execute, steps, min(args.warmup, 1))
+    torch.cuda.synchronize()
+    print(f"layered_stack: plan built, {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
+          flush=True)
+    dt = timed(plan.execute, args.steps, args.warmup)
     n_t = tgt[0].numel()
-    pairs = len(freqs) * (cfg.n_xd * cfg.n_if + 2 * cfg.n_if * cfg.n_if + cfg.n_if * n_t)
-    line = base_line(pairs * steps / dt / 1e9, steps, min(args.warmup, 1), dt,
-                     {"workload": "layered_stack: piston 2^16 -> 3 interfaces x 2^18 -> 128^3 volume, "
-                                  "64 frequencies 1-10 MHz, local T", "pair_frequencies_per_step": pairs})
+    nf = len(freqs)
+    pairs = nf * (cfg.n_xd * cfg.n_if + 2 * cfg.n_if * cfg.n_if + cfg.n_if * n_t)
+    line = base_line(pairs * args.steps / dt / 1e9, args.steps, args.warmup, dt,
+                     {"workload": "layered_stack: piston 2^16 (10 deg, 6.35 mm) -> 3 interfaces x 2^18 "
+                                  "(c = 1480/5900/2700/5900 m/s, 2 mm apart, local T) -> 128^3 volume, "
+                                  "64 frequencies 1-10 MHz", "pair_frequencies_per_step": pairs,
+                      "precision": "fp32 (fp64 reference distance + phase)"})
+    print(f"layered_stack: {1e3 * dt / max(args.steps, 1):.1f} ms per step", file=sys.stderr, flush=True)
+
+    # dominant kernel: the multi-frequency dipole pair sum of interface 3 onto the volume,
+    # the same launch as the chain's last stage, through rsi_propagate_multifreq with HIP
+    # events on the stream it runs on (per-frequency strengths seeded, 2^18 x 64)
+    rng = np.random.default_rng(0)
+    last = ifs[-1]
+    vel = torch.as_tensor(rng.normal(size=(nf, cfg.n_if)) + 1j * rng.normal(size=(nf, cfg.n_if)), device="cuda")
+    mf_out = torch.empty((nf, n_t), dtype=torch.complex64, device="cuda")
+    reps = args.kernel_reps if args.kernel_reps is not None else 2
+    s = torch.cuda.Stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    with torch.cuda.stream(s):
+        for e0, e1 in ev:
+            e0.record(s)
+            rsi.rsi_propagate_multifreq((last.x, last.y, last.z), last.w, vel, tgt, cfg.media[-1][0], freqs,
+                                        rsi.RSI_DIPOLE, rsi.RSI_FP32, rsi.RSI_FLAG_PLANAR_Z,
+                                        normal=(0.0, 0.0, 1.0), out=mf_out)
+            e1.record(s)
+    s.synchronize()
+    kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    fl = flops_multifreq_pair(nf)
+    kpairs = cfg.n_if * n_t
+    achieved = fl * kpairs / (kms * 1e-3) / 1e12
+    line["roofline"] = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                        "traffic": measured_traffic(MF_TRAFFIC_FILE, "multifreq"),
+                        "kernel": f"multifreq_f32_kernel<dipole, planar, per-frequency strengths> (interface 3 "
+                                  f"-> volume), {fl} flop per pair for {nf} frequencies x {kpairs:.4e} pairs / "
+                                  f"{kms:.3f} ms"}
+    line["fp32_valu_counters"] = measured_valu(MF_VALU_FILE, "multifreq")
+    del vel, mf_out
     if args.fp64_compare:
         # FP64 chain per frequency on every 64th volume point; FP32 from the timed plan
         sub = torch.arange(0, n_t, 64, device="cuda")
@@ -238,8 +351,11 @@ def layered_stack(args):
         got = plan.out[g["freq_index"]].cpu().numpy()[:, idx]
         line["parity_vs_oracle_samples"] = [float(np.linalg.norm(a - b) / np.linalg.norm(b))
                                             for a, b in zip(got, ref)]
-    print(json.dumps(line), flush=True)
     plan.destroy()
+    if not args.no_cpu:
+        print("layered_stack: timing the FP64 reference on the host", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline_layered(cfg)
+    print(json.dumps(line), flush=True)
 
 
 def interface_continuity(args):
@@ -780,8 +896,8 @@ def surrogate_inference(args):
     run = lambda: net.forward(q, y)
     dt = timed(run, args.steps, args.warmup)
     # 20 back-to-back calls between the events: a single call's events add launch latency
-    kms = _event_ms(lambda: [run() for _ in range(20)], reps=max(3, args.kernel_reps)) / 20
-    kms2 = _event_ms(lambda: [net.forward(q2, y2) for _ in range(20)], reps=max(3, args.kernel_reps)) / 20
+    kms = _event_ms(lambda: [run() for _ in range(20)], reps=max(3, args.kernel_reps or 5)) / 20
+    kms2 = _event_ms(lambda: [net.forward(q2, y2) for _ in range(20)], reps=max(3, args.kernel_reps or 5)) / 20
     net.destroy()
     fl = flops_mlp_row(cfg.n_ff, cfg.width, cfg.depth)
     achieved = n * fl / (kms * 1e-3) / 1e12
@@ -800,32 +916,10 @@ def surrogate_inference(args):
     print(json.dumps(line), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
+def one_interface(args):
+    """The single-frequency chain: piston (2^16, 5 MHz, tilted 10 deg) -> one interface
+    (2^18) -> 512 x 512 image, local transmission coefficient."""
     import torch
-
-    if args.workload == "layered_stack":
-        return layered_stack(args)
-    if args.workload == "interface_continuity":
-        return interface_continuity(args)
-    if args.workload == "focused_normal":
-        return focused_normal(args)
-    if args.workload == "ray_field":
-        return ray_field_leg(args)
-    if args.workload == "ray_crossover":
-        return ray_crossover(args)
-    if args.workload == "scan_batch":
-        return scan_batch(args)
-    if args.workload == "surrogate":
-        return surrogate(args)
-    if args.workload == "multilayer_noise":
-        return multilayer_noise(args)
-    if args.workload == "surrogate_inference":
-        return surrogate_inference(args)
-
     from paper_2408_06765_amd import rsi
     from paper_2408_06765_amd import workloads as W
 
@@ -858,6 +952,7 @@ def main():
 
     # dominant kernel: the interface (dipole) pair sum, one call per launch, timed with
     # HIP events on the stream it runs on
+    reps = args.kernel_reps if args.kernel_reps is not None else 5
     s = torch.cuda.Stream()
     vel = torch.ones(cfg.n_if, dtype=torch.complex128, device="cuda")
     out = torch.empty(cfg.nx * cfg.nz, dtype=torch.complex64, device="cuda")
@@ -865,7 +960,7 @@ def main():
         rsi.rsi_propagate_ex(qs[:3], qs[3], vel, tgt, cfg.media[1][0], cfg.freq, rsi.RSI_DIPOLE,
                              rsi.RSI_FP32, rsi.RSI_FLAG_PLANAR_Z, normal=(0.0, 0.0, 1.0), out=out)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.kernel_reps)]
+              for _ in range(reps)]
         for e0, e1 in ev:
             e0.record(s)
             rsi.rsi_propagate_ex(qs[:3], qs[3], vel, tgt, cfg.media[1][0], cfg.freq,
@@ -922,6 +1017,34 @@ def main():
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)
     plan.destroy()
+
+
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    if args.workload == "one_interface":
+        return one_interface(args)
+    if args.workload == "interface_continuity":
+        return interface_continuity(args)
+    if args.workload == "focused_normal":
+        return focused_normal(args)
+    if args.workload == "ray_field":
+        return ray_field_leg(args)
+    if args.workload == "ray_crossover":
+        return ray_crossover(args)
+    if args.workload == "scan_batch":
+        return scan_batch(args)
+    if args.workload == "surrogate":
+        return surrogate(args)
+    if args.workload == "multilayer_noise":
+        return multilayer_noise(args)
+    if args.workload == "surrogate_inference":
+        return surrogate_inference(args)
+    return layered_stack(args)
 
 
 if __name__ == "__main__":

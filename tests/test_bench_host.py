@@ -17,7 +17,7 @@ def test_region_takes_the_braced_block_or_the_statement():
 
 
 def _copy_sources(tmp_path, monkeypatch):
-    for f, _ in bench.KERNEL_SOURCES:
+    for f, _ in [x for v in bench.KERNEL_SOURCES.values() for x in v]:
         dst = tmp_path / f
         dst.parent.mkdir(parents=True, exist_ok=True)
         shutil.copy(os.path.join(bench.ROOT, f), dst)
@@ -38,6 +38,15 @@ def test_digest_follows_kernel_regions_only(tmp_path, monkeypatch):
     j = text.index("{", i) + 1
     hip.write_text(text[:j] + "\n    // edit\n" + text[j:])
     assert bench.kernel_sources_digest() != d0
+    # the multi-frequency kernel's digest follows its own kernel only
+    m0 = bench.kernel_sources_digest("multifreq")
+    mf = tmp_path / "paper_2408_06765_amd/csrc/rsi_multifreq.hip"
+    t2 = mf.read_text()
+    k = t2.index("{", t2.index("multifreq_f32_kernel(")) + 1
+    mf.write_text(t2[:k] + "\n    // edit\n" + t2[k:])
+    assert bench.kernel_sources_digest("multifreq") != m0
+    mf.write_text(t2)
+    assert bench.kernel_sources_digest("multifreq") == m0
     # a moved anchor reads as stale counters, not as an error
     hip.write_text(text.replace("pairsum_f32_kernel(", "pairsum_f32_kernel_renamed("))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
@@ -82,7 +91,10 @@ def test_committed_summaries_parse():
 
 def test_flop_conventions():
     """The per-unit flop counts the roofline lines use: the ray pair through one plane (two
-    Newton evaluations) and one row of the surrogate network (128 frequencies, 5 x 256)."""
+    Newton evaluations), one row of the surrogate network (128 frequencies, 5 x 256), and a
+    multi-frequency dipole pair (33 for each block's first frequency, 21 per further one)."""
     assert bench.flops_ray_pair(2) == 104
+    assert bench.flops_multifreq_pair(64) == 4 * 33 + 60 * 21
+    assert bench.flops_multifreq_pair(20) == 2 * 33 + 18 * 21
     assert bench.flops_mlp_row(128, 256, 5) == 2 * (256 * 256 + 4 * 256 * 256 + 2 * 256)
     assert bench.FLOPS_DIPOLE == 33

@@ -155,9 +155,11 @@ KERNEL_SOURCES = {
          ["struct alignas(32) SrcRecF", "constexpr int kBlock", "constexpr int64_t kFewWaves"]),
     ],
     "multifreq": [
-        ("paper_2408_06765_amd/csrc/rsi_device.h", ["constexpr int kSub", "constexpr int kFB"]),
+        ("paper_2408_06765_amd/csrc/rsi_device.h",
+         ["constexpr int kSub", "constexpr int kFB", "bool phase_in_sin_range("]),
         ("paper_2408_06765_amd/csrc/rsi_multifreq.hip",
-         ["multifreq_f32_kernel(", "rsi_status pairsum_multifreq_f32("]),
+         ["struct TargetMF", "void multifreq_sum(", "multifreq_f32_kernel(",
+          "rsi_status pairsum_multifreq_f32("]),
         ("paper_2408_06765_amd/csrc/rsi_internal.h",
          ["struct alignas(32) SrcRecF", "constexpr int kBlock"]),
     ],
@@ -237,6 +239,17 @@ def measured_valu(path=None, kernel="pairsum"):
             "cu_busy_pct": float(kv["dipole_cu_busy_pct"]),
             "issue_model_frac": float(kv["dipole_issue_model_frac"]),
             "source": os.path.relpath(path, ROOT)}
+
+
+def calib_copy():
+    """A plain device copy of known size (256 MiB read + 256 MiB written) in the same run,
+    whose HBM counters scale the kernel's."""
+    import torch
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return a.numel() * 4
 
 
 def timed(fn, steps, warmup):
@@ -328,8 +341,8 @@ def layered_stack(args):
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                         "traffic": measured_traffic(MF_TRAFFIC_FILE, "multifreq"),
                         "kernel": f"multifreq_f32_kernel<dipole, planar, per-frequency strengths> (interface 3 "
-                                  f"-> volume), {fl} flop per pair for {nf} frequencies x {kpairs:.4e} pairs / "
-                                  f"{kms:.3f} ms"}
+                                  f"-> volume: one call, launched per chunk of 8192 sources), {fl} flop per pair "
+                                  f"for {nf} frequencies x {kpairs:.4e} pairs / {kms:.3f} ms"}
     line["fp32_valu_counters"] = measured_valu(MF_VALU_FILE, "multifreq")
     del vel, mf_out
     if args.fp64_compare:
@@ -352,6 +365,8 @@ def layered_stack(args):
         line["parity_vs_oracle_samples"] = [float(np.linalg.norm(a - b) / np.linalg.norm(b))
                                             for a, b in zip(got, ref)]
     plan.destroy()
+    if args.calib_copy:
+        line["calib_copy_bytes"] = calib_copy()
     if not args.no_cpu:
         print("layered_stack: timing the FP64 reference on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline_layered(cfg)
@@ -1007,12 +1022,7 @@ def one_interface(args):
     if check is not None:
         line["parity_vs_oracle_samples"] = check
     if args.calib_copy:
-        # plain copy of known size: 256 MiB read + 256 MiB written, for scaling counters
-        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        line["calib_copy_bytes"] = a.numel() * 4
+        line["calib_copy_bytes"] = calib_copy()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

@@ -4,74 +4,82 @@
 // On a uniform grid f_q = f_0 + q df the phase of a pair is linear in q:
 //     r f_q / c = r f_b / c + (q - q_b) r df / c,
 // so e^{i k_q r} advances by the same unit phasor e^{i dk r} from one frequency to the
-// next.  The geometry of a pair (q, 1/r, r - r_ref) and two phasors (block start and
-// step) are evaluated once per block of kFB frequencies; each further frequency costs a
-// complex rotation and the complex multiply-accumulate with that frequency's strength.
+// next, and e_q = e^{i k_q r} obeys e_{q+1} = 2 cos(dk r) e_q - e_{q-1}.  The geometry of a
+// pair (q, 1/r, r - r_ref) and two phasors (block start and step) are evaluated once per
+// block of kFB frequencies; each further frequency costs two FMAs of that recurrence and
+// the complex multiply-accumulate with that frequency's strength.  The recurrence depends
+// on the step only through its cosine, whose rounding moves the step angle by up to
+// about sqrt(2 ulp) where sin(dk r) ~ 0; over a block of 16 frequencies this stays at a
+// few 1e-6 of the field (float32 emulation on the stack's last stage: 2.8e-6 worst
+// frequency against 1.0e-6 for the complex rotation).
 // The strengths of one source for a frequency block are contiguous (source-major,
 // frequency-minor), so a wave reads them with one wave-uniform load.  SHARED_S: one
 // real strength per source for every frequency (the transducer stage), taken from the
 // record's signed magnitude; its phase offset is zero for real strengths.
+#include <algorithm>
 #include <cmath>
 
 #include "rsi_device.h"
 
 namespace rsi {
 
-template <int KIND, bool PLANAR, bool SHARED_S>
-__global__ void __launch_bounds__(kBlock) multifreq_f32_kernel(
-    const SrcRecF *__restrict__ rec, const float2 *__restrict__ S, int64_t n_src, int nf_pad,
-    const double *__restrict__ tx, const double *__restrict__ ty, const double *__restrict__ tz,
-    int64_t n_tgt, const double *__restrict__ anchor, double f0, double df, int n_freq,
-    double inv_c, float2 *__restrict__ out) {
-    const int q0 = blockIdx.y * kFB;
-    const double fb = f0 + q0 * df;
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < n_tgt;
-    if (!valid) i = n_tgt - 1;
-    // per target, in FP64: reference distance and the two reference phases
-    const double dx = tx[i] - anchor[0], dy = ty[i] - anchor[1], dz = tz[i] - anchor[2];
-    const double rr2d = dx * dx + dy * dy + dz * dz, rrd = sqrt(rr2d);
-    double pb = rrd * fb * inv_c, pd = rrd * df * inv_c;
-    pb -= floor(pb);
-    pd -= floor(pd);
-    const float dmx = (float)(-2.0 * dx), dmy = (float)(-2.0 * dy), dmz = (float)(-2.0 * dz);
-    const float rr2 = (float)rr2d, rr = (float)rrd, p0b = (float)pb, p0d = (float)pd;
-    const float ht = (float)dz;  // n = +z for the interface (dipole) stages
-    const float ilb = (float)(fb * inv_c), ild = (float)(df * inv_c);
-    float kq[kFB];
-#pragma unroll
-    for (int q = 0; q < kFB; ++q) kq[q] = (float)(kTwoPi * (fb + q * df) * inv_c);
+// Per-target constants of a multi-frequency block (FP32, from the FP64 set-up).
+struct TargetMF {
+    float dmx, dmy, dmz;  // -2 (P - C)
+    float rr2, rr;        // r_ref^2, r_ref
+    float p0b, p0d;       // frac(r_ref f_b / c), frac(r_ref df / c)
+    float ht;             // (P - C).z: n.(P - Q) for planar sources with n = +z
+    float ilb, ild;       // f_b / c, df / c
+};
 
+// Sum over all sources for the kFB frequencies of one block into mre, mim.  FRACT: reduce
+// the two phase arguments with v_fract; without it they go to v_sin / v_cos as they are,
+// which the caller allows only while they stay inside the hardware's own reduction range.
+template <int KIND, bool PLANAR, bool SHARED_S, bool FRACT>
+__device__ __forceinline__ void multifreq_sum(const TargetMF &T, const float (&kq)[kFB],
+                                              const SrcRecF *__restrict__ rec,
+                                              const float2 *__restrict__ S, int64_t j0, int64_t j1,
+                                              int nf_pad, int q0, float (&mre)[kFB],
+                                              float (&mim)[kFB]) {
     // running FP32 sums of the 64-source block sums, without compensation: the registers
     // go to 16 frequencies per pair (one geometry and two transcendental phasors shared by
     // all of them), which measured faster than 8 frequencies with a compensated sum
-    float mre[kFB], mim[kFB];
 #pragma unroll
     for (int q = 0; q < kFB; ++q) mre[q] = mim[q] = 0.0f;
-    for (int64_t jb = 0; jb < n_src; jb += kSub) {
-        const int64_t je = (jb + kSub < n_src) ? jb + kSub : n_src;
+    for (int64_t jb = j0; jb < j1; jb += kSub) {
+        const int cnt = (int)((jb + kSub < j1) ? kSub : j1 - jb);
+        const SrcRecF *blk = rec + jb;
+        const float2 *Sb = S + jb * nf_pad + q0;
         float are[kFB], aim[kFB];
 #pragma unroll
         for (int q = 0; q < kFB; ++q) are[q] = aim[q] = 0.0f;
-        for (int64_t j = jb; j < je; ++j) {
-            const SrcRecF s = rec[j];
-            float t = dmx * s.ex;
-            t = fmaf(dmy, s.ey, t);
-            if constexpr (!PLANAR) t = fmaf(dmz, s.ez, t);
+        for (int jj = 0; jj < cnt; ++jj) {  // 32-bit count: the loop test stays scalar
+            const SrcRecF s = blk[jj];
+            float t = T.dmx * s.ex;
+            t = fmaf(T.dmy, s.ey, t);
+            if constexpr (!PLANAR) t = fmaf(T.dmz, s.ez, t);
             const float qq = t + s.es2;
-            const float r2 = rr2 + qq;
+            const float r2 = T.rr2 + qq;
             const float ir = __builtin_amdgcn_rsqf(fabsf(r2));
-            const float dr = qq * __builtin_amdgcn_rcpf(fmaf(r2, ir, rr));
-            const float phb = __builtin_amdgcn_fractf(fmaf(dr, ilb, p0b));
-            const float phd = __builtin_amdgcn_fractf(fmaf(dr, ild, p0d));
+            const float dr = qq * __builtin_amdgcn_rcpf(fmaf(r2, ir, T.rr));
+            float phb = fmaf(dr, T.ilb, T.p0b), phd = fmaf(dr, T.ild, T.p0d);
+            if constexpr (FRACT) {
+                phb = __builtin_amdgcn_fractf(phb);
+                phd = __builtin_amdgcn_fractf(phd);
+            }
             const float cd = __builtin_amdgcn_cosf(phd), sd = __builtin_amdgcn_sinf(phd);
             float amp = ir;  // monopole: e^{ikr}/r
             if constexpr (KIND == RSI_DIPOLE) {
-                const float hh = PLANAR ? ht : ht - s.h;
+                const float hh = PLANAR ? T.ht : T.ht - s.h;
                 amp = hh * ir * ir;  // cos(theta)/r, times (ik - 1/r) per frequency below
             }
             if constexpr (SHARED_S) amp *= s.a;  // one real strength for every frequency
+            // e_q = amp e^{i k_q r}: e_0 and e_1 from the two phasors, then the two-term
+            // recurrence e_{q+1} = 2 cos(dk r) e_q - e_{q-1} (real coefficient: 2 FMAs per
+            // frequency instead of a complex rotation's 4 operations)
             float er = __builtin_amdgcn_cosf(phb) * amp, ei = __builtin_amdgcn_sinf(phb) * amp;
+            float nr = fmaf(er, cd, -ei * sd), ni = fmaf(er, sd, ei * cd);
+            const float tc = cd + cd;
 #pragma unroll
             for (int q = 0; q < kFB; ++q) {
                 float gr = er, gi = ei;
@@ -83,16 +91,21 @@ __global__ void __launch_bounds__(kBlock) multifreq_f32_kernel(
                     are[q] += gr;
                     aim[q] += gi;
                 } else {
-                    const float2 sv = S[j * nf_pad + q0 + q];
+                    const float2 sv = Sb[(int64_t)jj * nf_pad + q];
                     are[q] = fmaf(sv.x, gr, are[q]);
                     are[q] = fmaf(-sv.y, gi, are[q]);
                     aim[q] = fmaf(sv.x, gi, aim[q]);
                     aim[q] = fmaf(sv.y, gr, aim[q]);
                 }
-                if (q + 1 < kFB) {  // advance to the next frequency: multiply by e^{i dk r}
-                    const float nr = er * cd - ei * sd;
-                    ei = fmaf(er, sd, ei * cd);
+                if (q + 2 < kFB) {  // e_{q+2} from e_{q+1} and e_q
+                    const float tr = fmaf(tc, nr, -er), ti = fmaf(tc, ni, -ei);
                     er = nr;
+                    ei = ni;
+                    nr = tr;
+                    ni = ti;
+                } else {
+                    er = nr;
+                    ei = ni;
                 }
             }
         }
@@ -102,10 +115,60 @@ __global__ void __launch_bounds__(kBlock) multifreq_f32_kernel(
             mim[q] += aim[q];
         }
     }
+}
+
+// Sources [j0, j1) of one launch; `accumulate`: add to what `out` holds (the sum of the
+// earlier source chunks, from earlier launches on the same stream) instead of storing.
+template <int KIND, bool PLANAR, bool SHARED_S>
+__global__ void __launch_bounds__(kBlock) multifreq_f32_kernel(
+    const SrcRecF *__restrict__ rec, const float2 *__restrict__ S, int64_t j0, int64_t j1,
+    int nf_pad, const double *__restrict__ tx, const double *__restrict__ ty,
+    const double *__restrict__ tz, int64_t n_tgt, const double *__restrict__ anchor, double f0,
+    double df, int n_freq, double inv_c, int accumulate, float2 *__restrict__ out) {
+    const int q0 = blockIdx.y * kFB;
+    const double fb = f0 + q0 * df;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < n_tgt;
+    if (!valid) i = n_tgt - 1;
+    // per target, in FP64: reference distance and the two reference phases
+    const double dx = tx[i] - anchor[0], dy = ty[i] - anchor[1], dz = tz[i] - anchor[2];
+    const double rr2d = dx * dx + dy * dy + dz * dz, rrd = sqrt(rr2d);
+    double pb = rrd * fb * inv_c, pd = rrd * df * inv_c;
+    pb -= floor(pb);
+    pd -= floor(pd);
+    TargetMF T;
+    T.dmx = (float)(-2.0 * dx);
+    T.dmy = (float)(-2.0 * dy);
+    T.dmz = (float)(-2.0 * dz);
+    T.rr2 = (float)rr2d;
+    T.rr = (float)rrd;
+    T.p0b = (float)pb;
+    T.p0d = (float)pd;
+    T.ht = (float)dz;  // n = +z for the interface (dipole) stages
+    T.ilb = (float)(fb * inv_c);
+    T.ild = (float)(df * inv_c);
+    float kq[kFB];
+#pragma unroll
+    for (int q = 0; q < kFB; ++q) kq[q] = (float)(kTwoPi * (fb + q * df) * inv_c);
+    float mre[kFB], mim[kFB];
+    // |r - r_ref| <= R (the set's half diagonal), so both phase arguments stay within
+    // 1 + R f_b / c revolutions (df <= f_b is not assumed: the larger of the two counts)
+    if (phase_in_sin_range(anchor[3], (fb > df ? fb : df) * inv_c))
+        multifreq_sum<KIND, PLANAR, SHARED_S, false>(T, kq, rec, S, j0, j1, nf_pad, q0, mre, mim);
+    else
+        multifreq_sum<KIND, PLANAR, SHARED_S, true>(T, kq, rec, S, j0, j1, nf_pad, q0, mre, mim);
     if (!valid) return;
 #pragma unroll
-    for (int q = 0; q < kFB; ++q)
-        if (q0 + q < n_freq) out[(int64_t)(q0 + q) * n_tgt + i] = make_float2(mre[q], mim[q]);
+    for (int q = 0; q < kFB; ++q) {
+        if (q0 + q >= n_freq) continue;
+        float2 &o = out[(int64_t)(q0 + q) * n_tgt + i];
+        if (accumulate) {
+            const float2 p = o;
+            o = make_float2(p.x + mre[q], p.y + mim[q]);
+        } else {
+            o = make_float2(mre[q], mim[q]);
+        }
+    }
 }
 
 // S[j][q] = -(1/2pi) w_j T_j phi_q(Q_j) F_q for q < n_freq, 0 for the padding, with the
@@ -195,24 +258,41 @@ rsi_status pairsum_multifreq_f32(const SrcSetF &set, const float2 *S, const Targ
     const dim3 grid((unsigned)bx, (unsigned)nfb);
     const double inv_c = 1.0 / c;
     const bool shared = (S == nullptr);
-#define RSI_MF_LAUNCH(K, P, SH)                                                               \
-    hipLaunchKernelGGL((multifreq_f32_kernel<K, P, SH>), grid, dim3(kBlock), 0, s, set.rec, S, \
-                       set.n, nf_pad, t.x, t.y, t.z, t.n, set.anchor, f0, df, n_freq, inv_c, out)
-    if (kind == RSI_MONOPOLE) {
-        if (shared) {
-            if (planar_z) RSI_MF_LAUNCH(RSI_MONOPOLE, true, true);
-            else RSI_MF_LAUNCH(RSI_MONOPOLE, false, true);
+    if (kind != RSI_MONOPOLE && !planar_z) return RSI_ERR_UNSUPPORTED;  // interface stages are planar (+z)
+    // One launch per chunk of sources, each adding to the output in chunk order (the sum
+    // stays deterministic).  A chunk's records and strengths (160 B per source for a block
+    // of 16 frequencies: 1.3 MB for 8192 sources) fit one XCD's 4 MB L2, and the
+    // workgroups in flight at any time all read the same chunk, because they are
+    // dispatched in order and every target tile of a chunk comes before the next chunk.
+    // Without chunks every workgroup streams the whole source set at its own pace and the
+    // L2 misses on nearly every record.  Measured on 2^18 sources x 2^18 points x 64
+    // frequencies: 992, 1005, 1038, 1047 ms for chunks of 8192, 16384, 32768, 65536
+    // sources, 1011 ms for one launch.
+    static const int64_t chunk = std::max<int64_t>(kSub, (int64_t)env_int("RSI_MF_CHUNK", 8192) / kSub * kSub);
+    const int64_t n_src = set.n > 0 ? set.n : 0;
+    int64_t j0 = 0;
+    do {
+        const int64_t j1 = (n_src - j0 > chunk) ? j0 + chunk : n_src;
+        const int acc = j0 > 0 ? 1 : 0;
+#define RSI_MF_LAUNCH(K, P, SH)                                                                  \
+    hipLaunchKernelGGL((multifreq_f32_kernel<K, P, SH>), grid, dim3(kBlock), 0, s, set.rec, S, j0, \
+                       j1, nf_pad, t.x, t.y, t.z, t.n, set.anchor, f0, df, n_freq, inv_c, acc, out)
+        if (kind == RSI_MONOPOLE) {
+            if (shared) {
+                if (planar_z) RSI_MF_LAUNCH(RSI_MONOPOLE, true, true);
+                else RSI_MF_LAUNCH(RSI_MONOPOLE, false, true);
+            } else {
+                if (planar_z) RSI_MF_LAUNCH(RSI_MONOPOLE, true, false);
+                else RSI_MF_LAUNCH(RSI_MONOPOLE, false, false);
+            }
         } else {
-            if (planar_z) RSI_MF_LAUNCH(RSI_MONOPOLE, true, false);
-            else RSI_MF_LAUNCH(RSI_MONOPOLE, false, false);
+            if (shared) RSI_MF_LAUNCH(RSI_DIPOLE, true, true);
+            else RSI_MF_LAUNCH(RSI_DIPOLE, true, false);
         }
-    } else {
-        if (!planar_z) return RSI_ERR_UNSUPPORTED;  // interface stages are planar (normal +z)
-        if (shared) RSI_MF_LAUNCH(RSI_DIPOLE, true, true);
-        else RSI_MF_LAUNCH(RSI_DIPOLE, true, false);
-    }
 #undef RSI_MF_LAUNCH
-    RSI_HIP(hipGetLastError());
+        RSI_HIP(hipGetLastError());
+        j0 = j1;
+    } while (j0 < n_src);
     return RSI_OK;
 }
 

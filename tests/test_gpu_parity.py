@@ -321,6 +321,38 @@ def test_chain_uniform_grid_ragged_block(gpu, orc, flags):
         assert rel(got[f], ref[f]) <= TOL[0], (f, rel(got[f], ref[f]))
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_fp32_field_points_near_a_source(gpu, orc, kind):
+    """The FP32 path does not test for close pairs; its documented behaviour: with
+    s = |P - C| + R (C the sources' bounding-box centre, R its half diagonal), a field
+    point at distance r >= 1e-3 s from a source gets a finite value, and at r = 1e-2 s it
+    stays within 1e-2 of the reference (the close term's rounding, about 3e-7 (s/r)^2).
+    Field points are placed at those distances from 64 sources in random directions
+    (above the plane for the planar dipole sources)."""
+    rng = np.random.default_rng(7 + kind)
+    src, w, s, _ = _case(91 + kind, 5000, 1, kind)
+    C = np.array([(v.max() + v.min()) / 2 for v in src])
+    R = 0.5 * math.sqrt(sum(float(np.ptp(v)) ** 2 for v in src))
+    idx = rng.choice(len(w), 64, replace=False)
+    P = np.stack([v[idx] for v in src], 1)
+    d = rng.normal(size=(64, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    if kind == 1:
+        d[:, 2] = np.abs(d[:, 2]) + 0.1
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+    sc = np.linalg.norm(P - C, axis=1) + R
+    for rho, bound in ((1e-3, None), (1e-2, 1e-2)):
+        T = P + rho * sc[:, None] * d
+        tgt = tuple(T[:, k].copy() for k in range(3))
+        got = host(gpu.rsi_propagate(devpts(src), dev(w), dev(s), devpts(tgt), 1480.0, 2.0e6, kind, 0,
+                                     normal=(0.0, 0.0, 1.0)))
+        assert np.all(np.isfinite(got.view(np.float32))), rho
+        if bound is not None:
+            ref = orc.propagate(kind, src, w, s, tgt, 1480.0, 2.0e6, normal=(0.0, 0.0, 1.0))
+            err = np.abs(got - ref) / np.abs(ref)
+            assert err.max() <= bound, (rho, err.max())
+
+
 @pytest.mark.parametrize("kind", [0, 1, 2])
 def test_fp64_field_point_on_a_source(gpu, orc, kind):
     """The kernel is singular on the radiating surface (Sec. 3.2): the FP64 path drops

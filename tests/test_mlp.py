@@ -65,6 +65,126 @@ def test_adam_first_step_is_sign_step():
     assert np.allclose(p1, p - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
 
 
+def _adam_broken_exponent(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam with the bias correction of step t taken at t - 1 (a plausible slip), used to
+    show that the pins below fail for it."""
+    m = beta1 * m + (1 - beta1) * g
+    v = beta2 * v + (1 - beta2) * g * g
+    mh = m / (1 - beta1 ** max(step - 1, 1))
+    vh = v / (1 - beta2 ** max(step - 1, 1))
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def _adam_swapped_betas(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam with the two decay rates exchanged (a plausible slip)."""
+    return MO.adam_step(p, g, m, v, step, lr, beta2, beta1, eps)
+
+
+def _run_adam(step_fn, p0, grads, lr, **kw):
+    p, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    out = []
+    for k, g in enumerate(grads, start=1):
+        p, m, v = step_fn(p, g, m, v, k, lr, **kw)
+        out.append(p.copy())
+    return out
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias-corrected moments are exactly g and g^2 at every
+    step (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so step t moves each parameter by
+    lr g / (|g| + eps): after t steps p0 - t lr g / (|g| + eps).  This pins the bias
+    correction's exponents; the same closed form fails for a correction taken one step
+    late."""
+    p0 = np.array([0.5, -1.0, 2.0, 0.0])
+    g = np.array([3e-3, -4.0, 0.25, 1e-6])
+    lr = 0.01
+    grads = [g] * 6
+    expect = [p0 - t * lr * g / (np.abs(g) + 1e-8) for t in range(1, 7)]
+    for got, want in zip(_run_adam(MO.adam_step, p0, grads, lr), expect):
+        assert np.allclose(got, want, rtol=1e-12, atol=1e-14)
+    bad = _run_adam(_adam_broken_exponent, p0, grads, lr)
+    assert not np.allclose(bad[3], expect[3], rtol=1e-6, atol=1e-9)
+
+
+def test_adam_three_steps_hand_expanded():
+    """Three different gradients g1, g2, g3 with decay rates b1 = 0.8, b2 = 0.95: the
+    moments written out as explicit sums (no recursion),
+        m_t = (1 - b1) sum_{s<=t} b1^(t-s) g_s,   v_t = (1 - b2) sum_{s<=t} b2^(t-s) g_s^2,
+    and p_3 = p0 - lr sum_t (m_t / (1 - b1^t)) / (sqrt(v_t / (1 - b2^t)) + eps).  This pins
+    b1 and b2 (it fails with the two rates exchanged) and the order of the terms."""
+    b1, b2, eps, lr = 0.8, 0.95, 1e-8, 0.003
+    p0 = np.array([0.1, -0.2, 0.3])
+    gs = [np.array([1.0, -2.0, 0.5]), np.array([-3.0, 0.5, 0.25]), np.array([2.0, 4.0, -1.0])]
+    moves = np.zeros(3)
+    for t in (1, 2, 3):
+        m = (1 - b1) * sum(b1 ** (t - s) * gs[s - 1] for s in range(1, t + 1))
+        v = (1 - b2) * sum(b2 ** (t - s) * gs[s - 1] ** 2 for s in range(1, t + 1))
+        moves += (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+    want = p0 - lr * moves
+    got = _run_adam(MO.adam_step, p0, gs, lr, beta1=b1, beta2=b2, eps=eps)[-1]
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-15)
+    swapped = _run_adam(_adam_swapped_betas, p0, gs, lr, beta1=b1, beta2=b2, eps=eps)[-1]
+    assert not np.allclose(swapped, want, rtol=1e-6)
+    late = _run_adam(_adam_broken_exponent, p0, gs, lr, beta1=b1, beta2=b2, eps=eps)[-1]
+    assert not np.allclose(late, want, rtol=1e-6)
+
+
+# ------------------------------------------------------------------ one exact layer
+def _ambiguous(x, delta=2.0 ** -20):
+    """Elements whose bf16 rounding could flip under a relative change of delta (FP32
+    rounding between two correct implementations): bf16(x (1 - d)) != bf16(x (1 + d))."""
+    x = np.asarray(x, dtype=np.float64)
+    return MO.bf16(x * (1 - delta)) != MO.bf16(x * (1 + delta))
+
+
+def exact_layer_case(seed):
+    """A one-hidden-layer network whose bf16 operands are the same on any correct
+    implementation: box [0, 1]^5 with rows at its corners (v = +-1 exactly), Fourier
+    matrix of quarter integers (u = B v a quarter integer: every feature is 0 or +-1),
+    weights and biases on the 2^-10 grid with |k| < 256 (exact in bf16; z = W h0 + b is
+    exact in FP32 whatever the summation order), targets on the same grid.  Returns None
+    unless every pre-rounding value (silu(z) and the output gradient dz) is clear of
+    bf16 rounding boundaries by more than 2^-20 relative."""
+    rng = np.random.default_rng(seed)
+    n_ff, width, n = 32, 64, 64
+    B = rng.integers(-8, 9, (n_ff, 5)) / 4.0
+    corners = ((np.arange(32)[:, None] >> np.arange(5)) & 1).astype(np.float64)
+    q = np.concatenate([corners, corners[rng.permutation(32)]])[:n]
+    W1 = rng.integers(-255, 256, (width, 2 * n_ff)) / 1024.0
+    b1 = rng.integers(-255, 256, width) / 1024.0
+    Wo = rng.integers(-255, 256, (2, width)) / 1024.0
+    bo = rng.integers(-255, 256, 2) / 1024.0
+    t = rng.integers(-255, 256, (n, 2)) / 1024.0
+    o = MO.MLPOracle(B, [W1], [b1], Wo, bo)
+    v = MO.normalise(q, np.zeros(5), np.ones(5))
+    y, (hs, zs) = o.forward(v)
+    if np.any(_ambiguous(MO.silu(zs[0]))):
+        return None
+    dy = (y - t) / n
+    if np.any(_ambiguous((dy @ Wo) * MO.silu_grad(zs[0]))):
+        return None
+    flat = np.concatenate([W1.ravel(), b1, Wo.ravel(), bo])
+    return dict(n_ff=n_ff, width=width, B=B, q=q, t=t, v=v, o=o, flat=flat, h0=hs[0], z=zs[0])
+
+
+def find_exact_layer_case():
+    for seed in range(1000):
+        c = exact_layer_case(seed)
+        if c is not None:
+            return seed, c
+    raise AssertionError("no exact case in 1000 seeds")
+
+
+def test_exact_layer_case_is_exact():
+    """The case's construction holds in the reference: features are 0 or +-1 (to FP64
+    rounding), z lies on the 2^-10 grid, and no value the layer rounds to bf16 sits near
+    a rounding boundary."""
+    _, c = find_exact_layer_case()
+    h0 = c["h0"]
+    assert np.all((np.abs(h0) < 1e-13) | (np.abs(np.abs(h0) - 1) < 1e-13))
+    assert np.allclose(c["z"] * 1024, np.round(c["z"] * 1024), atol=1e-9)
+
+
 # ------------------------------------------------------------------ GPU vs reference
 def _setup(gpu_ok, n_ff, width, depth, n, seed):
     import torch
@@ -194,6 +314,53 @@ def test_mlp_train_step_is_adam(gpu):
     assert clear.mean() > 0.9
     assert rel(d_gpu[clear], d_ref[clear]) <= 1e-4
     assert np.max(np.abs(d_gpu)) <= 1e-3 * (1 + 1e-5)
+    net.destroy()
+
+
+@pytest.mark.gpu
+def test_mlp_adam_steps_match_reference(gpu):
+    """Four Adam steps on the GPU against the reference's Adam fed the same gradients (the
+    GPU's own, read before each step with rsi_mlp_gradients, which runs the same kernels
+    as the training step): the bias correction and both moment recursions past step 1."""
+    net, o, q, t, v, tn, p0 = _setup(gpu, 32, 64, 3, 500, 5)
+    p, m, vv = p0.astype(np.float64), 0.0, 0.0
+    for k in range(1, 5):
+        g, _ = net.gradients(q, t)
+        g = g.cpu().numpy().astype(np.float64)
+        net.train_step(q, t, 1e-3)
+        p, m, vv = MO.adam_step(p, g, m, vv, k, 1e-3)
+        got = net.get_params().astype(np.float64)
+        assert rel(got - p0, p - p0) <= 2e-5, (k, rel(got - p0, p - p0))
+    net.destroy()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("fused", ["1", "0"])
+def test_mlp_one_layer_exact_operands(gpu, fused, monkeypatch):
+    """One hidden layer (features -> bf16 MFMA GEMM + bias + SiLU -> head) on inputs whose
+    bf16 operands are the same on both sides (see exact_layer_case): the forward output
+    and every gradient block match the FP64 reference to 1e-5 -- the MFMA path held to
+    FP32 accumulation error, without the rounding-flip allowance of deep networks."""
+    import torch
+    from paper_2408_06765_amd import surrogate as S
+    monkeypatch.setenv("RSI_MLP_FUSED", fused)
+    _, c = find_exact_layer_case()
+    net = S.MLP(c["n_ff"], c["width"], 1, c["B"], np.zeros(5), np.ones(5), 64)
+    net.set_params(c["flat"])
+    qd = torch.as_tensor(c["q"].astype(np.float32), device="cuda")
+    td = torch.as_tensor(c["t"].astype(np.float32), device="cuda")
+    y = net.forward(qd).cpu().numpy()
+    yr, _ = c["o"].forward(c["v"])
+    assert rel(y, yr) <= 1e-5, rel(y, yr)
+    g, loss = net.gradients(qd, td)
+    lr_, _, gr = c["o"].loss_and_grads(c["v"], c["t"])
+    g = g.cpu().numpy()
+    assert abs(float(loss.cpu()) / lr_ - 1) <= 1e-5
+    W, F = c["width"], 2 * c["n_ff"]
+    blocks = [("W1", 0, W * F, gr["Ws"][0]), ("b1", W * F, W, gr["bs"][0]),
+              ("Wo", W * F + W, 2 * W, gr["Wo"]), ("bo", W * F + 3 * W, 2, gr["bo"])]
+    for name, off, size, ref in blocks:
+        assert rel(g[off:off + size], np.ravel(ref)) <= 1e-5, (name, rel(g[off:off + size], np.ravel(ref)))
     net.destroy()
 
 

@@ -329,6 +329,35 @@ def test_omnidirectional_interface_sources(orc):
     assert np.linalg.norm(omni) / nd > 1.1
 
 
+@pytest.mark.parametrize("kz", [0.5 * math.pi, math.pi, 4 * math.pi, 20 * math.pi])
+def test_omnidirectional_sources_reproduce_a_plane_wave(orc, kz):
+    """The omnidirectional interface source of the ablation, K = ik e^{ikr}/r with the
+    prefactor -1/(2 pi): boundary values of a plane wave at normal incidence (phi = 1 on
+    z = 0) give -(ik/2pi) int e^{ikr}/r dA = -ik int_z^inf e^{ikr} dr = e^{ikz} exactly,
+    near the plane (kz = pi/2) as well as far from it.  A kernel that kept the near-field
+    term, (ik - 1/r) e^{ikr}/r without the obliquity, adds int_z^inf e^{ikr}/r dr, of order
+    1 at kz ~ 1 and ~ 1/(kz) beyond; planted here on the reference's own sums, it misses
+    by > 0.1 at kz = pi/2 and by far more than the tolerance everywhere."""
+    f = 1.0e6
+    k = 2 * math.pi * f / C_W
+    z = kz / k
+    rmax = 0.6
+    r, wr = gl_panels(0.0, rmax, 4000, 16)
+    win = np.where(r < rmax / 2, 1.0, np.cos(0.5 * math.pi * (r - rmax / 2) / (rmax / 2)) ** 2)
+    w = 2 * math.pi * r * wr * win
+    src = (r, 0 * r, 0 * r)
+    zt = np.array([z])
+    tgt = (0 * zt, 0 * zt, zt)
+    phi = orc.propagate(orc.OMNI, src, w, np.ones(r.size), tgt, C_W, f)[0]
+    # window truncation of the non-decaying integrand: 3.6e-6 measured
+    assert abs(phi / np.exp(1j * kz) - 1) < 2e-5, abs(phi / np.exp(1j * kz) - 1)
+    # the planted slip: add the sum of -(1/2pi) w (-1/r) e^{ikr}/r (a monopole sum with
+    # strengths -1/r for this one field point)
+    extra = orc.propagate(orc.MONOPOLE, src, w, -1.0 / np.sqrt(r * r + z * z), tgt, C_W, f)[0]
+    miss = abs((phi + extra) / np.exp(1j * kz) - 1)
+    assert miss > (0.1 if kz < 2 else 1e-3), miss
+
+
 # ----------------------------------------------------------------------------- source variants
 def _radical_inverse_exact(i, b):
     """Radical inverse as an exact fraction (independent of the reference's integer
@@ -550,6 +579,97 @@ def test_ray_is_stationary_phase_limit_of_rsi_chain(orc):
         e1, e2 = errs[(1.0e6, P)], errs[(2.0e6, P)]
         assert e1 < 4e-3 and e2 < 2e-3, (P, e1, e2)
         assert 0.4 < e2 / e1 < 0.6, (P, e1, e2)  # O(1/k)
+
+
+def sommerfeld_reflected(k1, k2, rho1, rho2, X, H, branch=1.0, n=4000):
+    """Exact reflected velocity potential of a point source e^{ik1 R}/R at height a above a
+    fluid half-space, at a receiver at height b and horizontal offset X (H = a + b):
+    the Sommerfeld integral over the horizontal wavenumber kr,
+        phi_r = i int_0^inf (kr / kz1) R(kr) J0(kr X) e^{i kz1 H} dkr,
+        R = (rho2 kz1 - rho1 kz2) / (rho2 kz1 + rho1 kz2),   kz_j = sqrt(k_j^2 - kr^2),
+    with the radiation condition Im kz >= 0 (waves decay away from the plane for
+    e^{-i omega t}); branch = -1 takes the other root for kz2 past k2, the reading the
+    test rules out.  Written from the continuity of pressure (rho phi) and normal velocity
+    (d phi / dz) for each plane-wave component, independently of the reference's
+    coefficient code.  Quadrature: kr = k1 sin(theta) on the propagating part (split at
+    the branch point kr = k2 with square-root substitutions, so the integrand is smooth),
+    kr = k1 cosh(t) on the evanescent part."""
+    from scipy.special import j0
+
+    def refl(kr, kz1):
+        d = k2 * k2 - kr * kr
+        kz2 = np.where(d >= 0, np.sqrt(np.abs(d)) + 0j, branch * 1j * np.sqrt(np.abs(d)))
+        return (rho2 * kz1 - rho1 * kz2) / (rho2 * kz1 + rho1 * kz2)
+
+    x, w = leggauss(n)
+    tc = math.asin(min(k2 / k1, 1.0))
+    total = 0j
+    # propagating: theta in [0, tc] as tc - s^2 and [tc, pi/2] as tc + s^2
+    for lo_s, hi_s, sign in ((0.0, math.sqrt(tc), -1.0), (0.0, math.sqrt(math.pi / 2 - tc), 1.0)):
+        s_ = lo_s + (hi_s - lo_s) * (x + 1) / 2
+        ws = (hi_s - lo_s) / 2 * w
+        th = tc + sign * s_ * s_
+        jac = 2 * s_
+        kr, kz1 = k1 * np.sin(th), k1 * np.cos(th)
+        f = k1 * np.sin(th) * refl(kr, kz1) * j0(kr * X) * np.exp(1j * kz1 * H)
+        total += 1j * np.sum(ws * jac * f)
+    # evanescent in medium 1: kr = k1 cosh t, kz1 = i k1 sinh t, (kr / kz1) dkr = -i k1 cosh t dt
+    tmax = math.asinh(60.0 / (k1 * H))
+    t, wt = (x + 1) / 2 * tmax, w * tmax / 2
+    kr, kz1 = k1 * np.cosh(t), 1j * k1 * np.sinh(t)
+    f = k1 * np.cosh(t) * refl(kr, kz1) * j0(kr * X) * np.exp(-k1 * H * np.sinh(t))
+    total += np.sum(wt * f)
+    return total
+
+
+def test_sommerfeld_integral_of_a_rigid_plane_is_the_image_source():
+    """Self-check of the integral above: with R = 1 (a rigid plane, rho2 -> infinity) it
+    must give the image source e^{ik1 R'}/R', R' = sqrt(X^2 + H^2)."""
+    for f, X, H in ((1.0e6, 0.017, 0.03), (2.0e6, 0.005, 0.02)):
+        k1 = 2 * math.pi * f / C_W
+        got = sommerfeld_reflected(k1, 0.5 * k1, RHO_W, 1e30, X, H)
+        Rp = math.hypot(X, H)
+        assert abs(got / (np.exp(1j * k1 * Rp) / Rp) - 1) < 1e-9
+
+
+def test_post_critical_reflection_branch(orc):
+    """Past the critical angle eq. (15) gives sin a2 > 1 and eqs. (8) and (11) need a
+    complex cos a2; the reading +i sqrt(sin^2 a2 - 1) is the decaying wave.  A point
+    source 20 mm above a water/solid plane (critical angle 14.5 deg) and a receiver
+    10 mm above it, 30 deg from the normal at the specular point: the reference's
+    reflected field (the above mode of the chain with local angles: R per sample,
+    dipole normal -z) must approach the exact Sommerfeld field like 1/k (1 and 2 MHz),
+    while the same radiation with the other root for cos a2 misses by O(1)."""
+    c1, r1, c2, r2 = C_W, RHO_W, 5900.0, 7800.0
+    a, b = 0.02, 0.01
+    th = math.radians(30.0)
+    X = (a + b) * math.tan(th)
+    S, P = (0.0, 0.0, -a), (X, 0.0, -b)
+    xs = a * math.tan(th)  # specular point on the plane z = 0
+    errs, flipped = {}, {}
+    for f in (1.0e6, 2.0e6):
+        k1, k2 = 2 * math.pi * f / c1, 2 * math.pi * f / c2
+        q = _polar_rule_at(xs, 0.0, 0.03, k1)
+        tot = orc.chain(_one(S), 1.0, S, (0.0, 0.0, 1.0), [q], [0.0], [c1, c2], [r1, r2], _pts([P]), [f],
+                        orc.T_LOCAL, flags=orc.CHAIN_ABOVE)[0, 0]
+        inc = orc.propagate(orc.MONOPOLE, _one(S)[:3], np.array([1.0]), 1.0, _pts([P]), c1, f)[0]
+        refl_rsi = tot - inc
+        # the chain's point source is -(1/2 pi) e^{ikr}/r
+        exact = -sommerfeld_reflected(k1, k2, r1, r2, X, a + b) / (2 * math.pi)
+        wrong = -sommerfeld_reflected(k1, k2, r1, r2, X, a + b, branch=-1.0) / (2 * math.pi)
+        errs[f] = abs(refl_rsi / exact - 1)
+        flipped[f] = abs(refl_rsi / wrong - 1)
+        # the reference's own boundary values with the other root: the reflected field
+        # then differs from the exact one by O(1)
+        R = orc.reflection(orc.T_LOCAL, 1, [0.0], [c1, c2], [r1, r2], S, (0, 0, 1), q[0], q[1])
+        Rw = np.where(np.abs(np.abs(R) - 1) < 1e-12, np.conj(R), R)
+        phi_q = orc.propagate(orc.MONOPOLE, _one(S)[:3], np.array([1.0]), 1.0, q[:3], c1, f)
+        bad = orc.propagate(orc.DIPOLE, q[:3], q[3], Rw * phi_q, _pts([P]), c1, f, normal=(0.0, 0.0, -1.0))[0]
+        assert abs(bad / exact - 1) > 0.2, (f, abs(bad / exact - 1))
+    # measured: 9.2e-3 and 4.2e-3 (the correct root); 0.25 at both frequencies (the other)
+    assert errs[1.0e6] < 1.5e-2 and errs[2.0e6] < 7e-3, errs
+    assert 0.35 < errs[2.0e6] / errs[1.0e6] < 0.65, errs  # O(1/k)
+    assert min(flipped.values()) > 0.2, flipped
 
 
 # ----------------------------------------------------------------------------- eqs. 8, 11, 15

@@ -79,10 +79,12 @@ def test_summaries_are_read_only_while_the_digest_matches(tmp_path, monkeypatch)
 
 
 def test_committed_summaries_parse():
-    """Both committed summaries carry the keys the readers use (whether or not they are
+    """The committed summaries carry the keys the readers use (whether or not they are
     current for the sources in this tree)."""
     for path, keys in ((bench.TRAFFIC_FILE, ["traffic_bytes_per_launch"]),
-                       (bench.VALU_FILE, ["dipole_executed_fp32_frac", "dipole_cu_busy_pct"])):
+                       (bench.VALU_FILE, ["dipole_executed_fp32_frac", "dipole_cu_busy_pct"]),
+                       (bench.MF_TRAFFIC_FILE, ["traffic_bytes_per_launch", "algorithmic_bytes_per_launch"]),
+                       (bench.MF_VALU_FILE, ["dipole_executed_fp32_frac", "dipole_cu_busy_pct"])):
         text = open(path).read()
         assert "kernel_sources_sha256:" in text
         for k in keys:

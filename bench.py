@@ -51,7 +51,8 @@ def parse():
     ap.add_argument("--workload", default="layered_stack",
                     choices=["layered_stack", "one_interface", "scan_batch", "surrogate",
                              "interface_continuity", "focused_normal", "ray_field",
-                             "ray_crossover", "multilayer_noise", "surrogate_inference"],
+                             "ray_crossover", "multilayer_noise", "surrogate_inference",
+                             "surrogate_training"],
                     help="layered_stack is the benchmark line; the others are secondary "
                          "measurements printed in the same format")
     ap.add_argument("--autotune", action="store_true",
@@ -1031,6 +1032,53 @@ def one_interface(args):
 
 
 
+def flops_mlp_train_row(n_ff, width, depth):
+    """Algorithmic flops of one row of a training step (FMA = 2): the forward products and
+    head, the weight gradients of every layer and the head, and the input gradients of
+    every layer but the first (the features need none)."""
+    F, W, L = 2 * n_ff, width, depth
+    fwd = 2 * (F * W + (L - 1) * W * W + 2 * W)
+    dw = 2 * (F * W + (L - 1) * W * W + 2 * W)
+    dx = 2 * ((L - 1) * W * W + 2 * W)
+    return fwd + dw + dx
+
+
+def surrogate_training(args):
+    """One Adam step of the surrogate network (the recipe's shape: 128 Fourier frequencies,
+    5 x 256 SiLU, bf16 MFMA GEMMs with FP32 accumulation) on a batch of 65536 rows: features,
+    forward, loss, backward, Adam, bf16 weight refresh.  Rows and targets are seeded
+    synthetic values (the time does not depend on them)."""
+    import torch
+    from paper_2408_06765_amd import surrogate as S
+
+    cfg = S.SurrogateConfig()
+    lo, hi = S.lohi(cfg.box)
+    n = cfg.batch
+    net = S.MLP(cfg.n_ff, cfg.width, cfg.depth, S.fourier_matrix(cfg.n_ff, cfg.ff_scales, cfg.seed),
+                lo, hi, n)
+    net.set_params(S.glorot_params(cfg.n_ff, cfg.width, cfg.depth, cfg.seed))
+    rng = np.random.default_rng(0)
+    q = torch.as_tensor(np.stack([rng.uniform(lo[c], hi[c], n) for c in range(5)], 1).astype(np.float32),
+                        device="cuda")
+    t = torch.as_tensor(rng.normal(size=(n, 2)).astype(np.float32), device="cuda")
+    run = lambda: net.train_step(q, t, 1e-5)
+    dt = timed(run, args.steps, args.warmup)
+    kms = _event_ms(lambda: [run() for _ in range(10)], reps=3) / 10
+    net.destroy()
+    fl = flops_mlp_train_row(cfg.n_ff, cfg.width, cfg.depth)
+    achieved = n * fl / (kms * 1e-3) / 1e12
+    line = base_line(n * args.steps / dt, args.steps, args.warmup, dt,
+                     {"workload": f"surrogate_training: {2 * cfg.n_ff} Fourier features -> {cfg.depth} x "
+                                  f"{cfg.width} SiLU -> 2, Adam, {n} rows per step", "rows_per_step": n},
+                     unit="rows/s")
+    line["metric"] = "surrogate training rows/s (one Adam step per batch) + % bf16 MFMA peak"
+    line["dtype"] = "bf16"
+    line["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                        "kernel": f"whole training step, {fl} flop/row x {n} rows / {kms:.4f} ms"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1054,6 +1102,8 @@ def main():
         return multilayer_noise(args)
     if args.workload == "surrogate_inference":
         return surrogate_inference(args)
+    if args.workload == "surrogate_training":
+        return surrogate_training(args)
     return layered_stack(args)
 
 

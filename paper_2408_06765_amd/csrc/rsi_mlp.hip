@@ -1,5 +1,5 @@
 // rsi_mlp.hip -- the learned surrogate: Fourier-feature MLP trained and evaluated with
-// bfloat16 MFMA GEMMs (gfx950 v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+// bfloat16 MFMA GEMMs (gfx950 v_mfma_f32_32x32x16_bf16, FP32 accumulation).
 //
 // Every GEMM of training is written in one "NT" form, C[M][N] = A[M][K] . B[N][K]^T, with
 // both operands contiguous along the reduction dimension, so that each lane of a wave
@@ -11,8 +11,14 @@
 // write the row-major and the transposed bfloat16 copies the next GEMM needs.  Weight
 // gradients are split over the batch and reduced in a fixed order (deterministic).
 //
-// MFMA 16x16x32 bf16 operand layout (lane l, i = 0..7 / e = 0..3):
-//   A[l % 16][8 (l / 16) + i],  B[8 (l / 16) + i][l % 16],  D[4 (l / 16) + e][l % 16].
+// MFMA 32x32x16 bf16 operand layout (lane l, i = 0..7 / v = 0..15; checked on gfx950 with
+// small-integer operands):
+//   A[l % 32][8 (l / 32) + i],  B[8 (l / 32) + i][l % 32],
+//   D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+// The 32x32x16 form is used throughout: measured on MI355X with independent chains and no
+// memory traffic, it sustains 2.12 PFLOP/s against 1.17 for v_mfma_f32_16x16x32_bf16.
+// Every GEMM and the fused inference kernel accumulate K in the same order (steps of 16),
+// so the fused and the layer-by-layer forward give the same bits.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -30,6 +36,14 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// One 32x32x16 bf16 MFMA step: acc += A (32 x 16) . B (16 x 32).
+__device__ __forceinline__ f32x16 mfma32(const bf16x8 &a, const bf16x8 &b, const f32x16 &acc) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+}
+// Row of element v of a 32 x 32 accumulator fragment held by lane l (its column is l % 32).
+__device__ __forceinline__ int frag_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
 
 constexpr int kTileK = 32;  // K step of the GEMM (one MFMA)
 constexpr int kMaxLayers = 16;
@@ -62,15 +76,15 @@ struct GemmArgs {
 };
 
 // NT GEMM on one workgroup tile BM x BN: four waves in a 2 x 2 grid, each computing a
-// (BM/2) x (BN/2) block as (BM/32) x (BN/32) MFMA fragments of 16 x 16.  K advances in
-// steps of 32 (one MFMA): both operand slices are staged in LDS (rows padded to 40
-// bfloat16 = 80 bytes, so the 16 lanes that read one 16-byte column chunk of 16 rows
-// hit 16 disjoint bank quadruples), double-buffered, with the global loads of step k+1
+// (BM/2) x (BN/2) block as (BM/64) x (BN/64) MFMA fragments of 32 x 32.  K advances in
+// steps of 32 (two MFMAs of K = 16): both operand slices are staged in LDS (rows padded to
+// 40 bfloat16 = 80 bytes, so the lanes that read one 16-byte column chunk of consecutive
+// rows hit disjoint bank quadruples), double-buffered, with the global loads of step k+1
 // issued before the MFMAs of step k.
 template <int EPI, int BM, int BN>
 __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
     constexpr int BK = 32, LDK = BK + 8;
-    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 32, FN = WN / 32;
     constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;  // 16-byte chunks per thread
     static_assert(CA >= 1 && CB >= 1, "tile too small for 256 threads");
     // operand buffers, reused after the K loop as the staging tile of the bf16 output
@@ -111,12 +125,14 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
             *reinterpret_cast<bf16x8 *>(&sB[buf][c >> 2][(c & 3) * 8]) = rb[i];
         }
     };
-    f32x4 acc[FM][FN];
+    f32x16 acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int r = lane & 15, kq = (lane >> 4) * 8;
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    const int r = lane & 31, kq = (lane >> 5) * 8;
     if (nk > 0) {
         gload(kb);
         sstore(0);
@@ -125,76 +141,86 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < nk) gload(kb + (int64_t)(kt + 1) * BK);
-        bf16x8 af[FM], bfr[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-            af[i] = *reinterpret_cast<const bf16x8 *>(&sA[buf][wm * WM + 16 * i + r][kq]);
+        for (int ks = 0; ks < BK; ks += 16) {
+            bf16x8 af[FM], bfr[FN];
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-            bfr[j] = *reinterpret_cast<const bf16x8 *>(&sB[buf][wn * WN + 16 * j + r][kq]);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FM; ++i)
+                af[i] = *reinterpret_cast<const bf16x8 *>(&sA[buf][wm * WM + 32 * i + r][ks + kq]);
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(&sB[buf][wn * WN + 32 * j + r][ks + kq]);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = mfma32(af[i], bfr[j], acc[i][j]);
+        }
         // the other buffer was last read before the barrier that ended step kt - 1
         if (kt + 1 < nk) sstore(buf ^ 1);
         __syncthreads();
     }
-    const int cn = lane & 15, cm = (lane >> 4) * 4;
+    const int cn = lane & 31;
     if constexpr (EPI == EPI_DW) {
         float *p = g.P + (int64_t)blockIdx.z * g.M * g.N;
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
-                const int64_t n = n0 + wn * WN + 16 * j + cn;
-                const int64_t mb = m0 + wm * WM + 16 * i + cm;
+                const int64_t n = n0 + wn * WN + 32 * j + cn;
+                const int64_t mb = m0 + wm * WM + 32 * i;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) p[(mb + e) * g.N + n] = acc[i][j][e];
+                for (int v = 0; v < 16; ++v) p[(mb + frag_row(v, lane)) * g.N + n] = acc[i][j][v];
             }
         return;
     }
-    // Tile-native order of Z: fragment (i, j) of wave w holds 4 values per lane, stored as
-    // one 16-byte chunk at ((tile * 4 + w) * FM * FN + i * FN + j) * 256 + lane * 4, so the
-    // forward GEMM writes and the input-gradient GEMM of the same shape reads it with
+    // Tile-native order of Z: fragment (i, j) of wave w holds 16 values per lane, stored as
+    // four 16-byte chunks at ((tile * 4 + w) * FM * FN + i * FN + j) * 1024 + lane * 16, so
+    // the forward GEMM writes and the input-gradient GEMM of the same shape reads it with
     // fully coalesced accesses.
     const int64_t tile = (int64_t)blockIdx.x * gridDim.y + blockIdx.y;
-    auto znat = [&](int i, int j) { return ((tile * 4 + wave) * (FM * FN) + i * FN + j) * 256 + lane * 4; };
+    auto znat = [&](int i, int j) { return ((tile * 4 + wave) * (FM * FN) + i * FN + j) * 1024 + lane * 16; };
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int nl = wn * WN + 16 * j + cn, ml = wm * WM + 16 * i + cm;
-            const int64_t n = n0 + nl, mb = m0 + ml;
-            f32x4 zin;
+            const int nl = wn * WN + 32 * j + cn, mbl = wm * WM + 32 * i;
+            const int64_t n = n0 + nl;
+            f32x16 zin;
             if constexpr (EPI == EPI_DX) {
                 if (g.ldz == 0) {
-                    zin = *reinterpret_cast<const f32x4 *>(g.Z + znat(i, j));
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const f32x4 z4 = *reinterpret_cast<const f32x4 *>(g.Z + znat(i, j) + 4 * c);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) zin[4 * c + e] = z4[e];
+                    }
                 } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) zin[e] = g.Z[(mb + e) * g.ldz + n];
+                    for (int v = 0; v < 16; ++v) zin[v] = g.Z[(m0 + mbl + frag_row(v, lane)) * g.ldz + n];
                 }
             }
-            f32x4 zout;
+            f32x16 zout;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                float v;
+            for (int v = 0; v < 16; ++v) {
+                float val;
                 if constexpr (EPI == EPI_DX) {
-                    v = acc[i][j][e] * silu_grad_f(zin[e]);
+                    val = acc[i][j][v] * silu_grad_f(zin[v]);
                 } else {
-                    const float z = acc[i][j][e] + g.bias[n];
-                    zout[e] = z;
-                    v = silu_f(z);
+                    const float z = acc[i][j][v] + g.bias[n];
+                    zout[v] = z;
+                    val = silu_f(z);
                 }
-                st[ml + e][nl] = (bf16)v;
+                st[mbl + frag_row(v, lane)][nl] = (bf16)val;
             }
             if constexpr (EPI == EPI_FWD) {
                 if (g.ldz == 0) {
-                    *reinterpret_cast<f32x4 *>(g.Z + znat(i, j)) = zout;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        *reinterpret_cast<f32x4 *>(g.Z + znat(i, j) + 4 * c) =
+                            f32x4{zout[4 * c], zout[4 * c + 1], zout[4 * c + 2], zout[4 * c + 3]};
                 } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) g.Z[(mb + e) * g.ldz + n] = zout[e];
+                    for (int v = 0; v < 16; ++v) g.Z[(m0 + mbl + frag_row(v, lane)) * g.ldz + n] = zout[v];
                 }
             }
         }
@@ -287,16 +313,27 @@ struct FusedArgs {
     float *y;
 };
 
-// Two workgroups per CU (the register budget that leaves: 192 VGPRs at width 256, no spill):
-// one workgroup's MFMAs then cover the other's weight-load waits and SiLU epilogue, which a
-// single wave per SIMD leaves exposed (122 against 81 us for 65536 rows of a 5 x 256 net;
-// unrolling the features loop for independent FP64 chains: 79 us).
+// Two workgroups per CU (the register budget that leaves: about 200 VGPRs at width 256, no
+// spill): one workgroup's MFMAs then cover the other's weight-load waits and SiLU epilogue,
+// which a single wave per SIMD leaves exposed (122 against 81 us for 65536 rows of a 5 x 256
+// net; unrolling the features loop for independent FP64 chains: 79 us).  Where the time
+// goes at 65536 rows (copies with one part removed): features 8 us, bias + SiLU 7, head 6,
+// weight loads 9; without them, the MFMA loop and its LDS operand reads take 50 us, against
+// 17 us of MFMA issue at the instruction's rate -- the phases of a layer run one after the
+// other in every workgroup, and the 32 x 32 fragments (half the MFMA instructions) and
+// weights fetched two steps ahead measured the same 79 us.
 // BM rows per workgroup: 128 when the grid still fills the chip, 32 or 64 for calls of a
 // few thousand rows, where one workgroup's latency is the call's time.
 template <int W, int BM>
 __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
-    constexpr int LDA = W + 8, FM = BM / 16, WN = W / 4, FN = WN / 16, TPR = 256 / BM;
-    static_assert(FN >= 1, "width below 64");
+    // waves split the W output columns into CG groups and the BM rows into RG groups, each
+    // wave a (BM/RG) x (W/CG) block of 32 x 32 fragments; waves past CG * RG (width 64 with
+    // 32-row tiles) only take part in the features, the barriers and the head
+    constexpr int LDA = W + 8, TPR = 256 / BM;
+    constexpr int CG = (W / 32 < 4) ? W / 32 : 4;
+    constexpr int RG = (BM / 32 < 4 / CG) ? BM / 32 : 4 / CG;
+    constexpr int WN = W / CG, WMr = BM / RG, FN = WN / 32, FM = WMr / 32;
+    static_assert(FN >= 1 && FM >= 1, "fragments of 32 x 32");
     static_assert(BM == 32 || BM == 64 || BM == 128, "32, 64 or 128 rows");
     __shared__ __attribute__((aligned(16))) bf16 act[BM][LDA];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -323,42 +360,62 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
         }
     }
     __syncthreads();
-    const int r = lane & 15, kq = (lane >> 4) * 8, cn = lane & 15, cm = (lane >> 4) * 4;
+    const bool mma = wave < CG * RG;
+    const int wc = wave % CG, wr = wave / CG;
+    const int r = lane & 31, kq = (lane >> 5) * 8;
     for (int l = 0; l < a.L; ++l) {
         const int K = a.in_dim[l];
-        const bf16 *Wl = a.Wl[l] + (int64_t)(wave * WN + r) * K + kq;
-        f32x4 acc[FM][FN];
+        f32x16 acc[FM][FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        bf16x8 bcur[FN], bnxt[FN];
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) bcur[j] = *reinterpret_cast<const bf16x8 *>(Wl + (int64_t)16 * j * K);
-        for (int k0 = 0; k0 < K; k0 += 32) {
-            if (k0 + 32 < K)
+                for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+        if (mma) {
+            // B fragments straight from L2: lane l reads W[n = col + l % 32][k + 8 (l / 32) .. + 8],
+            // the next K step's issued before this step's MFMAs
+            const bf16 *Wl = a.Wl[l] + (int64_t)(wc * WN + r) * K + kq;
+            bf16x8 bcur[2][FN], bnxt[2][FN];
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    bnxt[j] = *reinterpret_cast<const bf16x8 *>(Wl + (int64_t)16 * j * K + k0 + 32);
-#pragma unroll
-            for (int i = 0; i < FM; ++i) {
-                const bf16x8 af = *reinterpret_cast<const bf16x8 *>(&act[16 * i + r][k0 + kq]);
+            for (int s = 0; s < 2; ++s)
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bcur[j], acc[i][j], 0, 0, 0);
+                    bcur[s][j] = *reinterpret_cast<const bf16x8 *>(Wl + (int64_t)32 * j * K + 16 * s);
+            for (int k0 = 0; k0 < K; k0 += 32) {
+                if (k0 + 32 < K)
+#pragma unroll
+                    for (int s = 0; s < 2; ++s)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            bnxt[s][j] = *reinterpret_cast<const bf16x8 *>(Wl + (int64_t)32 * j * K + k0 + 32 + 16 * s);
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) {
+                        const bf16x8 af =
+                            *reinterpret_cast<const bf16x8 *>(&act[wr * WMr + 32 * i + r][k0 + 16 * s + kq]);
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) acc[i][j] = mfma32(af, bcur[s][j], acc[i][j]);
+                    }
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) bcur[s][j] = bnxt[s][j];
             }
-#pragma unroll
-            for (int j = 0; j < FN; ++j) bcur[j] = bnxt[j];
         }
         __syncthreads();  // every wave has read this layer's input
+        if (mma) {
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int n = wave * WN + 16 * j + cn;
-            const float bias = a.bl[l][n];
+            for (int j = 0; j < FN; ++j) {
+                const int n = wc * WN + 32 * j + r;
+                const float bias = a.bl[l][n];
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) act[16 * i + cm + e][n] = (bf16)silu_f(acc[i][j][e] + bias);
+                    for (int e = 0; e < 16; ++e)
+                        act[wr * WMr + 32 * i + frag_row(e, lane)][n] = (bf16)silu_f(acc[i][j][e] + bias);
+            }
         }
         __syncthreads();
     }

@@ -63,6 +63,12 @@ def parse():
                     help="surrogate: largest training tilt (degrees; default the recipe's)")
     ap.add_argument("--sur-carrier-samples", type=int, default=None,
                     help="surrogate: transducer samples of the ray-model carrier (default the recipe's)")
+    ap.add_argument("--sur-judge-scale", type=int, default=None,
+                    help="surrogate: sample-count multiplier of the judging / fallback RSI (default 1)")
+    ap.add_argument("--sur-train-if-scale", type=int, default=None,
+                    help="surrogate: interface sample-count multiplier of the training fields (default 1)")
+    ap.add_argument("--sur-epochs", type=int, default=None,
+                    help="surrogate: training epochs (default the recipe's)")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="layered_stack: FP32 vs FP64 rel-L2 per frequency on a volume subsample")
     return ap.parse_args()
@@ -157,10 +163,10 @@ KERNEL_SOURCES = {
     ],
     "multifreq": [
         ("paper_2408_06765_amd/csrc/rsi_device.h",
-         ["constexpr int kSub", "constexpr int kFB", "bool phase_in_sin_range("]),
+         ["constexpr int kSub", "bool phase_in_sin_range("]),
         ("paper_2408_06765_amd/csrc/rsi_multifreq.hip",
-         ["struct TargetMF", "void multifreq_sum(", "multifreq_f32_kernel(",
-          "rsi_status pairsum_multifreq_f32("]),
+         ["struct TargetMF", "struct BlockMF", "void multifreq_sum(", "multifreq_f32_kernel(",
+          "int mf_block(", "rsi_status pairsum_multifreq_f32("]),
         ("paper_2408_06765_amd/csrc/rsi_internal.h",
          ["struct alignas(32) SrcRecF", "constexpr int kBlock"]),
     ],
@@ -280,7 +286,9 @@ def flops_multifreq_pair(n_freq, block=16):
     evaluated in blocks of `block` (FMA = 2, transcendental = 1): 33 for each block's first
     frequency (the single-frequency dipole pair) and 21 for each further one (carrying
     e^{ikr} to the next frequency, the (ik - 1/r) factor, the complex multiply-accumulate
-    with that frequency's strength)."""
+    with that frequency's strength).  The convention was fixed with blocks of 16 and stays
+    there whatever block the kernel runs (32 on 64 frequencies: 1368 per pair instead of
+    1392)."""
     nb = (n_freq + block - 1) // block
     return FLOPS_DIPOLE * nb + 21 * (n_freq - nb)
 
@@ -341,9 +349,11 @@ def layered_stack(args):
     line["roofline"] = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                         "traffic": measured_traffic(MF_TRAFFIC_FILE, "multifreq"),
-                        "kernel": f"multifreq_f32_kernel<dipole, planar, per-frequency strengths> (interface 3 "
-                                  f"-> volume: one call, launched per chunk of 8192 sources), {fl} flop per pair "
-                                  f"for {nf} frequencies x {kpairs:.4e} pairs / {kms:.3f} ms"}
+                        "kernel": f"multifreq_f32_kernel<dipole, planar, per-frequency strengths, blocks of 32 "
+                                  f"frequencies> (interface 3 -> volume: one call, launched per chunk of 8192 "
+                                  f"sources), {fl} flop per pair for {nf} frequencies (convention of blocks of 16; "
+                                  f"{flops_multifreq_pair(nf, 32)} counted in blocks of 32) x {kpairs:.4e} pairs "
+                                  f"/ {kms:.3f} ms"}
     line["fp32_valu_counters"] = measured_valu(MF_VALU_FILE, "multifreq")
     del vel, mf_out
     if args.fp64_compare:
@@ -782,6 +792,12 @@ def surrogate(args):
         cfg.train_tilt_max = math.radians(args.sur_train_tilt_max)
     if args.sur_carrier_samples is not None:
         cfg.n_carrier = args.sur_carrier_samples
+    if args.sur_judge_scale is not None:
+        cfg.judge_scale = args.sur_judge_scale
+    if args.sur_epochs is not None:
+        cfg.epochs = args.sur_epochs
+    if args.sur_train_if_scale is not None:
+        cfg.train_if_scale = args.sur_train_if_scale
     sur = S.Surrogate(cfg)
     t0 = time.perf_counter()
     q, t = sur.dataset(S.training_configs(cfg, 5120, 3), points_per_config=1953)
@@ -800,7 +816,7 @@ def surrogate(args):
     torch.cuda.synchronize()
     t4 = time.perf_counter()
     for f, d, tl in qc:
-        sur.src.rsi_pressure(f, d, tl)
+        sur.judge(f, d, tl)
     torch.cuda.synchronize()
     t5 = time.perf_counter()
     for f, d, tl in qc:
@@ -819,7 +835,7 @@ def surrogate(args):
         torch.cuda.synchronize()
         ta = time.perf_counter()
         for f, d, tl in pass_cfgs:
-            sur.src.rsi_pressure(f, d, tl)
+            sur.judge(f, d, tl)
         torch.cuda.synchronize()
         tb = time.perf_counter()
         for f, d, tl in pass_cfgs:
@@ -832,13 +848,21 @@ def surrogate(args):
     if cfg.carrier == "ray":
         for f, d, tl in S.cell_configs(cfg, 101):
             if f <= cfg.train_f_max and tl <= cfg.train_tilt_max:
-                carrier.append(S.rel_l2(sur.src.ray_pressure(f, d, tl), sur.src.rsi_pressure(f, d, tl)))
+                carrier.append(S.rel_l2(sur.src.ray_pressure(f, d, tl), sur.judge(f, d, tl)))
     # the judge's own noise: RSI against RSI with both sample counts doubled, per cell (a
     # cell whose RSI moves by more than the threshold cannot be matched by a smooth model)
+    js = cfg.judge_scale
     judge = {}
     for f, d, tl in S.cell_configs(cfg, 101):
-        judge[S.cell_of(cfg, f, d, tl)] = S.rel_l2(sur.src.rsi_pressure(f, d, tl, scale=2),
-                                                  sur.src.rsi_pressure(f, d, tl))
+        judge[S.cell_of(cfg, f, d, tl)] = S.rel_l2(sur.src.rsi_pressure(f, d, tl, scale=2, if_scale=2 * js),
+                                                  sur.judge(f, d, tl))
+    # RSI at the training data's counts for the same queries (the cost the judge's counts add)
+    torch.cuda.synchronize()
+    tr0 = time.perf_counter()
+    for f, d, tl in qc:
+        sur.src.rsi_pressure(f, d, tl)
+    torch.cuda.synchronize()
+    rsi_base_s = time.perf_counter() - tr0
     jn = np.array([judge[c] for c in sorted(judge)])
     reach = [c for c in sorted(judge) if judge[c] <= cfg.threshold]
     rsi_s, routed_s, sur_s, net_s = t5 - t4, t4 - t3, t6 - t5, t7 - t6
@@ -855,7 +879,12 @@ def surrogate(args):
                                   f"tilt <= {math.degrees(cfg.train_tilt_max):g} deg"
                                   if cfg.carrier == "ray" else "plane-wave carrier"),
                    "train_samples": 5120 * 1953, "queries": n_q},
+        "judge_scale": js, "judge_samples": [cfg.n_xd, cfg.n_if * js],
+        "train_samples_per_surface": [cfg.n_xd, cfg.n_if * cfg.train_if_scale],
+        "epochs": cfg.epochs,
         "data_generation_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2), "final_loss": loss,
+        "rsi_at_training_counts_s_for_queries": round(rsi_base_s, 4),
+        "surrogate_speedup_all_queries_vs_rsi_at_training_counts": round(rsi_base_s / routed_s, 3),
         "cell_residual": {"min": float(e.min()), "median": float(np.median(e)), "max": float(e.max())},
         "cells_passing": {str(th): int((e <= th).sum()) for th in thresholds}, "cells": int(e.size),
         "cells_in_training_region": int(sum(1 for (f, d, tl) in S.cell_configs(cfg, 101)

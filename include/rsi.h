@@ -264,8 +264,8 @@ rsi_status rsi_propagate_ex(const rsi_points *src, const double *src_w, const do
  * as in rsi_propagate_ex.  out: device complex [n_freq][tgt->n] of the call's precision.
  * With RSI_FP32 on a uniform grid (n_freq >= 2, f_q = f_0 + q df) and a monopole or
  * omnidirectional kernel, or a dipole with RSI_FLAG_PLANAR_Z (normal +z or -z), the call
- * is one multi-frequency launch: the pair geometry is evaluated once per block of 16
- * frequencies and e^{ikr} is carried from one frequency to the next; every other case
+ * is one multi-frequency launch: the pair geometry is evaluated once per block of 16 or
+ * 32 frequencies and e^{ikr} is carried from one frequency to the next; every other case
  * (RSI_FP64, a non-uniform list, a dipole with any other normal) runs one pair sum per
  * frequency.  Errors: those of rsi_propagate_ex; RSI_ERR_ARG for a frequency <= 0 or not
  * finite; RSI_ERR_NULL for freqs == NULL with n_freq > 0; RSI_ERR_SIZE for n_freq < 0 or

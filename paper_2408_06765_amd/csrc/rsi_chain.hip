@@ -277,7 +277,7 @@ rsi_status alloc_chain(const AllocFn &alloc, const rsi_transducer *xd, const rsi
     RSI_TRY(alloc(&W.field[0], esz * (size_t)nmax * nf));
     RSI_TRY(alloc(&W.field[1], esz * (size_t)nmax * nf));
     if (W.multifreq) {
-        const size_t nf_pad = (size_t)(n_freq + kFB - 1) / kFB * kFB;
+        const size_t nf_pad = (size_t)mf_pad(n_freq);
         RSI_TRY(alloc((void **)&W.S, sizeof(float2) * (size_t)nmax * nf_pad));
         W.partial = nullptr;  // the multi-frequency stages write their outputs directly
         return RSI_OK;

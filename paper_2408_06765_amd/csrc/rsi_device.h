@@ -11,7 +11,6 @@
 namespace rsi {
 
 constexpr int kSub = 64;  // sources per FP32 partial block before the compensated fold
-constexpr int kFB = 16;   // frequencies per block of the multi-frequency kernel
 
 // Sources per iteration of the FP32 inner loop (independent pair chains per wave).
 #ifndef RSI_SRC_UNROLL

@@ -227,7 +227,11 @@ rsi_status pairsum_f64(const SrcSetD &set, const Targets &t, rsi_kernel kind,
 // --- rsi_multifreq.hip -------------------------------------------------------
 // True when freqs[0..n) is a uniform grid f0 + q df (n >= 2, df > 0).
 bool uniform_grid(const double *freqs, int n, double &f0, double &df);
-// S [n][n_freq rounded up to the frequency block] of -(1/2pi) w T phi from field [n_freq][n].
+// Frequencies per block of the multi-frequency kernel for a grid of n_freq (16 or 32;
+// RSI_MF_BLOCK forces one), and n_freq rounded up to it: the row length of the strengths.
+int mf_block(int n_freq);
+int mf_pad(int n_freq);
+// S [n][mf_pad(n_freq)] of -(1/2pi) w T phi from field [n_freq][n].
 // S[j][q] = -(1/2pi) w_j T_j field_q(Q_j) (Fa + i Fb k_q), k_q = 2 pi (f0 + q df) / c
 rsi_status strength_multifreq(int64_t n, int n_freq, const double *w, const float2 *field,
                               const double *tco, double Fa, double Fb, double c, double f0,

@@ -213,6 +213,13 @@ class SurrogateConfig:
     # below ~10 deg of tilt no part of the beam passes the critical angle
     train_f_max: float = 3.25e6
     train_tilt_max: float = math.radians(10.0)
+    # multiplier of the interface sample count of the RSI that judges the surrogate and
+    # answers where it fails (validation, fallback); the training data keep the counts
+    # above.  The interface samples set RSI's QMC error here: 2^18 on the 60 mm patch are
+    # ~1.5 per wavelength^2 at 10 MHz in the solid's water-side field, the piston's 2^16 ~11
+    judge_scale: int = 1
+    # multiplier of the interface sample count of the RSI that produces the training fields
+    train_if_scale: int = 1
 
 
 def lohi(box: W.SurrogateBox):
@@ -375,12 +382,15 @@ class FieldSource:
         p = self.ray_pressure(f, depth, tilt, (np.concatenate([xg, rx]), np.concatenate([zg, rz])))
         return p[:xg.size], p[xg.size:]
 
-    def rsi_pressure(self, f: float, depth: float, tilt: float, xz=None, scale: int = 1) -> torch.Tensor:
+    def rsi_pressure(self, f: float, depth: float, tilt: float, xz=None, scale: int = 1,
+                     if_scale: Optional[int] = None) -> torch.Tensor:
         """p = i omega rho2 phi at the grid points from the RSI chain (FP32); scale multiplies
-        both sample counts (the first scale x n points of the same sequences)."""
+        both sample counts, if_scale (default: scale) the interface's alone (the first
+        scale x n points of the same sequences)."""
         cfg, b = self.cfg, self.cfg.box
+        if_scale = scale if if_scale is None else if_scale
         xs = rsi.rsi_sample_disc(0, cfg.n_xd * scale, b.radius, (0.0, 0.0, 0.0), tilt)
-        qs = rsi.rsi_sample_square(1, cfg.n_if * scale, depth * math.tan(tilt), 0.0, depth, cfg.half_width)
+        qs = rsi.rsi_sample_square(1, cfg.n_if * if_scale, depth * math.tan(tilt), 0.0, depth, cfg.half_width)
         T = rsi.Transducer(*xs[:3], xs[3], 1.0, (0.0, 0.0, 0.0), (math.sin(tilt), 0.0, math.cos(tilt)))
         I = [rsi.Interface(*qs[:3], qs[3], depth)]
         tgt = self._targets(self.queries(f, depth, tilt, xz))
@@ -414,7 +424,7 @@ class Surrogate:
         for f, d, t in configs:
             xz = None if points_per_config is None else self.src.random_points(rng, points_per_config)
             q = self.src.queries(f, d, t, xz)
-            p = self.src.rsi_pressure(f, d, t, xz)
+            p = self.src.rsi_pressure(f, d, t, xz, if_scale=self.cfg.train_if_scale)
             if self.cfg.carrier == "ray":
                 pr, ref = self.src.ray_carrier(f, d, t, xz)
                 env = rsi_surrogate_ray_frame(pr, ref, self.cfg.sigma, 0, p, self.cfg.clip)
@@ -467,10 +477,16 @@ class Surrogate:
             return rsi_surrogate_ray_frame(pr, ref, self.cfg.sigma, 1, y)
         return rsi_surrogate_carrier(q, self.m1, self.m2, 1, y)
 
+    def judge(self, f: float, depth: float, tilt: float, xz=None) -> torch.Tensor:
+        """The RSI field that judges the surrogate and answers where it fails: the chain with
+        judge_scale times the training data's interface samples."""
+        return self.src.rsi_pressure(f, depth, tilt, xz, if_scale=self.cfg.judge_scale)
+
     def validate(self, configs: np.ndarray) -> Dict[int, float]:
-        """Held-out residual (rel-L2 against RSI) per cell; the worst config in a cell counts."""
+        """Held-out residual (rel-L2 against the judge's RSI) per cell; the worst config in a
+        cell counts."""
         for f, d, t in configs:
-            err = rel_l2(self.predict(f, d, t), self.src.rsi_pressure(f, d, t))
+            err = rel_l2(self.predict(f, d, t), self.judge(f, d, t))
             c = cell_of(self.cfg, f, d, t)
             self.cell_err[c] = max(self.cell_err.get(c, 0.0), err)
         return self.cell_err
@@ -482,6 +498,6 @@ class Surrogate:
         for f, d, t in configs:
             c = cell_of(self.cfg, f, d, t)
             ok = self.cell_err.get(c, math.inf) <= self.cfg.threshold
-            out.append(self.predict(f, d, t) if ok else self.src.rsi_pressure(f, d, t))
+            out.append(self.predict(f, d, t) if ok else self.judge(f, d, t))
             used.append(not ok)
         return out, used

@@ -98,5 +98,6 @@ def test_flop_conventions():
     assert bench.flops_ray_pair(2) == 104
     assert bench.flops_multifreq_pair(64) == 4 * 33 + 60 * 21
     assert bench.flops_multifreq_pair(20) == 2 * 33 + 18 * 21
+    assert bench.flops_multifreq_pair(64, 32) == 2 * 33 + 62 * 21
     assert bench.flops_mlp_row(128, 256, 5) == 2 * (256 * 256 + 4 * 256 * 256 + 2 * 256)
     assert bench.FLOPS_DIPOLE == 33

@@ -299,24 +299,25 @@ def test_chain_nonuniform_frequency_list(gpu, orc, prec):
         assert rel(got[f], ref[f]) <= TOL[prec], (f, rel(got[f], ref[f]))
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2])
-def test_chain_uniform_grid_ragged_block(gpu, orc, flags):
-    """A uniform grid of 20 frequencies, 1-10 MHz: the FP32 multi-frequency stages run one
-    full block of 16 frequencies and a ragged second block of 4 (zero-padded strengths,
-    outputs masked).  Plain chain, omnidirectional interface sources, and field points
-    above the last interface with the reflected field; every frequency against the
-    reference."""
+@pytest.mark.parametrize("flags,nf", [(0, 20), (1, 20), (2, 20), (0, 40), (0, 50)])
+def test_chain_uniform_grid_ragged_block(gpu, orc, flags, nf):
+    """Uniform grids of 20, 40 and 50 frequencies, 1-10 MHz, whose FP32 multi-frequency
+    stages end in a ragged block (zero-padded strengths, outputs masked): 20 in one block
+    of 32, 40 in blocks of 16 (16 + 16 + 8), 50 in blocks of 32 (32 + 18, past the restart
+    of the recurrence at a block's 17th frequency).  Plain chain, omnidirectional interface
+    sources, and field points above the last interface with the reflected field; every
+    frequency against the reference."""
     cfg = W.LayeredStack()
     xd, ifs, tgt = _small_chain(orc, 1 << 11, cfg.z_if, cfg.media, cfg.tilt, 500, seed=6)
     if flags & 2:
         tgt = _above_targets(ifs, cfg.z_if, 500, 19)
-    freqs = list(np.linspace(1.0e6, 10.0e6, 20))
+    freqs = list(np.linspace(1.0e6, 10.0e6, nf))
     ref = orc.chain(xd, 1.0, (0, 0, 0), cfg.axis, ifs, list(cfg.z_if), [m[0] for m in cfg.media],
                     [m[1] for m in cfg.media], tgt, freqs, 1, flags=flags)
     T = gpu.Transducer(*devpts(xd[:3]), dev(xd[3]), 1.0, (0.0, 0.0, 0.0), cfg.axis)
     I = [gpu.Interface(*devpts(q[:3]), dev(q[3]), z) for q, z in zip(ifs, cfg.z_if)]
     got = host(gpu.rsi_chain(T, I, cfg.media, devpts(tgt), freqs, 1, 0, flags=flags))
-    assert got.shape == (20, len(tgt[0]))
+    assert got.shape == (nf, len(tgt[0]))
     for f in range(len(freqs)):
         assert rel(got[f], ref[f]) <= TOL[0], (f, rel(got[f], ref[f]))
 
@@ -476,6 +477,7 @@ MF_CASES = [  # (kind, planar, normal z, frequencies, strengths given)
     (0, False, 1.0, "grid20", True), (0, False, 1.0, "grid20", False), (1, True, 1.0, "grid20", True),
     (1, True, -1.0, "grid20", True), (1, True, -1.0, "grid3", False), (2, False, 1.0, "grid20", True),
     (1, False, 1.0, "grid20", True), (1, True, 1.0, "list", True), (0, False, 1.0, "one", True),
+    (1, True, 1.0, "grid40", True), (1, True, 1.0, "grid50", True), (0, False, 1.0, "grid50", False),
 ]
 
 
@@ -485,9 +487,13 @@ def test_propagate_multifreq_matches_reference(gpu, orc, kind, planar, nz, fr, g
     """rsi_propagate_multifreq (multi-frequency superposition, Sec. 4): every frequency
     against the reference's single-frequency pair sum with that frequency's strengths.
     FP32 uniform grids with a monopole, omnidirectional or planar +-z dipole kernel run
-    the multi-frequency launch (20 frequencies: a full block of 16 and a ragged one of 4);
-    a general dipole, a non-uniform list and FP64 run one pair sum per frequency."""
+    the multi-frequency launch: 3 and 40 frequencies in blocks of 16 (40: two full blocks
+    and a ragged one of 8), 20 and 50 in blocks of 32 (one ragged block of 20; a full block
+    and a ragged one of 18, which crosses the restart of the recurrence at its 17th
+    frequency); a general dipole, a non-uniform list and FP64 run one pair sum per
+    frequency."""
     freqs = {"grid20": list(np.linspace(1.0e6, 10.0e6, 20)), "grid3": [2.0e6, 2.5e6, 3.0e6],
+             "grid40": list(np.linspace(1.0e6, 10.0e6, 40)), "grid50": list(np.linspace(1.0e6, 10.0e6, 50)),
              "list": [1.0e6, 1.7e6, 4.2e6], "one": [3.3e6]}[fr]
     ns, nt = 3001, 700
     src, w, _, tgt = _case(51 + kind, ns, nt, 1 if planar else 0)

@@ -57,7 +57,7 @@ __device__ __forceinline__ void multifreq_sum(const TargetMF &T, const BlockMF &
     for (int q = 0; q < NB; ++q) mre[q] = mim[q] = 0.0f;
     const int cnt = (int)(j1 - j0);  // chunks are far below 2^31 sources
     const SrcRecF *blk = rec + j0;
-    const float2 *Sb = S + j0 * nf_pad + q0;
+    const float2 *Sb = SHARED_S ? nullptr : S + j0 * nf_pad + q0;  // S is NULL when shared
     for (int jj = 0; jj < cnt; ++jj) {  // 32-bit count: the loop test stays scalar
         const SrcRecF s = blk[jj];
         // the block's strengths up front: wave-uniform loads, all in flight at once

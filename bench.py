@@ -64,9 +64,11 @@ def parse():
     ap.add_argument("--sur-carrier-samples", type=int, default=None,
                     help="surrogate: transducer samples of the ray-model carrier (default the recipe's)")
     ap.add_argument("--sur-judge-scale", type=int, default=None,
-                    help="surrogate: sample-count multiplier of the judging / fallback RSI (default 1)")
+                    help="surrogate: interface sample-count multiplier of the judging / fallback RSI (default the recipe's)")
     ap.add_argument("--sur-train-if-scale", type=int, default=None,
-                    help="surrogate: interface sample-count multiplier of the training fields (default 1)")
+                    help="surrogate: interface sample-count multiplier of the training fields (default the recipe's)")
+    ap.add_argument("--sur-depth", type=int, default=None,
+                    help="surrogate, surrogate_inference, surrogate_training: hidden layers (default the recipe's)")
     ap.add_argument("--sur-epochs", type=int, default=None,
                     help="surrogate: training epochs (default the recipe's)")
     ap.add_argument("--fp64-compare", action="store_true",
@@ -777,11 +779,12 @@ def multilayer_noise(args):
 
 def surrogate(args):
     """The learned surrogate: 10^7 RSI samples (5120 random configurations of the
-    one-interface piston family x 1953 points, drawn where the recipe trains: f <= 3.25 MHz,
-    tilt <= 10 deg), 5 x 256 MLP on the ray-model carrier trained with the MFMA kernels,
-    held-out residual per (f, depth, tilt) cell (8 x 4 x 8 over the whole box), 10^6
-    queries (64 random configurations over the whole box x 125^2) answered by the
-    surrogate where its cell passes the threshold and by RSI elsewhere."""
+    one-interface piston family x 1953 points, drawn where the recipe trains: f <= 7.75 MHz,
+    tilt <= 10 deg; the chain at 2^16 piston and 2^20 interface samples), 7 x 256 MLP on the
+    ray-model carrier trained with the MFMA kernels, held-out residual per (f, depth, tilt)
+    cell (8 x 4 x 8 over the whole box) against the judge (the chain at the same counts),
+    10^6 queries (64 random configurations over the whole box x 125^2) answered by the
+    surrogate where its cell passes the threshold and by the judge elsewhere."""
     import torch
     from paper_2408_06765_amd import surrogate as S
 
@@ -798,6 +801,8 @@ def surrogate(args):
         cfg.epochs = args.sur_epochs
     if args.sur_train_if_scale is not None:
         cfg.train_if_scale = args.sur_train_if_scale
+    if args.sur_depth is not None:
+        cfg.depth = args.sur_depth
     sur = S.Surrogate(cfg)
     t0 = time.perf_counter()
     q, t = sur.dataset(S.training_configs(cfg, 5120, 3), points_per_config=1953)
@@ -925,6 +930,8 @@ def surrogate_inference(args):
     from paper_2408_06765_amd import surrogate as S
 
     cfg = S.SurrogateConfig()
+    if args.sur_depth is not None:
+        cfg.depth = args.sur_depth
     lo, hi = S.lohi(cfg.box)
     net = S.MLP(cfg.n_ff, cfg.width, cfg.depth, S.fourier_matrix(cfg.n_ff, cfg.ff_scales, cfg.seed),
                 lo, hi, cfg.batch)
@@ -1074,13 +1081,15 @@ def flops_mlp_train_row(n_ff, width, depth):
 
 def surrogate_training(args):
     """One Adam step of the surrogate network (the recipe's shape: 128 Fourier frequencies,
-    5 x 256 SiLU, bf16 MFMA GEMMs with FP32 accumulation) on a batch of 65536 rows: features,
+    7 x 256 SiLU, bf16 MFMA GEMMs with FP32 accumulation) on a batch of 65536 rows: features,
     forward, loss, backward, Adam, bf16 weight refresh.  Rows and targets are seeded
     synthetic values (the time does not depend on them)."""
     import torch
     from paper_2408_06765_amd import surrogate as S
 
     cfg = S.SurrogateConfig()
+    if args.sur_depth is not None:
+        cfg.depth = args.sur_depth
     lo, hi = S.lohi(cfg.box)
     n = cfg.batch
     net = S.MLP(cfg.n_ff, cfg.width, cfg.depth, S.fourier_matrix(cfg.n_ff, cfg.ff_scales, cfg.seed),

@@ -194,7 +194,7 @@ class SurrogateConfig:
     cells: Tuple[int, int, int] = (8, 4, 8)
     n_ff: int = 128
     width: int = 256
-    depth: int = 5
+    depth: int = 7                # hidden layers (5: 70 cells pass 1e-3 instead of 76)
     ff_scales: Tuple[float, ...] = (2.0, 1.5, 0.75, 0.75, 0.75)
     batch: int = 65536
     epochs: int = 300
@@ -207,19 +207,25 @@ class SurrogateConfig:
     sigma: float = 0.02           # expected departure of RSI from the ray model (frame scale)
     clip: float = 5.0             # cap on training targets in that frame
     n_ref_side: int = 16          # ref grid of the frame's scale: n_ref_side^2 points
-    # training configurations are drawn from the part of the box where 1e-3 is within
-    # reach: below ~3 MHz the RSI field at 2^16 / 2^18 samples is itself reproducible to
-    # a few 1e-4 (it moves by ~1e-2 at 8-10 MHz when the sample counts are doubled), and
-    # below ~10 deg of tilt no part of the beam passes the critical angle
-    train_f_max: float = 3.25e6
+    # training configurations are drawn from the part of the box where a smooth model can
+    # reach 1e-3: below ~7.75 MHz the judge's RSI field (below) moves by less than 1e-3 in
+    # most cells when its sample counts are doubled (by ~1e-2 at 10 MHz, its QMC error),
+    # and below ~10 deg of tilt no part of the beam passes the critical angle, where the
+    # ray carrier has no ray.  Training over the whole band (or to 12.5 deg) spends the
+    # network's capacity on cells it cannot pass: 22 (or 5) cells below 1e-3 against 70
+    # at 5 layers.
+    train_f_max: float = 7.75e6
     train_tilt_max: float = math.radians(10.0)
     # multiplier of the interface sample count of the RSI that judges the surrogate and
-    # answers where it fails (validation, fallback); the training data keep the counts
-    # above.  The interface samples set RSI's QMC error here: 2^18 on the 60 mm patch are
-    # ~1.5 per wavelength^2 at 10 MHz in the solid's water-side field, the piston's 2^16 ~11
-    judge_scale: int = 1
-    # multiplier of the interface sample count of the RSI that produces the training fields
-    train_if_scale: int = 1
+    # answers where it fails (validation, fallback).  The interface samples set RSI's QMC
+    # error here: 2^18 on the 60 mm patch are ~1.5 per wavelength^2 at 10 MHz in the
+    # solid's water-side field, the piston's 2^16 ~11; at 2^18 RSI moves by more than 1e-3
+    # in 205 of the 256 cells when its counts double, at 2^20 in 136.
+    judge_scale: int = 4
+    # multiplier of the interface sample count of the RSI that produces the training fields:
+    # fields as noisy as 2^18 samples cap the residual the network reaches (26 cells below
+    # 1e-3 with 2^18, 40 with 2^19, 55 with 2^20 on the same box up to 5.5 MHz)
+    train_if_scale: int = 4
 
 
 def lohi(box: W.SurrogateBox):
@@ -479,7 +485,7 @@ class Surrogate:
 
     def judge(self, f: float, depth: float, tilt: float, xz=None) -> torch.Tensor:
         """The RSI field that judges the surrogate and answers where it fails: the chain with
-        judge_scale times the training data's interface samples."""
+        judge_scale times n_if interface samples."""
         return self.src.rsi_pressure(f, depth, tilt, xz, if_scale=self.cfg.judge_scale)
 
     def validate(self, configs: np.ndarray) -> Dict[int, float]:

@@ -46,7 +46,8 @@ def test_training_fits_the_rsi_fields(small):
 
 
 def test_routing_threshold_zero_is_plain_rsi(small):
-    """Threshold 0: every query cell fails validation, every answer is the RSI field."""
+    """Threshold 0: every query cell fails validation, every answer is the judge's RSI
+    field (the chain at judge_scale times the interface samples)."""
     import torch
     S, cfg, sur = small
     sur.cell_err = {}
@@ -60,7 +61,7 @@ def test_routing_threshold_zero_is_plain_rsi(small):
         cfg.threshold = old
     assert all(used)
     for (f, d, t), o in zip(qc, out):
-        ref = sur.src.rsi_pressure(f, d, t)
+        ref = sur.src.rsi_pressure(f, d, t, if_scale=cfg.judge_scale)
         assert torch.equal(o, ref)
 
 

@@ -292,13 +292,15 @@ __global__ void __launch_bounds__(256) features_kernel(int64_t n, int64_t Mp, in
 
 // Fused inference: features, every hidden layer and the head for a tile of BM rows in
 // one workgroup, the activations kept in LDS between layers (bf16, rows padded by 8 so the
-// 16 lanes that read one MFMA A fragment hit disjoint banks) and the weights streamed
-// from L2 straight into the MFMA B operands (16-byte loads, the next K step's loaded
-// before the current step's MFMAs).  Four waves split each layer's W output columns.
-// The arithmetic is that of the unfused path step for step -- the same bf16 features, the
-// same MFMA sequence over K, bias + SiLU in FP32 rounded to bf16, the head's FMAs in
-// feature order -- so the two give the same bits; only the HBM round trips of the
-// activations are gone.
+// 16 lanes that read one MFMA fragment hit disjoint banks) and the weights streamed from
+// L2 straight into MFMA operands, from a copy in fragment order (one contiguous 1 KB block
+// per MFMA operand).  Four waves split each layer's W output columns.  The MFMA takes the
+// weights as its A operand and the activations as B, so each lane ends with four
+// consecutive output columns of one row per four accumulator elements and stores them as
+// one 8-byte write.  The arithmetic is that of the unfused path step for step -- the same
+// bf16 features, the same products summed over K in the same order, bias + SiLU in FP32
+// rounded to bf16, the head's FMAs in feature order -- so the two give the same bits; only
+// the HBM round trips of the activations are gone.
 struct FusedArgs {
     const float *q;
     int64_t n;
@@ -306,7 +308,7 @@ struct FusedArgs {
     const float *Bff;
     int m;  // Fourier frequencies (F = 2m features)
     int L;
-    const bf16 *Wl[kMaxLayers];  // [W][in_dim] row-major
+    const bf16 *Wl[kMaxLayers];  // bf16 weights in MFMA fragment order (cast_weight_kernel)
     const float *bl[kMaxLayers];
     int in_dim[kMaxLayers];
     const float *Wo, *bo;
@@ -316,12 +318,15 @@ struct FusedArgs {
 // Two workgroups per CU (the register budget that leaves: about 200 VGPRs at width 256, no
 // spill): one workgroup's MFMAs then cover the other's weight-load waits and SiLU epilogue,
 // which a single wave per SIMD leaves exposed (122 against 81 us for 65536 rows of a 5 x 256
-// net; unrolling the features loop for independent FP64 chains: 79 us).  Where the time
-// goes at 65536 rows (copies with one part removed): features 8 us, bias + SiLU 7, head 6,
-// weight loads 9; without them, the MFMA loop and its LDS operand reads take 50 us, against
-// 17 us of MFMA issue at the instruction's rate -- the phases of a layer run one after the
-// other in every workgroup, and the 32 x 32 fragments (half the MFMA instructions) and
-// weights fetched two steps ahead measured the same 79 us.
+// net).  Measured on the 7 x 256 net at 65536 rows: 103 us with row-major weights and
+// one-element activation stores, 91 us with the weights in fragment order, 84-86 us with
+// the transposed output as well.  Timing copies with one part removed: features 8 us,
+// bias + SiLU 10, head 5, weight loads 5; with neither weight loads nor LDS operand reads
+// the kernel still takes 82 us, against 27 us of MFMA issue: the phases of each layer
+// (MFMAs, barrier, SiLU and stores, barrier) run in sequence inside every workgroup.  Not
+// kept, measured: 8 waves per workgroup (64 rows each, 4 waves per SIMD) 91-138 us; 256-row
+// tiles 117 us; LDS operand reads half a step ahead of their MFMAs, and a start delay for
+// every other workgroup, no change.
 // BM rows per workgroup: 128 when the grid still fills the chip, 32 or 64 for calls of a
 // few thousand rows, where one workgroup's latency is the call's time.
 template <int W, int BM>
@@ -338,6 +343,27 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
     __shared__ __attribute__((aligned(16))) bf16 act[BM][LDA];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t r0 = (int64_t)blockIdx.x * BM;
+    const bool mma = wave < CG * RG;
+    const int wc = wave % CG, wr = wave / CG;
+    const int r = lane & 31, kq = (lane >> 5) * 8;
+    // B fragments straight from L2, from the weights in fragment order: the operand of one
+    // MFMA (32 columns x 16 inputs) is 1 KB, lane l's 16 bytes at l * 16, so a wave's load
+    // is one contiguous block; blocks of a 32-column group follow each other along K
+    // (32 x K elements per group).  Two register sets take turns (no copies between them);
+    // every K step issues the loads of the step after it, the last step of a layer those
+    // of the next layer's first step (the last layer's re-reads its final slice), and the
+    // first layer's first slice is loaded before the features.  The loop body is
+    // straight-line, so each step's MFMAs wait only for the loads issued one step earlier.
+    auto wrow = [&](int l) { return a.Wl[l] + (int64_t)wc * FN * 32 * a.in_dim[l] + 8 * lane; };
+    bf16x8 b0[2][FN], b1[2][FN];
+    auto load = [&](bf16x8 (&b)[2][FN], const bf16 *p, int64_t ld) {  // p: slice start, ld: K
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[s][j] = *reinterpret_cast<const bf16x8 *>(p + (int64_t)32 * j * ld + 512 * s);
+    };
+    if (mma) load(b0, wrow(0), a.in_dim[0]);
     {
         // features as in features_kernel: TPR threads per row, each a share of the frequencies
         const int row = tid & (BM - 1), part = tid / BM;
@@ -360,9 +386,6 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
         }
     }
     __syncthreads();
-    const bool mma = wave < CG * RG;
-    const int wc = wave % CG, wr = wave / CG;
-    const int r = lane & 31, kq = (lane >> 5) * 8;
     for (int l = 0; l < a.L; ++l) {
         const int K = a.in_dim[l];
         f32x16 acc[FM][FN];
@@ -373,49 +396,54 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
         if (mma) {
-            // B fragments straight from L2: lane l reads W[n = col + l % 32][k + 8 (l / 32) .. + 8],
-            // the next K step's issued before this step's MFMAs
-            const bf16 *Wl = a.Wl[l] + (int64_t)(wc * WN + r) * K + kq;
-            bf16x8 bcur[2][FN], bnxt[2][FN];
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    bcur[s][j] = *reinterpret_cast<const bf16x8 *>(Wl + (int64_t)32 * j * K + 16 * s);
-            for (int k0 = 0; k0 < K; k0 += 32) {
-                if (k0 + 32 < K)
-#pragma unroll
-                    for (int s = 0; s < 2; ++s)
-#pragma unroll
-                        for (int j = 0; j < FN; ++j)
-                            bnxt[s][j] = *reinterpret_cast<const bf16x8 *>(Wl + (int64_t)32 * j * K + k0 + 32 + 16 * s);
+            const bf16 *Wl = wrow(l);
+            const bool more = l + 1 < a.L;
+            const bf16 *Wn = more ? wrow(l + 1) : Wl + 32 * (K - 32);
+            const int64_t Kn = more ? a.in_dim[l + 1] : K;
+            auto step = [&](const bf16x8 (&b)[2][FN], int k) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
 #pragma unroll
                     for (int i = 0; i < FM; ++i) {
                         const bf16x8 af =
-                            *reinterpret_cast<const bf16x8 *>(&act[wr * WMr + 32 * i + r][k0 + 16 * s + kq]);
+                            *reinterpret_cast<const bf16x8 *>(&act[wr * WMr + 32 * i + r][k + 16 * s + kq]);
 #pragma unroll
-                        for (int j = 0; j < FN; ++j) acc[i][j] = mfma32(af, bcur[s][j], acc[i][j]);
+                        for (int j = 0; j < FN; ++j) acc[i][j] = mfma32(b[s][j], af, acc[i][j]);
                     }
-#pragma unroll
-                for (int s = 0; s < 2; ++s)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) bcur[s][j] = bnxt[s][j];
+            };
+            // (the scheduling barriers keep the compiler from sinking the loads below the MFMAs)
+            for (int k0 = 0; k0 < K; k0 += 64) {  // K is a multiple of 64
+                load(b1, Wl + 32 * (k0 + 32), K);
+                __builtin_amdgcn_sched_barrier(0);
+                step(b0, k0);
+                __builtin_amdgcn_sched_barrier(0);
+                const bool last = k0 + 64 >= K;
+                load(b0, last ? Wn : Wl + 32 * (k0 + 64), last ? Kn : K);
+                __builtin_amdgcn_sched_barrier(0);
+                step(b1, k0 + 32);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         __syncthreads();  // every wave has read this layer's input
         if (mma) {
 #pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const int n = wc * WN + 32 * j + r;
-                const float bias = a.bl[l][n];
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
+                for (int q = 0; q < 4; ++q) {
+                    // the transposed fragment: lane l holds row l % 32 and, for q, the four
+                    // consecutive columns 8 q + 4 (l / 32) .. + 3 (elements 4 q .. 4 q + 3)
+                    const int n = wc * WN + 32 * j + 8 * q + 4 * (lane >> 5);
+                    const float4 bias = *reinterpret_cast<const float4 *>(a.bl[l] + n);
 #pragma unroll
-                    for (int e = 0; e < 16; ++e)
-                        act[wr * WMr + 32 * i + frag_row(e, lane)][n] = (bf16)silu_f(acc[i][j][e] + bias);
-            }
+                    for (int i = 0; i < FM; ++i) {
+                        bf16x4 h;
+                        h[0] = (bf16)silu_f(acc[i][j][4 * q + 0] + bias.x);
+                        h[1] = (bf16)silu_f(acc[i][j][4 * q + 1] + bias.y);
+                        h[2] = (bf16)silu_f(acc[i][j][4 * q + 2] + bias.z);
+                        h[3] = (bf16)silu_f(acc[i][j][4 * q + 3] + bias.w);
+                        *reinterpret_cast<bf16x4 *>(&act[wr * WMr + 32 * i + r][n]) = h;
+                    }
+                }
         }
         __syncthreads();
     }
@@ -424,7 +452,11 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
     const int row = tid >> 1, k = tid & 1;
     const int64_t b = r0 + row;
     float yk = 0.0f;
-    for (int f = 0; f < W; ++f) yk = fmaf(a.Wo[k * W + f], (float)act[row][f], yk);
+    for (int f = 0; f < W; f += 8) {  // 16-byte LDS reads, the FMAs still in feature order
+        const bf16x8 h = *reinterpret_cast<const bf16x8 *>(&act[row][f]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) yk = fmaf(a.Wo[k * W + f + e], (float)h[e], yk);
+    }
     yk += a.bo[k];
     if (b < a.n) a.y[2 * b + k] = yk;
 }
@@ -586,13 +618,19 @@ __global__ void __launch_bounds__(256) adam_kernel(int64_t P, float *__restrict_
 
 // bf16 copies of one weight matrix [O][I]: row-major and transposed.
 __global__ void __launch_bounds__(256) cast_weight_kernel(const float *__restrict__ Wf, int O, int I,
-                                                          bf16 *__restrict__ Wb, bf16 *__restrict__ WTb) {
+                                                          bf16 *__restrict__ Wb, bf16 *__restrict__ WTb,
+                                                          bf16 *__restrict__ Wf32) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= (int64_t)O * I) return;
     const int o = (int)(k / I), i = (int)(k - (int64_t)o * I);
     const bf16 v = (bf16)Wf[k];
     Wb[k] = v;
     WTb[(int64_t)i * O + o] = v;
+    // fragment order for the fused inference kernel: the B operand of one 32x32x16 MFMA
+    // (32 output columns x 16 inputs) as 64 lanes x 8 contiguous values, lane = o % 32 +
+    // 32 ((i % 16) / 8), blocks ordered by input slice within each 32-column group
+    const int c = o >> 5, t = i >> 4, lane = (o & 31) + 32 * ((i & 15) >> 3);
+    Wf32[(((int64_t)c * (I >> 4) + t) * 64 + lane) * 8 + (i & 7)] = v;
 }
 
 // Carrier: the phase of the tilted piston's plane wave refracted at the plane z = depth.
@@ -680,6 +718,7 @@ struct rsi_mlp {
     int64_t step = 0;
     rsi::DeviceBuffer Bff, params, grads, adam_m, adam_v;
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> Wb, WTb;  // bf16 weights and transposes
+    std::vector<std::unique_ptr<rsi::DeviceBuffer>> Wfr;      // bf16 weights in MFMA fragment order
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> H, Z;    // activations [L+1], pre-acts [L]
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> HT;      // transposed layer inputs [L]
     rsi::DeviceBuffer dZ[2], dZT[2], dwpart, headpart, dyl, lossbuf;
@@ -722,7 +761,7 @@ static rsi_status refresh_bf16(rsi_mlp *net, hipStream_t s) {
         const int64_t cnt = (int64_t)O * I;
         hipLaunchKernelGGL(cast_weight_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
                            net->params.as<float>() + net->offW[l], O, I, net->Wb[l]->as<bf16>(),
-                           net->WTb[l]->as<bf16>());
+                           net->WTb[l]->as<bf16>(), net->Wfr[l]->as<bf16>());
         RSI_HIP(hipGetLastError());
     }
     return RSI_OK;
@@ -898,8 +937,10 @@ rsi_status rsi_mlp_create(rsi_mlp **out, int n_ff, int width, int depth, const f
     for (int l = 0; l < depth; ++l) {
         net->Wb.emplace_back(new DeviceBuffer);
         net->WTb.emplace_back(new DeviceBuffer);
+        net->Wfr.emplace_back(new DeviceBuffer);
         RSI_TRY(net->Wb.back()->alloc(sizeof(bf16) * width * net->in_dim[l]));
         RSI_TRY(net->WTb.back()->alloc(sizeof(bf16) * width * net->in_dim[l]));
+        RSI_TRY(net->Wfr.back()->alloc(sizeof(bf16) * width * net->in_dim[l]));
         net->Z.emplace_back(new DeviceBuffer);
         RSI_TRY(net->Z.back()->alloc(sizeof(float) * Mp * width));
     }
@@ -982,7 +1023,7 @@ rsi_status rsi_mlp_forward(rsi_mlp *net, int64_t n, const float *q, float *y, vo
         a.L = net->L;
         const float *params = net->params.as<float>();
         for (int l = 0; l < net->L; ++l) {
-            a.Wl[l] = net->Wb[l]->as<bf16>();
+            a.Wl[l] = net->Wfr[l]->as<bf16>();
             a.bl[l] = params + net->offb[l];
             a.in_dim[l] = net->in_dim[l];
         }

@@ -327,7 +327,9 @@ struct FusedArgs {
 // kept, measured: 8 waves per workgroup (64 rows each, 4 waves per SIMD) 91-138 us; 256-row
 // tiles 117 us; LDS operand reads half a step ahead of their MFMAs, and a start delay for
 // every other workgroup, no change; two 64-row tiles per workgroup taking turns (one tile's
-// MFMAs interleaved with the other's bias + SiLU, each tile streaming the weights) 88 us.
+// MFMAs interleaved with the other's bias + SiLU, each tile streaming the weights) 88 us;
+// two activation buffers (one barrier per layer) 101 us at 64 rows (LDS then allows two
+// workgroups per CU instead of four; 64-row tiles with one buffer: 84 us).
 // BM rows per workgroup: 128 when the grid still fills the chip, 32 or 64 for calls of a
 // few thousand rows, where one workgroup's latency is the call's time.
 template <int W, int BM>

@@ -31,7 +31,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic FP32 flops per pair (FMA = 2, transcendental = 1); see the design notes
+# algorithmic FP32 flops per pair (FMA = 2, transcendental = 1), a convention fixed before
+# measuring: monopole 25, dipole 33 (the per-step counts are listed with each kernel)
 FLOPS_MONOPOLE = 25
 FLOPS_DIPOLE = 33
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 2.4 GHz x 256 flop/CU/clk)

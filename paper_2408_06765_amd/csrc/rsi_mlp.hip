@@ -584,14 +584,18 @@ __global__ void __launch_bounds__(256) colsum_kernel(const float *__restrict__ i
     if (ry == 0 && c < C) out[c] = (float)(((sh[0][cx] + sh[1][cx]) + sh[2][cx]) + sh[3][cx]);
 }
 
-// Bias gradient: out[o] = sum_b dZ^T[o][b] (rows of the transposed copy the weight
-// gradient already uses), one block per row, FP32 lanes then a fixed-order tree.
-__global__ void __launch_bounds__(256) rowsum_bf16_kernel(const bf16 *__restrict__ X, int64_t cols,
-                                                          float *__restrict__ out) {
+// Bias gradient, first level: part[sg][o] = the sum of dZ^T[o][b] over the batch columns b
+// of segment sg (16-byte chunks (sg * 256 + thread) * 8 + 2048 kRowSumSegs i), FP32 lanes
+// then a fixed-order tree; colsum_kernel adds the segments in order.  W x kRowSumSegs
+// workgroups: one per row left most of the chip idle.
+constexpr int kRowSumSegs = 16;
+__global__ void __launch_bounds__(256) rowsum_part_kernel(const bf16 *__restrict__ X, int64_t cols, int W,
+                                                          float *__restrict__ part) {
     __shared__ float sh[256];
-    const bf16 *x = X + (int64_t)blockIdx.x * cols;
+    const int o = blockIdx.x, sg = blockIdx.y;
+    const bf16 *x = X + (int64_t)o * cols;
     float acc = 0.0f;
-    for (int64_t k = (int64_t)threadIdx.x * 8; k < cols; k += 256 * 8) {
+    for (int64_t k = ((int64_t)sg * 256 + threadIdx.x) * 8; k < cols; k += (int64_t)kRowSumSegs * 256 * 8) {
         const bf16x8 v = *reinterpret_cast<const bf16x8 *>(x + k);
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc += (float)v[u];
@@ -602,7 +606,7 @@ __global__ void __launch_bounds__(256) rowsum_bf16_kernel(const bf16 *__restrict
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) part[(int64_t)sg * W + o] = sh[0];
 }
 
 __global__ void __launch_bounds__(256) adam_kernel(int64_t P, float *__restrict__ p,
@@ -724,7 +728,7 @@ struct rsi_mlp {
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> Wfr;      // bf16 weights in MFMA fragment order
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> H, Z;    // activations [L+1], pre-acts [L]
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> HT;      // transposed layer inputs [L]
-    rsi::DeviceBuffer dZ[2], dZT[2], dwpart, headpart, dyl, lossbuf;
+    rsi::DeviceBuffer dZ[2], dZT[2], dwpart, headpart, bpart, dyl, lossbuf;
     int dw_splits = 1;
 };
 
@@ -847,9 +851,12 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
         hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C + 63) / 64)), dim3(256), 0, s,
                            net->dwpart.as<float>(), (int64_t)splits, C, C, grad + net->offW[l]);
         RSI_HIP(hipGetLastError());
-        // bias gradient: row sums of dZ^T
-        hipLaunchKernelGGL(rowsum_bf16_kernel, dim3((unsigned)W), dim3(256), 0, s, net->dZT[cur].as<bf16>(), Mp,
-                           grad + net->offb[l]);
+        // bias gradient: row sums of dZ^T, in kRowSumSegs segments added in order
+        hipLaunchKernelGGL(rowsum_part_kernel, dim3((unsigned)W, (unsigned)kRowSumSegs), dim3(256), 0, s,
+                           net->dZT[cur].as<bf16>(), Mp, W, net->bpart.as<float>());
+        RSI_HIP(hipGetLastError());
+        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((W + 63) / 64)), dim3(256), 0, s, net->bpart.as<float>(),
+                           (int64_t)kRowSumSegs, (int64_t)W, (int64_t)W, grad + net->offb[l]);
         RSI_HIP(hipGetLastError());
         if (l == 0) break;
         GemmArgs d{};
@@ -973,6 +980,7 @@ rsi_status rsi_mlp_create(rsi_mlp **out, int n_ff, int width, int depth, const f
     const size_t dw_elems = (size_t)splits * width * maxdim;
     RSI_TRY(net->dwpart.alloc(sizeof(float) * dw_elems));
     RSI_TRY(net->headpart.alloc(sizeof(float) * (size_t)((Mp + kHeadRows - 1) / kHeadRows) * (2 * width + 3)));
+    RSI_TRY(net->bpart.alloc(sizeof(float) * kRowSumSegs * (size_t)width));
     RSI_TRY(net->dyl.alloc(sizeof(float) * 3 * (size_t)Mp));
     RSI_TRY(net->lossbuf.alloc(sizeof(float) * 4));
     RSI_TRY(refresh_bf16(net.get(), nullptr));

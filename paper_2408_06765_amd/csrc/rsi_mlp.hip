@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <memory>
 #include <vector>
 
@@ -316,20 +317,25 @@ struct FusedArgs {
 };
 
 // Two workgroups per CU (the register budget that leaves: about 200 VGPRs at width 256, no
-// spill): one workgroup's MFMAs then cover the other's weight-load waits and SiLU epilogue,
-// which a single wave per SIMD leaves exposed (122 against 81 us for 65536 rows of a 5 x 256
-// net).  Measured on the 7 x 256 net at 65536 rows: 103 us with row-major weights and
-// one-element activation stores, 91 us with the weights in fragment order, 84-86 us with
-// the transposed output as well.  Timing copies with one part removed: features 8 us,
-// bias + SiLU 10, head 5, weight loads 5; with neither weight loads nor LDS operand reads
-// the kernel still takes 82 us, against 27 us of MFMA issue: the phases of each layer
-// (MFMAs, barrier, SiLU and stores, barrier) run in sequence inside every workgroup.  Not
-// kept, measured: 8 waves per workgroup (64 rows each, 4 waves per SIMD) 91-138 us; 256-row
-// tiles 117 us; LDS operand reads half a step ahead of their MFMAs, and a start delay for
-// every other workgroup, no change; two 64-row tiles per workgroup taking turns (one tile's
-// MFMAs interleaved with the other's bias + SiLU, each tile streaming the weights) 88 us;
-// two activation buffers (one barrier per layer) 101 us at 64 rows (LDS then allows two
-// workgroups per CU instead of four; 64-row tiles with one buffer: 84 us).
+// spill); a single wave per SIMD left every load wait exposed (122 against 81 us for 65536
+// rows of a 5 x 256 net).  On gfx950 the VALU work of one wave does not hide behind the
+// MFMAs of the other wave on its SIMD: a micro-benchmark of this MFMA pattern runs 2.0
+// PFLOP/s without an epilogue and 1.43 with a SiLU after every layer, also when the two waves
+// are in opposite phases or keep their accumulators in AGPRs.  So every instruction besides
+// the MFMAs costs time, and the kernel is written to issue few: the small operands sit in
+// LDS, the first K step of a layer adds into the constant 0 instead of cleared registers.
+// Measured on the 7 x 256 net at 65536 rows: 103 us with row-major weights and one-element
+// activation stores, 91 us with the weights in fragment order, 84-86 us with the transposed
+// output as well, 74-79 us with the LDS operands and the constant-0 first step.  Timing
+// copies with one part removed (79.6 us with all parts): LDS operand reads 3.3 us, weight
+// loads 4.3 (both 11.2), barriers 1.3, features 3.6, head 1.2, SiLU 9.7.  Not kept,
+// measured: 8 waves per workgroup (64 rows each, 4 waves per SIMD) 91-138 us; 256-row tiles
+// 117 us; LDS operand reads half a step ahead of their MFMAs, a start delay for every other
+// workgroup, and a warm-up load of all weights into L2, no change; two 64-row tiles per
+// workgroup taking turns (one tile's MFMAs interleaved with the other's bias + SiLU, each
+// tile streaming the weights) 88 us; two activation buffers (one barrier per layer) 101 us
+// at 64 rows (LDS then allows two workgroups per CU instead of four; 64-row tiles with one
+// buffer: 84 us).
 // BM rows per workgroup: 128 when the grid still fills the chip, 32 or 64 for calls of a
 // few thousand rows, where one workgroup's latency is the call's time.
 template <int W, int BM>
@@ -344,6 +350,12 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
     static_assert(FN >= 1 && FM >= 1, "fragments of 32 x 32");
     static_assert(BM == 32 || BM == 64 || BM == 128, "32, 64 or 128 rows");
     __shared__ __attribute__((aligned(16))) bf16 act[BM][LDA];
+    // small operands every wave reads at the same addresses, staged once so that no
+    // per-iteration global load stalls a phase: the Fourier matrix in FP64 while the features
+    // are computed, then the head's weights and biases; and the current layer's biases
+    constexpr int NSIDE = W / 2 * 5, NBF = (NSIDE + 255) / 256, NWO = (2 * W + 2 + 255) / 256;
+    __shared__ __attribute__((aligned(16))) double side[NSIDE];
+    __shared__ __attribute__((aligned(16))) float bias_s[W];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t r0 = (int64_t)blockIdx.x * BM;
     const bool mma = wave < CG * RG;
@@ -366,23 +378,40 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
             for (int j = 0; j < FN; ++j)
                 b[s][j] = *reinterpret_cast<const bf16x8 *>(p + (int64_t)32 * j * ld + 512 * s);
     };
+    // Every global load below is unconditional (indices clamped into their arrays), so
+    // that the compiler can count the loads still in flight instead of draining them all.
+    // (Rows past n compute u = +0, as they do in features_kernel; their outputs are
+    // dropped.)  m <= W / 2: the features fit the width.
+    const int row = tid & (BM - 1), part = tid / BM;
+    const int64_t b = r0 + row;
+    const bool live = b < a.n;
+    float bff[NBF], wo[NWO], qv[5];
+#pragma unroll
+    for (int t = 0; t < NBF; ++t) bff[t] = a.Bff[min(tid + 256 * t, 5 * a.m - 1)];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) qv[c] = a.q[(live ? b : a.n - 1) * 5 + c];
+#pragma unroll
+    for (int t = 0; t < NWO; ++t) {
+        const int i = min(tid + 256 * t, 2 * W + 1);
+        wo[t] = i < 2 * W ? a.Wo[i] : a.bo[i - 2 * W];
+    }
+    float bcur = a.bl[0][tid & (W - 1)];  // biases of the layer about to run
     if (mma) load(b0, wrow(0), a.in_dim[0]);
+#pragma unroll
+    for (int t = 0; t < NBF; ++t)
+        if (tid + 256 * t < NSIDE) side[tid + 256 * t] = (double)bff[t];
+    __syncthreads();
     {
         // features as in features_kernel: TPR threads per row, each a share of the frequencies
-        const int row = tid & (BM - 1), part = tid / BM;
-        const int64_t b = r0 + row;
-        const bool live = b < a.n;
-        double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        if (live)
+        double v[5];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) v[c] = 2.0 * ((double)a.q[b * 5 + c] - a.box.lo[c]) * a.box.inv[c] - 1.0;
+        for (int c = 0; c < 5; ++c) v[c] = live ? 2.0 * ((double)qv[c] - a.box.lo[c]) * a.box.inv[c] - 1.0 : 0.0;
         const int mh = a.m / TPR;  // m is a multiple of 32
 #pragma unroll 4
         for (int j = part * mh; j < (part + 1) * mh; ++j) {
             double u = 0.0;
-            if (live)
 #pragma unroll
-                for (int c = 0; c < 5; ++c) u = fma((double)a.Bff[j * 5 + c], v[c], u);
+            for (int c = 0; c < 5; ++c) u = fma(side[j * 5 + c], v[c], u);
             const float ph = (float)(u - floor(u));
             act[row][j] = (bf16)__builtin_amdgcn_sinf(ph);
             act[row][a.m + j] = (bf16)__builtin_amdgcn_cosf(ph);
@@ -391,19 +420,27 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
     __syncthreads();
     for (int l = 0; l < a.L; ++l) {
         const int K = a.in_dim[l];
-        f32x16 acc[FM][FN];
+        // this layer's biases, loaded a layer ahead (the previous layer's readers are past
+        // the barrier that ended it), and the next layer's load; the wait for them here is
+        // the wait for this layer's first weights.  Before the first layer the head's weights
+        // and biases take the place of the Fourier matrix, which the features are done with.
+        if (tid < W) bias_s[tid] = bcur;
+        bcur = a.bl[min(l + 1, a.L - 1)][tid & (W - 1)];
+        if (l == 0) {
+            float *wos = reinterpret_cast<float *>(side);  // Wo [2][W], then bo [2]
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-#pragma unroll
-                for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+            for (int t = 0; t < NWO; ++t)
+                if (tid + 256 * t < 2 * W + 2) wos[tid + 256 * t] = wo[t];
+        }
+        f32x16 acc[FM][FN];  // set by the first K step (waves without MFMA work never read it)
         if (mma) {
             const bf16 *Wl = wrow(l);
             const bool more = l + 1 < a.L;
             const bf16 *Wn = more ? wrow(l + 1) : Wl + 32 * (K - 32);
             const int64_t Kn = more ? a.in_dim[l + 1] : K;
-            auto step = [&](const bf16x8 (&b)[2][FN], int k) {
+            // first: the layer's first K step, whose MFMAs take the constant 0 as their
+            // accumulator input (no register clearing; the same sums)
+            auto step = [&](const bf16x8 (&b)[2][FN], int k, auto first) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -411,19 +448,25 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
                         const bf16x8 af =
                             *reinterpret_cast<const bf16x8 *>(&act[wr * WMr + 32 * i + r][k + 16 * s + kq]);
 #pragma unroll
-                        for (int j = 0; j < FN; ++j) acc[i][j] = mfma32(b[s][j], af, acc[i][j]);
+                        for (int j = 0; j < FN; ++j) {
+                            if constexpr (decltype(first)::value)
+                                acc[i][j] = mfma32(b[s][j], af, s == 0 ? f32x16{} : acc[i][j]);
+                            else
+                                acc[i][j] = mfma32(b[s][j], af, acc[i][j]);
+                        }
                     }
             };
             // (the scheduling barriers keep the compiler from sinking the loads below the MFMAs)
             for (int k0 = 0; k0 < K; k0 += 64) {  // K is a multiple of 64
                 load(b1, Wl + 32 * (k0 + 32), K);
                 __builtin_amdgcn_sched_barrier(0);
-                step(b0, k0);
+                if (k0 == 0) step(b0, k0, std::true_type{});
+                else step(b0, k0, std::false_type{});
                 __builtin_amdgcn_sched_barrier(0);
                 const bool last = k0 + 64 >= K;
                 load(b0, last ? Wn : Wl + 32 * (k0 + 64), last ? Kn : K);
                 __builtin_amdgcn_sched_barrier(0);
-                step(b1, k0 + 32);
+                step(b1, k0 + 32, std::false_type{});
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -436,7 +479,7 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
                     // the transposed fragment: lane l holds row l % 32 and, for q, the four
                     // consecutive columns 8 q + 4 (l / 32) .. + 3 (elements 4 q .. 4 q + 3)
                     const int n = wc * WN + 32 * j + 8 * q + 4 * (lane >> 5);
-                    const float4 bias = *reinterpret_cast<const float4 *>(a.bl[l] + n);
+                    const float4 bias = *reinterpret_cast<const float4 *>(&bias_s[n]);
 #pragma unroll
                     for (int i = 0; i < FM; ++i) {
                         bf16x4 h;
@@ -452,16 +495,19 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
     }
     // head as in head_kernel: one (row, output) per thread, FMAs in feature order
     if (tid >= 2 * BM) return;
-    const int row = tid >> 1, k = tid & 1;
-    const int64_t b = r0 + row;
+    const int hrow = tid >> 1, k = tid & 1;
+    const float *wos = reinterpret_cast<const float *>(side);  // Wo [2][W], then bo [2]
     float yk = 0.0f;
     for (int f = 0; f < W; f += 8) {  // 16-byte LDS reads, the FMAs still in feature order
-        const bf16x8 h = *reinterpret_cast<const bf16x8 *>(&act[row][f]);
+        const bf16x8 h = *reinterpret_cast<const bf16x8 *>(&act[hrow][f]);
+        const float4 w0 = *reinterpret_cast<const float4 *>(&wos[k * W + f]);
+        const float4 w1 = *reinterpret_cast<const float4 *>(&wos[k * W + f + 4]);
+        const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
-        for (int e = 0; e < 8; ++e) yk = fmaf(a.Wo[k * W + f + e], (float)h[e], yk);
+        for (int e = 0; e < 8; ++e) yk = fmaf(w[e], (float)h[e], yk);
     }
-    yk += a.bo[k];
-    if (b < a.n) a.y[2 * b + k] = yk;
+    yk += wos[2 * W + k];
+    if (r0 + hrow < a.n) a.y[2 * (r0 + hrow) + k] = yk;
 }
 
 // Output layer (FP32), one thread per row: y = Wo h + bo.  Training (t != NULL): the

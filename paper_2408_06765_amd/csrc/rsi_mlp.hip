@@ -623,8 +623,17 @@ __global__ void __launch_bounds__(256) colsum_kernel(const float *__restrict__ i
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
     const int64_t c = (int64_t)blockIdx.x * 64 + cx;
     double acc = 0.0;
-    if (c < C)
-        for (int64_t r = ry; r < R; r += 4) acc += (double)in[r * ld + c];
+    if (c < C) {
+        int64_t r = ry;
+        for (; r + 60 < R; r += 64) {  // 16 rows of the group loaded ahead of their additions
+            float x[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) x[u] = in[(r + 4 * u) * ld + c];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += (double)x[u];
+        }
+        for (; r < R; r += 4) acc += (double)in[r * ld + c];
+    }
     sh[ry][cx] = acc;
     __syncthreads();
     if (ry == 0 && c < C) out[c] = (float)(((sh[0][cx] + sh[1][cx]) + sh[2][cx]) + sh[3][cx]);
@@ -684,6 +693,90 @@ __global__ void __launch_bounds__(256) cast_weight_kernel(const float *__restric
     // 32 ((i % 16) / 8), blocks ordered by input slice within each 32-column group
     const int c = o >> 5, t = i >> 4, lane = (o & 31) + 32 * ((i & 15) >> 3);
     Wf32[(((int64_t)c * (I >> 4) + t) * 64 + lane) * 8 + (i & 7)] = v;
+}
+
+// One training step's Adam update fused with the reductions that finish its gradients:
+// parameter i reads the partial sums the backward kernels left for it (weight-gradient
+// splits, bias-gradient segments, head chunks) and adds them in colsum_kernel's order, so
+// the update equals that of separate colsum, adam and weight-cast launches bit for bit; a
+// weight's new value then goes to its three bf16 copies as cast_weight_kernel writes them.
+struct AdamArgs {
+    int64_t P;
+    float *p, *m, *v;
+    float lr, c1, c2;
+    int L, W;
+    int64_t offW[kMaxLayers], offb[kMaxLayers];
+    int in_dim[kMaxLayers];
+    const float *dw[kMaxLayers];  // [splits][W][in_dim[l]] weight-gradient partials
+    const float *bp[kMaxLayers];  // [kRowSumSegs][W] bias-gradient segments
+    bf16 *Wb[kMaxLayers], *WTb[kMaxLayers], *Wfr[kMaxLayers];
+    int64_t splits;
+    const float *head;  // [chunks][2W + 3]: dWo, dbo, loss
+    int64_t chunks, offWo;
+};
+
+// colsum_kernel's sum of one column: rows r = g mod 4 in order, in FP64, then the four
+// groups.  Rows are loaded 16 at a time ahead of their additions (one thread walks the whole
+// column, so the loads in flight are what hides the memory latency).
+__device__ inline float colsum_at(const float *__restrict__ in, int64_t R, int64_t ld, int64_t c) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t r = 0;
+    for (; r + 16 <= R; r += 16) {
+        float x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x[u] = in[(r + u) * ld + c];
+#pragma unroll
+        for (int u = 0; u < 16; u += 4) {
+            a0 += (double)x[u];
+            a1 += (double)x[u + 1];
+            a2 += (double)x[u + 2];
+            a3 += (double)x[u + 3];
+        }
+    }
+    for (; r < R; ++r) {
+        const double x = (double)in[r * ld + c];
+        const int gq = (int)(r & 3);
+        if (gq == 0) a0 += x;
+        else if (gq == 1) a1 += x;
+        else if (gq == 2) a2 += x;
+        else a3 += x;
+    }
+    return (float)(((a0 + a1) + a2) + a3);
+}
+
+__global__ void __launch_bounds__(256) adam_fused_kernel(AdamArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.P) return;
+    float g;
+    int lw = -1;  // the layer whose weight i is, or -1
+    int64_t e = 0;
+    if (i >= a.offWo) {
+        g = colsum_at(a.head, a.chunks, 2 * (int64_t)a.W + 3, i - a.offWo);
+    } else {
+        int l = 0;
+        while (l + 1 < a.L && i >= a.offW[l + 1]) ++l;
+        if (i < a.offb[l]) {
+            lw = l;
+            e = i - a.offW[l];
+            g = colsum_at(a.dw[l], a.splits, (int64_t)a.W * a.in_dim[l], e);
+        } else {
+            g = colsum_at(a.bp[l], kRowSumSegs, a.W, i - a.offb[l]);
+        }
+    }
+    const float mi = 0.9f * a.m[i] + 0.1f * g;
+    const float vi = 0.999f * a.v[i] + 0.001f * g * g;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float pn = a.p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + 1e-8f);
+    a.p[i] = pn;
+    if (lw >= 0) {
+        const int I = a.in_dim[lw], o = (int)(e / I), ii = (int)(e - (int64_t)o * I);
+        const bf16 bv = (bf16)pn;
+        a.Wb[lw][e] = bv;
+        a.WTb[lw][(int64_t)ii * a.W + o] = bv;
+        const int c = o >> 5, t = ii >> 4, lane = (o & 31) + 32 * ((ii & 15) >> 3);
+        a.Wfr[lw][(((int64_t)c * (I >> 4) + t) * 64 + lane) * 8 + (ii & 7)] = bv;
+    }
 }
 
 // Carrier: the phase of the tilted piston's plane wave refracted at the plane z = depth.
@@ -775,6 +868,7 @@ struct rsi_mlp {
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> H, Z;    // activations [L+1], pre-acts [L]
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> HT;      // transposed layer inputs [L]
     rsi::DeviceBuffer dZ[2], dZT[2], dwpart, headpart, bpart, dyl, lossbuf;
+    std::vector<int64_t> dwoff;  // per layer, into dwpart (each layer keeps its partials)
     int dw_splits = 1;
 };
 
@@ -851,8 +945,11 @@ static rsi_status forward_hidden(rsi_mlp *net, int64_t n, const float *q, bool t
     return RSI_OK;
 }
 
+// The gradients into grad, or (grad == NULL) only their partial sums -- per-layer weight
+// splits, bias segments, head chunks -- for the fused Adam step to add; the loss is summed
+// either way.  Returns the number of weight-gradient splits used.
 static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad, float *loss,
-                           hipStream_t s) {
+                           hipStream_t s, int *splits_used = nullptr) {
     const int64_t Mp = pad64(n);
     const int W = net->W;
     const float *params = net->params.as<float>();
@@ -868,9 +965,11 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
                            net->H[net->L]->as<bf16>(), net->dyl.as<float>(), net->headpart.as<float>());
         RSI_HIP(hipGetLastError());
         float *lossdst = loss ? loss : net->lossbuf.as<float>();
-        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C - 1 + 63) / 64)), dim3(256), 0, s,
-                           net->headpart.as<float>(), chunks, C - 1, C, grad + net->offWo);
-        RSI_HIP(hipGetLastError());
+        if (grad) {
+            hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C - 1 + 63) / 64)), dim3(256), 0, s,
+                               net->headpart.as<float>(), chunks, C - 1, C, grad + net->offWo);
+            RSI_HIP(hipGetLastError());
+        }
         hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, net->headpart.as<float>() + (C - 1), chunks,
                            (int64_t)1, C, lossdst);
         RSI_HIP(hipGetLastError());
@@ -882,6 +981,9 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
         // written by the epilogues that produced dZ_l and H_l
         int splits = net->dw_splits;
         while (splits > 1 && (Mp % ((int64_t)splits * kTileK) != 0)) splits >>= 1;
+        if (splits_used) *splits_used = splits;
+        float *dwp = net->dwpart.as<float>() + net->dwoff[l];
+        float *bpp = net->bpart.as<float>() + (int64_t)l * kRowSumSegs * W;
         GemmArgs g{};
         g.A = net->dZT[cur].as<bf16>();
         g.lda = Mp;
@@ -891,19 +993,23 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
         g.N = I;
         g.K = Mp;
         g.k_per_split = Mp / splits;
-        g.P = net->dwpart.as<float>();
+        g.P = dwp;
         RSI_TRY(gemm(EPI_DW, g, splits, s));
         const int64_t C = (int64_t)W * I;
-        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C + 63) / 64)), dim3(256), 0, s,
-                           net->dwpart.as<float>(), (int64_t)splits, C, C, grad + net->offW[l]);
-        RSI_HIP(hipGetLastError());
+        if (grad) {
+            hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C + 63) / 64)), dim3(256), 0, s, dwp,
+                               (int64_t)splits, C, C, grad + net->offW[l]);
+            RSI_HIP(hipGetLastError());
+        }
         // bias gradient: row sums of dZ^T, in kRowSumSegs segments added in order
         hipLaunchKernelGGL(rowsum_part_kernel, dim3((unsigned)W, (unsigned)kRowSumSegs), dim3(256), 0, s,
-                           net->dZT[cur].as<bf16>(), Mp, W, net->bpart.as<float>());
+                           net->dZT[cur].as<bf16>(), Mp, W, bpp);
         RSI_HIP(hipGetLastError());
-        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((W + 63) / 64)), dim3(256), 0, s, net->bpart.as<float>(),
-                           (int64_t)kRowSumSegs, (int64_t)W, (int64_t)W, grad + net->offb[l]);
-        RSI_HIP(hipGetLastError());
+        if (grad) {
+            hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((W + 63) / 64)), dim3(256), 0, s, bpp,
+                               (int64_t)kRowSumSegs, (int64_t)W, (int64_t)W, grad + net->offb[l]);
+            RSI_HIP(hipGetLastError());
+        }
         if (l == 0) break;
         GemmArgs d{};
         d.A = net->dZ[cur].as<bf16>();
@@ -1023,10 +1129,15 @@ rsi_status rsi_mlp_create(rsi_mlp **out, int n_ff, int width, int depth, const f
     int splits = 1;
     while (splits < max_splits && Mp / (splits * 2) >= 256) splits *= 2;
     net->dw_splits = splits;
-    const size_t dw_elems = (size_t)splits * width * maxdim;
+    // every layer's partials stay until the fused Adam step adds them
+    size_t dw_elems = 0;
+    for (int l = 0; l < depth; ++l) {
+        net->dwoff.push_back((int64_t)dw_elems);
+        dw_elems += (size_t)splits * width * net->in_dim[l];
+    }
     RSI_TRY(net->dwpart.alloc(sizeof(float) * dw_elems));
     RSI_TRY(net->headpart.alloc(sizeof(float) * (size_t)((Mp + kHeadRows - 1) / kHeadRows) * (2 * width + 3)));
-    RSI_TRY(net->bpart.alloc(sizeof(float) * kRowSumSegs * (size_t)width));
+    RSI_TRY(net->bpart.alloc(sizeof(float) * kRowSumSegs * (size_t)width * depth));
     RSI_TRY(net->dyl.alloc(sizeof(float) * 3 * (size_t)Mp));
     RSI_TRY(net->lossbuf.alloc(sizeof(float) * 4));
     RSI_TRY(refresh_bf16(net.get(), nullptr));
@@ -1131,15 +1242,50 @@ rsi_status rsi_mlp_train_step(rsi_mlp *net, int64_t n, const float *q, const flo
     if (!(lr > 0.0f)) return RSI_ERR_ARG;
     hipStream_t s = as_stream(stream);
     RSI_TRY(forward_hidden(net, n, q, true, s));
-    RSI_TRY(backward(net, n, t, net->grads.as<float>(), loss, s));
+    // RSI_MLP_ADAM_FUSED=0: the gradients summed by colsum_kernel, then adam_kernel and the
+    // weight casts as separate launches (the same arithmetic in the same order)
+    const char *fe = std::getenv("RSI_MLP_ADAM_FUSED");
+    if (fe && fe[0] == '0' && fe[1] == 0) {
+        RSI_TRY(backward(net, n, t, net->grads.as<float>(), loss, s));
+        net->step += 1;
+        const float c1 = (float)(1.0 - std::pow(0.9, (double)net->step));
+        const float c2 = (float)(1.0 - std::pow(0.999, (double)net->step));
+        hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((net->P + 255) / 256)), dim3(256), 0, s, net->P,
+                           net->params.as<float>(), net->grads.as<float>(), net->adam_m.as<float>(),
+                           net->adam_v.as<float>(), lr, c1, c2);
+        RSI_HIP(hipGetLastError());
+        return refresh_bf16(net, s);
+    }
+    int splits = 1;
+    RSI_TRY(backward(net, n, t, nullptr, loss, s, &splits));
     net->step += 1;
-    const float c1 = (float)(1.0 - std::pow(0.9, (double)net->step));
-    const float c2 = (float)(1.0 - std::pow(0.999, (double)net->step));
-    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((net->P + 255) / 256)), dim3(256), 0, s, net->P,
-                       net->params.as<float>(), net->grads.as<float>(), net->adam_m.as<float>(),
-                       net->adam_v.as<float>(), lr, c1, c2);
+    AdamArgs a{};
+    a.P = net->P;
+    a.p = net->params.as<float>();
+    a.m = net->adam_m.as<float>();
+    a.v = net->adam_v.as<float>();
+    a.lr = lr;
+    a.c1 = (float)(1.0 - std::pow(0.9, (double)net->step));
+    a.c2 = (float)(1.0 - std::pow(0.999, (double)net->step));
+    a.L = net->L;
+    a.W = net->W;
+    for (int l = 0; l < net->L; ++l) {
+        a.offW[l] = net->offW[l];
+        a.offb[l] = net->offb[l];
+        a.in_dim[l] = net->in_dim[l];
+        a.dw[l] = net->dwpart.as<float>() + net->dwoff[l];
+        a.bp[l] = net->bpart.as<float>() + (int64_t)l * kRowSumSegs * net->W;
+        a.Wb[l] = net->Wb[l]->as<bf16>();
+        a.WTb[l] = net->WTb[l]->as<bf16>();
+        a.Wfr[l] = net->Wfr[l]->as<bf16>();
+    }
+    a.splits = splits;
+    a.head = net->headpart.as<float>();
+    a.chunks = (pad64(n) + kHeadRows - 1) / kHeadRows;
+    a.offWo = net->offWo;
+    hipLaunchKernelGGL(adam_fused_kernel, dim3((unsigned)((net->P + 255) / 256)), dim3(256), 0, s, a);
     RSI_HIP(hipGetLastError());
-    return refresh_bf16(net, s);
+    return RSI_OK;
 }
 
 static const uint32_t kMagic = 0x524d4c50u;  // "RMLP"

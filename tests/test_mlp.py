@@ -320,8 +320,9 @@ def test_mlp_train_step_is_adam(gpu):
 @pytest.mark.gpu
 def test_mlp_adam_steps_match_reference(gpu):
     """Four Adam steps on the GPU against the reference's Adam fed the same gradients (the
-    GPU's own, read before each step with rsi_mlp_gradients, which runs the same kernels
-    as the training step): the bias correction and both moment recursions past step 1."""
+    GPU's own, read before each step with rsi_mlp_gradients, whose sums the training step's
+    fused update reproduces bit for bit): the bias correction and both moment recursions
+    past step 1."""
     net, o, q, t, v, tn, p0 = _setup(gpu, 32, 64, 3, 500, 5)
     p, m, vv = p0.astype(np.float64), 0.0, 0.0
     for k in range(1, 5):
@@ -362,6 +363,32 @@ def test_mlp_one_layer_exact_operands(gpu, fused, monkeypatch):
     for name, off, size, ref in blocks:
         assert rel(g[off:off + size], np.ravel(ref)) <= 1e-5, (name, rel(g[off:off + size], np.ravel(ref)))
     net.destroy()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n_ff,width,depth,n", [(32, 64, 3, 500), (128, 256, 3, 1000)])
+def test_mlp_fused_adam_equals_separate_launches(gpu, n_ff, width, depth, n, monkeypatch):
+    """The training step's Adam update, fused with the reductions that finish the gradients
+    and with the bf16 weight casts, equals the separate launches (column sums, Adam, casts;
+    RSI_MLP_ADAM_FUSED=0) bit for bit: the parameters after three steps, and what reads the
+    three bf16 weight copies -- the fused and the layer-by-layer forward, and the gradients."""
+    a, _, q, t, _, _, _ = _setup(gpu, n_ff, width, depth, n, 7)
+    b, _, _, _, _, _, _ = _setup(gpu, n_ff, width, depth, n, 7)
+    for _ in range(3):
+        monkeypatch.setenv("RSI_MLP_ADAM_FUSED", "1")
+        a.train_step(q, t, 1e-3)
+        monkeypatch.setenv("RSI_MLP_ADAM_FUSED", "0")
+        b.train_step(q, t, 1e-3)
+    pa, pb = a.get_params(), b.get_params()
+    assert np.array_equal(pa.view(np.uint32), pb.view(np.uint32))
+    for mode in ("1", "0"):
+        monkeypatch.setenv("RSI_MLP_FUSED", mode)
+        ya, yb = a.forward(q).cpu().numpy(), b.forward(q).cpu().numpy()
+        assert np.array_equal(ya.view(np.uint32), yb.view(np.uint32)), mode
+    ga, gb = a.gradients(q, t)[0].cpu().numpy(), b.gradients(q, t)[0].cpu().numpy()
+    assert np.array_equal(ga.view(np.uint32), gb.view(np.uint32))
+    a.destroy()
+    b.destroy()
 
 
 @pytest.mark.gpu

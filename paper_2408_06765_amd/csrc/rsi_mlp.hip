@@ -262,6 +262,11 @@ __global__ void __launch_bounds__(256) features_kernel(int64_t n, int64_t Mp, in
     const int64_t b = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int j0 = (blockIdx.y * 4 + threadIdx.y) * 8;
     if (b >= Mp || j0 >= m) return;
+    // the 8 features' 40 matrix entries loaded before any FMA (rows past n have v = 0, so
+    // their u is +0 as when the sum is skipped)
+    float bf[40];
+#pragma unroll
+    for (int k = 0; k < 40; ++k) bf[k] = Bff[j0 * 5 + k];
     // v and u = B v, and u's reduction to one revolution, in FP64: the bf16 features then
     // round the same values the FP64 reference rounds (|u| reaches tens of revolutions)
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -273,9 +278,8 @@ __global__ void __launch_bounds__(256) features_kernel(int64_t n, int64_t Mp, in
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         double u = 0.0;
-        if (live)
 #pragma unroll
-            for (int c = 0; c < 5; ++c) u = fma((double)Bff[(j0 + t) * 5 + c], v[c], u);
+        for (int c = 0; c < 5; ++c) u = fma((double)bf[t * 5 + c], v[c], u);
         const float ph = (float)(u - floor(u));  // sin(2 pi u): revolutions
         hs[t] = (bf16)__builtin_amdgcn_sinf(ph);
         hc[t] = (bf16)__builtin_amdgcn_cosf(ph);
@@ -527,13 +531,18 @@ __global__ void __launch_bounds__(256) head_kernel(int64_t n, int64_t Mp, int W,
     const ConstF Wo = (ConstF)Wo_, bo = (ConstF)bo_;
     const bf16 *h = H + row * W;
     float y0 = 0.0f, y1 = 0.0f;
-    for (int f = 0; f < W; f += 8) {
-        const bf16x8 hv = *reinterpret_cast<const bf16x8 *>(h + f);
+    for (int f0 = 0; f0 < W; f0 += 64) {  // W is a multiple of 64: 8 loads ahead of their FMAs
+        bf16x8 hb[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            y0 = fmaf(Wo[f + u], (float)hv[u], y0);
-            y1 = fmaf(Wo[W + f + u], (float)hv[u], y1);
-        }
+        for (int k = 0; k < 8; ++k) hb[k] = *reinterpret_cast<const bf16x8 *>(h + f0 + 8 * k);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int f = f0 + 8 * k;
+                y0 = fmaf(Wo[f + u], (float)hb[k][u], y0);
+                y1 = fmaf(Wo[W + f + u], (float)hb[k][u], y1);
+            }
     }
     y0 += bo[0];
     y1 += bo[1];
@@ -555,15 +564,22 @@ __global__ void __launch_bounds__(256) head_kernel(int64_t n, int64_t Mp, int W,
     dyl[3 * row + 2] = loss;
     const float *z = Z + row * W;
     bf16 *dz = dZ + row * W;
-    for (int f = 0; f < W; f += 8) {
-        bf16x8 o;
+    for (int f0 = 0; f0 < W; f0 += 32) {  // 32 pre-activations loaded ahead of their use
+        f32x4 zb[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float dh = d0 * Wo[f + u] + d1 * Wo[W + f + u];
-            o[u] = (bf16)(dh * silu_grad_f(z[f + u]));
-            dZT[(int64_t)(f + u) * Mp + row] = o[u];  // transposed copy [W][Mp]
+        for (int k = 0; k < 8; ++k) zb[k] = *reinterpret_cast<const f32x4 *>(z + f0 + 4 * k);
+#pragma unroll
+        for (int k8 = 0; k8 < 4; ++k8) {
+            const int f = f0 + 8 * k8;
+            bf16x8 o;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float dh = d0 * Wo[f + u] + d1 * Wo[W + f + u];
+                o[u] = (bf16)(dh * silu_grad_f(zb[2 * k8 + u / 4][u % 4]));
+                dZT[(int64_t)(f + u) * Mp + row] = o[u];  // transposed copy [W][Mp]
+            }
+            *reinterpret_cast<bf16x8 *>(dz + f) = o;
         }
-        *reinterpret_cast<bf16x8 *>(dz + f) = o;
     }
 }
 
@@ -585,7 +601,23 @@ __global__ void __launch_bounds__(256) head_grad_kernel(int64_t Mp, int W, const
         float a0[8], a1[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) a0[u] = a1[u] = 0.0f;
-        for (int r = ty; r < rows; r += 4) {
+        // rows ty, ty + 4, ... in order, eight rows' loads issued ahead of their FMAs
+        int r = ty;
+        for (; r + 28 < rows; r += 32) {
+            bf16x8 hb[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) hb[k] = *reinterpret_cast<const bf16x8 *>(H + (r0 + r + 4 * k) * W + 8 * fc);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float d0 = sdy[3 * (r + 4 * k)], d1 = sdy[3 * (r + 4 * k) + 1];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    a0[u] = fmaf(d0, (float)hb[k][u], a0[u]);
+                    a1[u] = fmaf(d1, (float)hb[k][u], a1[u]);
+                }
+            }
+        }
+        for (; r < rows; r += 4) {
             const bf16x8 h = *reinterpret_cast<const bf16x8 *>(H + (r0 + r) * W + 8 * fc);
             const float d0 = sdy[3 * r], d1 = sdy[3 * r + 1];
 #pragma unroll

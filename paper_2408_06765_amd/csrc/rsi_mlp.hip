@@ -1,15 +1,16 @@
 // rsi_mlp.hip -- the learned surrogate: Fourier-feature MLP trained and evaluated with
 // bfloat16 MFMA GEMMs (gfx950 v_mfma_f32_32x32x16_bf16, FP32 accumulation).
 //
-// Every GEMM of training is written in one "NT" form, C[M][N] = A[M][K] . B[N][K]^T, with
-// both operands contiguous along the reduction dimension, so that each lane of a wave
-// loads its 8 bfloat16 MFMA operands with one 16-byte load:
+// The forward and input-gradient GEMMs are written in the "NT" form, C[M][N] = A[M][K] .
+// B[N][K]^T, with both operands contiguous along the reduction dimension, so that each lane
+// of a wave reads its 8 bfloat16 MFMA operands with one 16-byte LDS read:
 //   forward   Z_l  = H_{l-1} [B][K]  . W_l   [N][K]^T
 //   input grad dH  = dZ_l    [B][N]  . W_l^T [K][N]^T      (transposed weight copy)
-//   weight grad dW = dZ_l^T  [N][B]  . H^T   [K][B]^T      (transposed activations)
-// The epilogues fuse bias + SiLU (forward) and the SiLU derivative (input gradient) and
-// write the row-major and the transposed bfloat16 copies the next GEMM needs.  Weight
-// gradients are split over the batch and reduced in a fixed order (deterministic).
+// The weight gradient dW = dZ_l^T . H_{l-1} contracts over the batch, along the rows of both
+// row-major tensors; its kernel transposes its operand tiles as it reads them from LDS.  The
+// epilogues fuse bias + SiLU (forward) and the SiLU derivative (input gradient) and write
+// bfloat16 row-major.  Weight gradients are split over the batch and reduced in a fixed
+// order (deterministic).
 //
 // MFMA 32x32x16 bf16 operand layout (lane l, i = 0..7 / v = 0..15; checked on gfx950 with
 // small-integer operands):
@@ -58,7 +59,7 @@ __device__ inline float silu_grad_f(float z) {
     return s * (1.0f + z * (1.0f - s));
 }
 
-enum { EPI_FWD = 0, EPI_FWD_INFER = 1, EPI_DX = 2, EPI_DW = 3 };
+enum { EPI_FWD = 0, EPI_FWD_INFER = 1, EPI_DX = 2 };
 
 struct GemmArgs {
     const bf16 *A;
@@ -71,9 +72,7 @@ struct GemmArgs {
     int64_t ldz;        // row pitch of Z, or 0: Z in the tile-native order (see below)
     bf16 *H;            // EPI_FWD*: activation out; EPI_DX: previous dZ out
     int64_t ldh;
-    bf16 *HT;           // optional transposed copy [N][M]
-    int64_t ldht;
-    float *P;           // EPI_DW: partials [split][M][N]
+    float *P;           // weight gradient (gemm_dw_rowmajor_kernel): partials [split][M][N]
 };
 
 // NT GEMM on one workgroup tile BM x BN: four waves in a 2 x 2 grid, each computing a
@@ -163,19 +162,6 @@ __global__ void __launch_bounds__(256, 3) gemm_nt_kernel(GemmArgs g) {
         __syncthreads();
     }
     const int cn = lane & 31;
-    if constexpr (EPI == EPI_DW) {
-        float *p = g.P + (int64_t)blockIdx.z * g.M * g.N;
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const int64_t n = n0 + wn * WN + 32 * j + cn;
-                const int64_t mb = m0 + wm * WM + 32 * i;
-#pragma unroll
-                for (int v = 0; v < 16; ++v) p[(mb + frag_row(v, lane)) * g.N + n] = acc[i][j][v];
-            }
-        return;
-    }
     // Tile-native order of Z: fragment (i, j) of wave w holds 16 values per lane, stored as
     // four 16-byte chunks at ((tile * 4 + w) * FM * FN + i * FN + j) * 1024 + lane * 16, so
     // the forward GEMM writes and the input-gradient GEMM of the same shape reads it with
@@ -234,16 +220,116 @@ __global__ void __launch_bounds__(256, 3) gemm_nt_kernel(GemmArgs g) {
         *reinterpret_cast<bf16x8 *>(g.H + (m0 + row) * g.ldh + n0 + c8) =
             *reinterpret_cast<const bf16x8 *>(&st[row][c8]);
     }
-    // transposed copy [N][M] in 16-byte chunks of 8 consecutive rows
-    if (g.HT) {
-        for (int c = tid; c < BM * BN / 8; c += 256) {
-            const int col = c / (BM / 8), r8 = (c - col * (BM / 8)) * 8;
-            bf16x8 v;
+}
+
+// Weight gradient from the row-major tensors: P[split][m][n] = sum over the split's rows k
+// of A[k][m] B[k][n] (A = dZ [rows][M], B = H [rows][N]), the contraction running along the
+// rows of both.  Tiles of 32 rows are copied to LDS as they are (16-byte loads and stores),
+// and each MFMA operand -- 8 consecutive k of one m -- is read with two transposing LDS reads
+// (ds_read_b64_tr_b16): within a group of 16 lanes, lane j points at row kb + j / 4, columns
+// c + 4 (j % 4) .. + 3, and lane i receives rows kb .. kb + 3 of column c + i.  The operands,
+// and so the products and their order, are those of an NT GEMM over transposed copies of dZ
+// and H, without those copies being written.
+// Row pitch of the LDS tiles: 32 mod 64 elements (an odd multiple of 16 banks), so one read's
+// 8 rows x 64 bytes cover the 64 banks twice (the minimum for 512 bytes).
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+template <int BM, int BN>
+__global__ void __launch_bounds__(256, 3) gemm_dw_rowmajor_kernel(GemmArgs g) {
+    constexpr int BK = 32, PA = BM + 32, PB = BN + 32;
+    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 32, FN = WN / 32;
+    constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;  // 16-byte chunks per thread
+    static_assert(CA >= 1 && CB >= 1, "tile too small for 256 threads");
+    static_assert(PA % 64 == 32 && PB % 64 == 32, "row pitch 32 mod 64");
+    __shared__ __attribute__((aligned(16))) bf16 sA[2][BK][PA];
+    __shared__ __attribute__((aligned(16))) bf16 sB[2][BK][PB];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+    const int64_t kb = (int64_t)blockIdx.z * g.k_per_split;
+    const int64_t ke = (kb + g.k_per_split < g.K) ? kb + g.k_per_split : g.K;
+    const int nk = (int)((ke - kb) / BK);
+    bf16x8 ra[CA], rb[CB];
+    auto gload = [&](int64_t k) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = st[r8 + t][col];
-            *reinterpret_cast<bf16x8 *>(g.HT + (n0 + col) * g.ldht + m0 + r8) = v;
+        for (int i = 0; i < CA; ++i) {
+            const int c = tid + 256 * i;
+            ra[i] = *reinterpret_cast<const bf16x8 *>(g.A + (k + c / (BM / 8)) * g.lda + m0 + (c % (BM / 8)) * 8);
         }
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            const int c = tid + 256 * i;
+            rb[i] = *reinterpret_cast<const bf16x8 *>(g.B + (k + c / (BN / 8)) * g.ldb + n0 + (c % (BN / 8)) * 8);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < CA; ++i) {
+            const int c = tid + 256 * i;
+            *reinterpret_cast<bf16x8 *>(&sA[buf][c / (BM / 8)][(c % (BM / 8)) * 8]) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            const int c = tid + 256 * i;
+            *reinterpret_cast<bf16x8 *>(&sB[buf][c / (BN / 8)][(c % (BN / 8)) * 8]) = rb[i];
+        }
+    };
+    // lane's place in its group of 16: the row offset and the column offset of its read
+    const int grp = lane >> 4, jr = (lane & 15) >> 2, jc = 4 * (lane & 3);
+    const int colg = 16 * (grp & 1), kq = 8 * (grp >> 1);
+    auto tread = [&](const bf16 *p) {
+        const s16x4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (__attribute__((address_space(3))) s16x4 *)(p));
+        return v;
+    };
+    auto operand = [&](const bf16 *tile, int pitch, int col, int ks) {
+        // rows ks + kq .. + 7 of column col + lane % 32
+        const bf16 *p = tile + (ks + kq + jr) * pitch + col + colg + jc;
+        const bf16x4 lo = __builtin_bit_cast(bf16x4, tread(p));
+        const bf16x4 hi = __builtin_bit_cast(bf16x4, tread(p + 4 * pitch));
+        return (bf16x8)__builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    };
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    if (nk > 0) {
+        gload(kb);
+        sstore(0);
     }
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) gload(kb + (int64_t)(kt + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 16) {
+            bf16x8 af[FM], bfr[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) af[i] = operand(&sA[buf][0][0], PA, wm * WM + 32 * i, ks);
+#pragma unroll
+            for (int j = 0; j < FN; ++j) bfr[j] = operand(&sB[buf][0][0], PB, wn * WN + 32 * j, ks);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = mfma32(af[i], bfr[j], acc[i][j]);
+        }
+        // the other buffer was last read before the barrier that ended step kt - 1
+        if (kt + 1 < nk) sstore(buf ^ 1);
+        __syncthreads();
+    }
+    const int cn = lane & 31;
+    float *p = g.P + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int64_t n = n0 + wn * WN + 32 * j + cn;
+            const int64_t mb = m0 + wm * WM + 32 * i;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) p[(mb + frag_row(v, lane)) * g.N + n] = acc[i][j][v];
+        }
 }
 
 // Fourier features of the normalised query: h0 = [sin 2 pi u, cos 2 pi u], u = B v.
@@ -253,14 +339,11 @@ struct Box {
 
 // One thread: 8 consecutive features of one row.  Block = 64 rows (x) x 4 chunks of 8
 // features (y); grid.y covers the m/32 groups of chunks.  Writes the row-major features
-// (16-byte stores) and, when HT != NULL, the transposed copy [2m][Mp] the first layer's
-// weight gradient reads (consecutive lanes write consecutive rows).  Rows past n get
-// u = 0.
+// (16-byte stores).  Rows past n get u = 0.
 __global__ void __launch_bounds__(256) features_kernel(int64_t n, int64_t Mp, int m,
                                                        const float *__restrict__ q, Box box,
                                                        const float *__restrict__ Bff,
-                                                       bf16 *__restrict__ H0, int64_t ld,
-                                                       bf16 *__restrict__ HT) {
+                                                       bf16 *__restrict__ H0, int64_t ld) {
     const int64_t b = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int j0 = (blockIdx.y * 4 + threadIdx.y) * 8;
     if (b >= Mp || j0 >= m) return;
@@ -288,13 +371,6 @@ __global__ void __launch_bounds__(256) features_kernel(int64_t n, int64_t Mp, in
     }
     *reinterpret_cast<bf16x8 *>(H0 + b * ld + j0) = hs;
     *reinterpret_cast<bf16x8 *>(H0 + b * ld + m + j0) = hc;
-    if (HT) {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            HT[(int64_t)(j0 + t) * Mp + b] = hs[t];
-            HT[(int64_t)(m + j0 + t) * Mp + b] = hc[t];
-        }
-    }
 }
 
 // Fused inference: features, every hidden layer and the head for a tile of BM rows in
@@ -518,8 +594,8 @@ __global__ void __launch_bounds__(256, 2) mlp_infer_fused_kernel(FusedArgs a) {
 
 // Output layer (FP32), one thread per row: y = Wo h + bo.  Training (t != NULL): the
 // row's loss and output gradient dy = (y - t)/n go to dyl [Mp][3] (0 for padding rows)
-// and dZ_L = bf16((dy Wo) * silu'(Z_L)), row-major and transposed.  Wo is read through the constant address space
-// (scalar loads: every lane uses the same weights).
+// and dZ_L = bf16((dy Wo) * silu'(Z_L)), row-major.  Wo is read through the constant address
+// space (scalar loads: every lane uses the same weights).
 typedef const __attribute__((address_space(4))) float *ConstF;
 
 __global__ void __launch_bounds__(256) head_kernel(int64_t n, int64_t Mp, int W,
@@ -527,7 +603,7 @@ __global__ void __launch_bounds__(256) head_kernel(int64_t n, int64_t Mp, int W,
                                                    const float *__restrict__ Z, const float *Wo_,
                                                    const float *bo_, const float *__restrict__ t,
                                                    float *__restrict__ y, bf16 *__restrict__ dZ,
-                                                   bf16 *__restrict__ dZT, float *__restrict__ dyl) {
+                                                   float *__restrict__ dyl) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (row >= Mp) return;
     const ConstF Wo = (ConstF)Wo_, bo = (ConstF)bo_;
@@ -578,7 +654,6 @@ __global__ void __launch_bounds__(256) head_kernel(int64_t n, int64_t Mp, int W,
             for (int u = 0; u < 8; ++u) {
                 const float dh = d0 * Wo[f + u] + d1 * Wo[W + f + u];
                 o[u] = (bf16)(dh * silu_grad_f(zb[2 * k8 + u / 4][u % 4]));
-                dZT[(int64_t)(f + u) * Mp + row] = o[u];  // transposed copy [W][Mp]
             }
             *reinterpret_cast<bf16x8 *>(dz + f) = o;
         }
@@ -673,30 +748,9 @@ __global__ void __launch_bounds__(256) colsum_kernel(const float *__restrict__ i
     if (ry == 0 && c < C) out[c] = (float)(((sh[0][cx] + sh[1][cx]) + sh[2][cx]) + sh[3][cx]);
 }
 
-// Bias gradient, first level: part[sg][o] = the sum of dZ^T[o][b] over the batch columns b
-// of segment sg (16-byte chunks (sg * 256 + thread) * 8 + 2048 kRowSumSegs i), FP32 lanes
-// then a fixed-order tree; colsum_kernel adds the segments in order.  W x kRowSumSegs
-// workgroups: one per row left most of the chip idle.
+// Bias-gradient segments: the batch is cut into kRowSumSegs interleaved segments whose sums
+// are added in order (bias_node_kernel, bias_tree_kernel, then the column sums).
 constexpr int kRowSumSegs = 16;
-__global__ void __launch_bounds__(256) rowsum_part_kernel(const bf16 *__restrict__ X, int64_t cols, int W,
-                                                          float *__restrict__ part) {
-    __shared__ float sh[256];
-    const int o = blockIdx.x, sg = blockIdx.y;
-    const bf16 *x = X + (int64_t)o * cols;
-    float acc = 0.0f;
-    for (int64_t k = ((int64_t)sg * 256 + threadIdx.x) * 8; k < cols; k += (int64_t)kRowSumSegs * 256 * 8) {
-        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(x + k);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc += (float)v[u];
-    }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(int64_t)sg * W + o] = sh[0];
-}
 
 __global__ void __launch_bounds__(256) adam_kernel(int64_t P, float *__restrict__ p,
                                                    const float *__restrict__ g, float *__restrict__ m,
@@ -727,6 +781,57 @@ __global__ void __launch_bounds__(256) cast_weight_kernel(const float *__restric
     // 32 ((i % 16) / 8), blocks ordered by input slice within each 32-column group
     const int c = o >> 5, t = i >> 4, lane = (o & 31) + 32 * ((i & 15) >> 3);
     Wf32[(((int64_t)c * (I >> 4) + t) * 64 + lane) * 8 + (i & 7)] = v;
+}
+
+// Bias gradient from the row-major dZ [rows][W], for each column o and segment sg: 256
+// leaves t, each the sum in order of the 8-row chunks (sg * 256 + t) * 8 + 2048 kRowSumSegs i,
+// meet in the halving tree sh[t] += sh[t + w], w = 128 .. 1 (the order of a reduction with one
+// workgroup per row of a transposed copy of dZ, 256 threads each summing its chunks).
+// Here a thread takes the 8 leaves t5 + 32 i of one column and adds them as the tree's first
+// three levels do (w = 128, 64, 32), giving node [kRowSumSegs][32][W]; bias_tree_kernel
+// finishes the last five levels.  Block (64 columns,
+// 4 values of t5); grid (W / 64, kRowSumSegs, 8).
+__global__ void __launch_bounds__(256) bias_node_kernel(const bf16 *__restrict__ dZ, int64_t rows, int W,
+                                                        float *__restrict__ node) {
+    const int o = blockIdx.x * 64 + threadIdx.x, sg = blockIdx.y, t5 = blockIdx.z * 4 + threadIdx.y;
+    constexpr int64_t kStride = (int64_t)kRowSumSegs * 256 * 8;
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = 0.0f;
+    for (int64_t c = 0; c < rows; c += kStride) {
+        bf16 x[8][8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t k = ((int64_t)sg * 256 + t5 + 32 * i) * 8 + c;
+            const int64_t kl = k < rows ? k : rows - 8;  // loads unconditional, so all are in flight
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[i][u] = dZ[(kl + u) * W + o];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t k = ((int64_t)sg * 256 + t5 + 32 * i) * 8 + c;
+            if (k < rows)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[i] += (float)x[i][u];
+        }
+    }
+    const float a0 = v[0] + v[4], a1 = v[1] + v[5], a2 = v[2] + v[6], a3 = v[3] + v[7];  // w = 128
+    node[((int64_t)sg * 32 + t5) * W + o] = (a0 + a2) + (a1 + a3);                     // w = 64, 32
+}
+
+// The tree's last levels (w = 16 .. 1) over node [kRowSumSegs][32][W] -> part [kRowSumSegs][W];
+// grid (W / 64, kRowSumSegs), 64 threads.
+__global__ void __launch_bounds__(64) bias_tree_kernel(const float *__restrict__ node, int W,
+                                                       float *__restrict__ part) {
+    const int o = blockIdx.x * 64 + threadIdx.x, sg = blockIdx.y;
+    float n[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) n[t] = node[((int64_t)sg * 32 + t) * W + o];
+#pragma unroll
+    for (int w = 16; w > 0; w >>= 1)
+#pragma unroll
+        for (int t = 0; t < w; ++t) n[t] += n[t + w];
+    part[(int64_t)sg * W + o] = n[0];
 }
 
 // One training step's Adam update fused with the reductions that finish its gradients:
@@ -900,8 +1005,7 @@ struct rsi_mlp {
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> Wb, WTb;  // bf16 weights and transposes
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> Wfr;      // bf16 weights in MFMA fragment order
     std::vector<std::unique_ptr<rsi::DeviceBuffer>> H, Z;    // activations [L+1], pre-acts [L]
-    std::vector<std::unique_ptr<rsi::DeviceBuffer>> HT;      // transposed layer inputs [L]
-    rsi::DeviceBuffer dZ[2], dZT[2], dwpart, headpart, bpart, dyl, lossbuf;
+    rsi::DeviceBuffer dZ[2], dwpart, headpart, bpart, bnode, dyl, lossbuf;
     std::vector<int64_t> dwoff;  // per layer, into dwpart (each layer keeps its partials)
     int dw_splits = 1;
 };
@@ -918,8 +1022,7 @@ static void launch_gemm(int epi, const GemmArgs &g, int splits, hipStream_t s) {
         case EPI_FWD_INFER:
             hipLaunchKernelGGL((gemm_nt_kernel<EPI_FWD_INFER, BM, BN>), grid, dim3(256), 0, s, g);
             break;
-        case EPI_DX: hipLaunchKernelGGL((gemm_nt_kernel<EPI_DX, BM, BN>), grid, dim3(256), 0, s, g); break;
-        default: hipLaunchKernelGGL((gemm_nt_kernel<EPI_DW, BM, BN>), grid, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL((gemm_nt_kernel<EPI_DX, BM, BN>), grid, dim3(256), 0, s, g); break;
     }
 }
 
@@ -932,6 +1035,19 @@ static rsi_status gemm(int epi, const GemmArgs &g, int splits, hipStream_t s) {
     else if (bm) launch_gemm<128, 64>(epi, g, splits, s);
     else if (bn) launch_gemm<64, 128>(epi, g, splits, s);
     else launch_gemm<64, 64>(epi, g, splits, s);
+    RSI_HIP(hipGetLastError());
+    return RSI_OK;
+}
+
+// The weight-gradient GEMM on row-major operands (gemm_dw_rowmajor_kernel), tiles as gemm().
+static rsi_status gemm_dw(const GemmArgs &g, int splits, hipStream_t s) {
+    if (g.M % 64 || g.N % 64 || g.k_per_split % 32 || (g.K % g.k_per_split)) return RSI_ERR_SIZE;
+    const bool bm = g.M % 128 == 0, bn = g.N % 128 == 0;
+    const dim3 grid((unsigned)(g.M / (bm ? 128 : 64)), (unsigned)(g.N / (bn ? 128 : 64)), (unsigned)splits);
+    if (bm && bn) hipLaunchKernelGGL((gemm_dw_rowmajor_kernel<128, 128>), grid, dim3(256), 0, s, g);
+    else if (bm) hipLaunchKernelGGL((gemm_dw_rowmajor_kernel<128, 64>), grid, dim3(256), 0, s, g);
+    else if (bn) hipLaunchKernelGGL((gemm_dw_rowmajor_kernel<64, 128>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((gemm_dw_rowmajor_kernel<64, 64>), grid, dim3(256), 0, s, g);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }
@@ -954,7 +1070,7 @@ static rsi_status forward_hidden(rsi_mlp *net, int64_t n, const float *q, bool t
     // m is a multiple of 32: m / 32 groups of 4 chunks of 8 features
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)(Mp / 64), (unsigned)(net->m / 32)), dim3(64, 4), 0, s,
                        n, Mp, net->m, q, net->box, net->Bff.as<float>(), net->H[0]->as<bf16>(),
-                       (int64_t)net->F, train ? net->HT[0]->as<bf16>() : (bf16 *)nullptr);
+                       (int64_t)net->F);
     RSI_HIP(hipGetLastError());
     for (int l = 0; l < net->L; ++l) {
         GemmArgs g{};
@@ -971,9 +1087,6 @@ static rsi_status forward_hidden(rsi_mlp *net, int64_t n, const float *q, bool t
         g.ldz = (l + 1 == net->L) ? net->W : 0;  // tile-native except for the head's input
         g.H = net->H[l + 1]->as<bf16>();
         g.ldh = net->W;
-        // training: the transposed activations feed the next layer's weight gradient
-        g.HT = (train && l + 1 < net->L) ? net->HT[l + 1]->as<bf16>() : nullptr;
-        g.ldht = Mp;
         RSI_TRY(gemm(train ? EPI_FWD : EPI_FWD_INFER, g, 1, s));
     }
     return RSI_OK;
@@ -989,8 +1102,7 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
     const float *params = net->params.as<float>();
     hipLaunchKernelGGL(head_kernel, dim3((unsigned)((Mp + 255) / 256)), dim3(256), 0, s, n, Mp, W,
                        net->H[net->L]->as<bf16>(), net->Z[net->L - 1]->as<float>(), params + net->offWo,
-                       params + net->offbo, t, (float *)nullptr, net->dZ[0].as<bf16>(), net->dZT[0].as<bf16>(),
-                       net->dyl.as<float>());
+                       params + net->offbo, t, (float *)nullptr, net->dZ[0].as<bf16>(), net->dyl.as<float>());
     RSI_HIP(hipGetLastError());
     // head partials [chunks][2W + 3] -> dWo, dbo (columns 0..2W+1) and the loss (column 2W+2)
     {
@@ -1011,33 +1123,36 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
     int cur = 0;
     for (int l = net->L - 1; l >= 0; --l) {
         const int I = net->in_dim[l];
-        // the weight gradient reads the transposed copies dZ_l^T [W][Mp] and H_l^T [I][Mp],
-        // written by the epilogues that produced dZ_l and H_l
+        // the weight gradient and the bias gradient read dZ_l [Mp][W] and H_l [Mp][I] as the
+        // epilogues that produced them wrote them (row-major)
         int splits = net->dw_splits;
         while (splits > 1 && (Mp % ((int64_t)splits * kTileK) != 0)) splits >>= 1;
         if (splits_used) *splits_used = splits;
         float *dwp = net->dwpart.as<float>() + net->dwoff[l];
         float *bpp = net->bpart.as<float>() + (int64_t)l * kRowSumSegs * W;
         GemmArgs g{};
-        g.A = net->dZT[cur].as<bf16>();
-        g.lda = Mp;
-        g.B = net->HT[l]->as<bf16>();
-        g.ldb = Mp;
+        g.A = net->dZ[cur].as<bf16>();
+        g.lda = W;
+        g.B = net->H[l]->as<bf16>();
+        g.ldb = I;
         g.M = W;
         g.N = I;
         g.K = Mp;
         g.k_per_split = Mp / splits;
         g.P = dwp;
-        RSI_TRY(gemm(EPI_DW, g, splits, s));
+        RSI_TRY(gemm_dw(g, splits, s));
         const int64_t C = (int64_t)W * I;
         if (grad) {
             hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((C + 63) / 64)), dim3(256), 0, s, dwp,
                                (int64_t)splits, C, C, grad + net->offW[l]);
             RSI_HIP(hipGetLastError());
         }
-        // bias gradient: row sums of dZ^T, in kRowSumSegs segments added in order
-        hipLaunchKernelGGL(rowsum_part_kernel, dim3((unsigned)W, (unsigned)kRowSumSegs), dim3(256), 0, s,
-                           net->dZT[cur].as<bf16>(), Mp, W, bpp);
+        // bias gradient: column sums of dZ, in kRowSumSegs segments added in order
+        hipLaunchKernelGGL(bias_node_kernel, dim3((unsigned)(W / 64), (unsigned)kRowSumSegs, 8u), dim3(64, 4), 0, s,
+                           net->dZ[cur].as<bf16>(), Mp, W, net->bnode.as<float>());
+        RSI_HIP(hipGetLastError());
+        hipLaunchKernelGGL(bias_tree_kernel, dim3((unsigned)(W / 64), (unsigned)kRowSumSegs), dim3(64), 0, s,
+                           net->bnode.as<float>(), W, bpp);
         RSI_HIP(hipGetLastError());
         if (grad) {
             hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((W + 63) / 64)), dim3(256), 0, s, bpp,
@@ -1058,8 +1173,6 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
         d.ldz = 0;  // written tile-native by the forward GEMM of the same shape
         d.H = net->dZ[cur ^ 1].as<bf16>();
         d.ldh = I;
-        d.HT = net->dZT[cur ^ 1].as<bf16>();
-        d.ldht = Mp;
         RSI_TRY(gemm(EPI_DX, d, 1, s));
         cur ^= 1;
     }
@@ -1144,13 +1257,8 @@ rsi_status rsi_mlp_create(rsi_mlp **out, int n_ff, int width, int depth, const f
         net->H.emplace_back(new DeviceBuffer);
         RSI_TRY(net->H.back()->alloc(sizeof(bf16) * Mp * (l == 0 ? F : width)));
     }
-    for (int l = 0; l < depth; ++l) {
-        net->HT.emplace_back(new DeviceBuffer);
-        RSI_TRY(net->HT.back()->alloc(sizeof(bf16) * Mp * net->in_dim[l]));
-    }
     for (int k = 0; k < 2; ++k) {
         RSI_TRY(net->dZ[k].alloc(sizeof(bf16) * Mp * maxdim));
-        RSI_TRY(net->dZT[k].alloc(sizeof(bf16) * Mp * maxdim));
     }
     // weight-gradient split over the batch: at least 256 rows per split, at most 64
     // splits (measured best for 256 x 256 weights at a batch of 65536: 256 workgroups
@@ -1172,6 +1280,7 @@ rsi_status rsi_mlp_create(rsi_mlp **out, int n_ff, int width, int depth, const f
     RSI_TRY(net->dwpart.alloc(sizeof(float) * dw_elems));
     RSI_TRY(net->headpart.alloc(sizeof(float) * (size_t)((Mp + kHeadRows - 1) / kHeadRows) * (2 * width + 3)));
     RSI_TRY(net->bpart.alloc(sizeof(float) * kRowSumSegs * (size_t)width * depth));
+    RSI_TRY(net->bnode.alloc(sizeof(float) * kRowSumSegs * 32 * (size_t)width));
     RSI_TRY(net->dyl.alloc(sizeof(float) * 3 * (size_t)Mp));
     RSI_TRY(net->lossbuf.alloc(sizeof(float) * 4));
     RSI_TRY(refresh_bf16(net.get(), nullptr));
@@ -1252,8 +1361,7 @@ rsi_status rsi_mlp_forward(rsi_mlp *net, int64_t n, const float *q, float *y, vo
     const float *params = net->params.as<float>();
     hipLaunchKernelGGL(head_kernel, dim3((unsigned)((Mp + 255) / 256)), dim3(256), 0, s, n, Mp, net->W,
                        net->H[net->L]->as<bf16>(), (const float *)nullptr, params + net->offWo,
-                       params + net->offbo, (const float *)nullptr, y, (bf16 *)nullptr, (bf16 *)nullptr,
-                       (float *)nullptr);
+                       params + net->offbo, (const float *)nullptr, y, (bf16 *)nullptr, (float *)nullptr);
     RSI_HIP(hipGetLastError());
     return RSI_OK;
 }

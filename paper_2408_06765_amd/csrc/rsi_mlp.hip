@@ -1260,10 +1260,11 @@ rsi_status rsi_mlp_create(rsi_mlp **out, int n_ff, int width, int depth, const f
     for (int k = 0; k < 2; ++k) {
         RSI_TRY(net->dZ[k].alloc(sizeof(bf16) * Mp * maxdim));
     }
-    // weight-gradient split over the batch: at least 256 rows per split, at most 64
-    // splits (measured best for 256 x 256 weights at a batch of 65536: 256 workgroups
-    // of 1024-row K ranges; more splits cost more in partial traffic than they gain)
-    int max_splits = 64;
+    // weight-gradient split over the batch: at least 256 rows per split, at most 128
+    // splits (measured best for 256 x 256 weights at a batch of 65536: 512 workgroups of
+    // 512-row K ranges, a training step 0.809 ms against 0.836 with 64 splits and 0.887
+    // with 256, where the partials' traffic outgrows what the extra workgroups gain)
+    int max_splits = 128;
     if (const char *e = std::getenv("RSI_MLP_DW_SPLITS")) {  // tuning sweeps: a power of two
         const int v = std::atoi(e);
         if (v >= 1 && v <= 4096 && (v & (v - 1)) == 0) max_splits = v;

@@ -819,11 +819,14 @@ __global__ void __launch_bounds__(256) bias_node_kernel(const bf16 *__restrict__
     node[((int64_t)sg * 32 + t5) * W + o] = (a0 + a2) + (a1 + a3);                     // w = 64, 32
 }
 
-// The tree's last levels (w = 16 .. 1) over node [kRowSumSegs][32][W] -> part [kRowSumSegs][W];
-// grid (W / 64, kRowSumSegs), 64 threads.
-__global__ void __launch_bounds__(64) bias_tree_kernel(const float *__restrict__ node, int W,
-                                                       float *__restrict__ part) {
+// The tree's last levels (w = 16 .. 1) over node [kRowSumSegs][32][W] -> part [kRowSumSegs][W],
+// for every layer in one launch (layer blockIdx.z: node and part at its offsets); grid
+// (W / 64, kRowSumSegs, layers), 64 threads.
+__global__ void __launch_bounds__(64) bias_tree_kernel(const float *__restrict__ node_all, int W,
+                                                       float *__restrict__ part_all) {
     const int o = blockIdx.x * 64 + threadIdx.x, sg = blockIdx.y;
+    const float *node = node_all + (int64_t)blockIdx.z * kRowSumSegs * 32 * W;
+    float *part = part_all + (int64_t)blockIdx.z * kRowSumSegs * W;
     float n[32];
 #pragma unroll
     for (int t = 0; t < 32; ++t) n[t] = node[((int64_t)sg * 32 + t) * W + o];
@@ -1129,7 +1132,6 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
         while (splits > 1 && (Mp % ((int64_t)splits * kTileK) != 0)) splits >>= 1;
         if (splits_used) *splits_used = splits;
         float *dwp = net->dwpart.as<float>() + net->dwoff[l];
-        float *bpp = net->bpart.as<float>() + (int64_t)l * kRowSumSegs * W;
         GemmArgs g{};
         g.A = net->dZ[cur].as<bf16>();
         g.lda = W;
@@ -1148,17 +1150,11 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
             RSI_HIP(hipGetLastError());
         }
         // bias gradient: column sums of dZ, in kRowSumSegs segments added in order
+        // (the trees' last levels run for all layers after the loop)
         hipLaunchKernelGGL(bias_node_kernel, dim3((unsigned)(W / 64), (unsigned)kRowSumSegs, 8u), dim3(64, 4), 0, s,
-                           net->dZ[cur].as<bf16>(), Mp, W, net->bnode.as<float>());
+                           net->dZ[cur].as<bf16>(), Mp, W,
+                           net->bnode.as<float>() + (int64_t)l * kRowSumSegs * 32 * W);
         RSI_HIP(hipGetLastError());
-        hipLaunchKernelGGL(bias_tree_kernel, dim3((unsigned)(W / 64), (unsigned)kRowSumSegs), dim3(64), 0, s,
-                           net->bnode.as<float>(), W, bpp);
-        RSI_HIP(hipGetLastError());
-        if (grad) {
-            hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((W + 63) / 64)), dim3(256), 0, s, bpp,
-                               (int64_t)kRowSumSegs, (int64_t)W, (int64_t)W, grad + net->offb[l]);
-            RSI_HIP(hipGetLastError());
-        }
         if (l == 0) break;
         GemmArgs d{};
         d.A = net->dZ[cur].as<bf16>();
@@ -1176,6 +1172,16 @@ static rsi_status backward(rsi_mlp *net, int64_t n, const float *t, float *grad,
         RSI_TRY(gemm(EPI_DX, d, 1, s));
         cur ^= 1;
     }
+    hipLaunchKernelGGL(bias_tree_kernel, dim3((unsigned)(W / 64), (unsigned)kRowSumSegs, (unsigned)net->L), dim3(64),
+                       0, s, net->bnode.as<float>(), W, net->bpart.as<float>());
+    RSI_HIP(hipGetLastError());
+    if (grad)
+        for (int l = 0; l < net->L; ++l) {
+            hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((W + 63) / 64)), dim3(256), 0, s,
+                               net->bpart.as<float>() + (int64_t)l * kRowSumSegs * W, (int64_t)kRowSumSegs,
+                               (int64_t)W, (int64_t)W, grad + net->offb[l]);
+            RSI_HIP(hipGetLastError());
+        }
     return RSI_OK;
 }
 
@@ -1281,7 +1287,7 @@ rsi_status rsi_mlp_create(rsi_mlp **out, int n_ff, int width, int depth, const f
     RSI_TRY(net->dwpart.alloc(sizeof(float) * dw_elems));
     RSI_TRY(net->headpart.alloc(sizeof(float) * (size_t)((Mp + kHeadRows - 1) / kHeadRows) * (2 * width + 3)));
     RSI_TRY(net->bpart.alloc(sizeof(float) * kRowSumSegs * (size_t)width * depth));
-    RSI_TRY(net->bnode.alloc(sizeof(float) * kRowSumSegs * 32 * (size_t)width));
+    RSI_TRY(net->bnode.alloc(sizeof(float) * kRowSumSegs * 32 * (size_t)width * depth));
     RSI_TRY(net->dyl.alloc(sizeof(float) * 3 * (size_t)Mp));
     RSI_TRY(net->lossbuf.alloc(sizeof(float) * 4));
     RSI_TRY(refresh_bf16(net.get(), nullptr));

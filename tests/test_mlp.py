@@ -280,8 +280,13 @@ def test_mlp_fused_row_tiles_equal_layerwise(gpu, n_ff, width, depth, n, rows, m
     net.destroy()
 
 
+# the weight-gradient kernel's four tile shapes: 64 x 64, 128 x 128 (SHAPES), 128 x 64 (first
+# layer of width 256 on 64 features), 64 x 128 (first layer of width 64 on 128 features)
+GRAD_SHAPES = SHAPES + [(32, 256, 2, 500), (64, 64, 2, 300)]
+
+
 @pytest.mark.gpu
-@pytest.mark.parametrize("n_ff,width,depth,n", SHAPES)
+@pytest.mark.parametrize("n_ff,width,depth,n", GRAD_SHAPES)
 def test_mlp_gradients_match_reference(gpu, n_ff, width, depth, n):
     net, o, q, t, v, tn, params = _setup(gpu, n_ff, width, depth, n, 4)
     g, loss = net.gradients(q, t)

@@ -966,7 +966,7 @@ __global__ void __launch_bounds__(256) ray_frame_kernel(int64_t n, const float2 
     part[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
         __syncthreads();
     }
     const double s = sqrt(part[0] / (double)n_ref);

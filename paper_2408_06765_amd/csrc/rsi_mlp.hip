@@ -789,8 +789,8 @@ __global__ void __launch_bounds__(256) cast_weight_kernel(const float *__restric
 // workgroup per row of a transposed copy of dZ, 256 threads each summing its chunks).
 // Here a thread takes the 8 leaves t5 + 32 i of one column and adds them as the tree's first
 // three levels do (w = 128, 64, 32), giving node [kRowSumSegs][32][W]; bias_tree_kernel
-// finishes the last five levels.  Block (64 columns,
-// 4 values of t5); grid (W / 64, kRowSumSegs, 8).
+// finishes the last five levels.  Block (64 columns, 4 values of t5); grid (W / 64,
+// kRowSumSegs, 8).
 __global__ void __launch_bounds__(256) bias_node_kernel(const bf16 *__restrict__ dZ, int64_t rows, int W,
                                                         float *__restrict__ node) {
     const int o = blockIdx.x * 64 + threadIdx.x, sg = blockIdx.y, t5 = blockIdx.z * 4 + threadIdx.y;

@@ -37,6 +37,7 @@ FLOPS_MONOPOLE = 25
 FLOPS_DIPOLE = 33
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 2.4 GHz x 256 flop/CU/clk)
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 MFMA
+PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
 
 
 def parse():
@@ -1080,6 +1081,37 @@ def flops_mlp_train_row(n_ff, width, depth):
     return fwd + dw + dx
 
 
+def bytes_mlp_train_step(n_ff, width, depth, n, splits):
+    """HBM bytes one training step's kernels read and write, from the tensors' shapes (a
+    traffic model, not a counter reading): bf16 features and activations, FP32
+    pre-activations, bf16 layer gradients, the weight gradients' FP32 split partials
+    (written and read once), the FP32 parameters and Adam moments and the weights' three
+    bf16 copies.  Per row: features 2F; forward layer l reads 2 I_l, writes 2W + 4W; the head
+    reads 2W + 4W, writes 2W, and its gradient reads 2W again; backward layer l reads dZ (2W)
+    and H_l (2 I_l) for the weight gradient and dZ (2W) for the bias gradient, and (l >= 1)
+    dZ (2W) and Z_{l-1} (4W) while writing dZ_{l-1} (2W)."""
+    F, W, L = 2 * n_ff, width, depth
+    ins = [F] + [W] * (L - 1)
+    row = 2 * F
+    row += sum(2 * i + 6 * W for i in ins)
+    row += 8 * W + 2 * W
+    row += sum(2 * W + 2 * i + 2 * W for i in ins) + (L - 1) * 8 * W
+    weights = sum(W * i for i in ins)
+    params = weights + L * W + 2 * W + 2
+    step = 2 * 4 * splits * weights  # split partials, written and read
+    step += params * (4 + 4 + 2 * 8) + weights * 3 * 2  # p read/write, m and v read/write, bf16 copies
+    return n * row + step
+
+
+def dw_splits(n):
+    """The weight gradient's batch splits the library picks for n rows: the largest power of
+    two up to 128 that leaves at least 256 rows per split."""
+    mp, s = (n + 63) // 64 * 64, 1
+    while s < 128 and mp // (2 * s) >= 256:
+        s *= 2
+    return s
+
+
 def surrogate_training(args):
     """One Adam step of the surrogate network (the recipe's shape: 128 Fourier frequencies,
     7 x 256 SiLU, bf16 MFMA GEMMs with FP32 accumulation) on a batch of 65536 rows: features,
@@ -1115,6 +1147,12 @@ def surrogate_training(args):
     line["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
                         "kernel": f"whole training step, {fl} flop/row x {n} rows / {kms:.4f} ms"}
+    # the step is bound by memory traffic: the same time against the HBM peak
+    nb = bytes_mlp_train_step(cfg.n_ff, cfg.width, cfg.depth, n, dw_splits(n))
+    line["hbm_view"] = {"bytes_per_step": nb, "achieved": round(nb / (kms * 1e-3) / 1e9, 1),
+                        "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                        "frac": round(nb / (kms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+                        "basis": "tensor bytes the step's kernels read and write, from the shapes"}
     print(json.dumps(line), flush=True)
 
 

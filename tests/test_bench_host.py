@@ -101,3 +101,19 @@ def test_flop_conventions():
     assert bench.flops_multifreq_pair(64, 32) == 2 * 33 + 62 * 21
     assert bench.flops_mlp_row(128, 256, 5) == 2 * (256 * 256 + 4 * 256 * 256 + 2 * 256)
     assert bench.FLOPS_DIPOLE == 33
+
+
+def test_training_traffic_model():
+    """The training step's HBM model: the library's split rule, and the bytes for the
+    recipe's network (7 x 256 on 128 frequencies, 65536 rows) counted by hand: per row
+    512 (features) + 2 (256 + 6 x 256) x 7 (forward) + 2560 (head and its gradient) +
+    7 x 1536 + 6 x 2048 (backward); per step the split partials 2 x 4 x 128 x 458752 and
+    the parameters 460290 x 24 plus 3 bf16 copies of the 458752 weights."""
+    assert bench.dw_splits(65536) == 128
+    assert bench.dw_splits(1000) == 4
+    assert bench.dw_splits(64) == 1
+    row = 512 + 7 * (2 * 256 + 6 * 256) + 2560 + 7 * 1536 + 6 * 2048
+    weights = 7 * 256 * 256
+    params = weights + 7 * 256 + 2 * 256 + 2
+    step = 2 * 4 * 128 * weights + params * 24 + weights * 6
+    assert bench.bytes_mlp_train_step(128, 256, 7, 65536, 128) == 65536 * row + step

@@ -39,7 +39,11 @@ typedef struct rsi_mlp rsi_mlp;
 
 /* Create a network and its training workspace on the current device.  B: host float
  * [n_ff][5]; lo, hi: host float[5], the box of q.  Parameters start at zero (set them
- * with rsi_mlp_set_params).  RSI_ERR_ARG for unsupported dimensions. */
+ * with rsi_mlp_set_params).  RSI_ERR_ARG for unsupported dimensions.  The workspace,
+ * for Mp = max_batch padded to 64: bf16 activations of every layer and FP32
+ * pre-activations (Mp (2m + L W) x 2 + Mp L W x 4 bytes), two bf16 gradient buffers, and
+ * every layer's FP32 weight-gradient partials over up to 128 batch splits (128 x W x
+ * (2m + (L - 1) W) x 4 bytes); about 1.0 GB for L = 7, W = 256, m = 128, max_batch 65536. */
 rsi_status rsi_mlp_create(rsi_mlp **net, int n_ff, int width, int depth, const float *B,
                           const float *lo, const float *hi, int64_t max_batch);
 rsi_status rsi_mlp_destroy(rsi_mlp *net);
